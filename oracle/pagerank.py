@@ -1,0 +1,149 @@
+"""Non-normalised PageRank R^(3): definitions and the plain power series.
+
+Test infrastructure only (see the package docstring).
+
+Conventions (Def. 3.4): A is the adjacency matrix with every non-zero row
+scaled to sum to one.  Self-loops are ignored, as in the experiments of
+Sec. 4.2; a repeated edge counts with its multiplicity (the paper assumes
+simple graphs, Sec. 2, so this only matters for inputs that are not).
+Dangling vertices have a zero row.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def out_degree(n, row_ptr, col):
+    """Out-degree without self-loops, duplicates counted."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    keep = src != col
+    return np.bincount(src[keep], minlength=n).astype(np.int64)
+
+
+def transition_dense(n, row_ptr, col):
+    """Dense A of Def. 3.4 (row-normalised, loops dropped)."""
+    A = np.zeros((n, n), dtype=np.float64)
+    for u in range(n):
+        for e in range(int(row_ptr[u]), int(row_ptr[u + 1])):
+            v = int(col[e])
+            if v != u:
+                A[u, v] += 1.0
+    s = A.sum(axis=1)
+    nz = s > 0
+    A[nz] /= s[nz, None]
+    return A
+
+
+def transition_T_csr(n, row_ptr, col):
+    """A^T as a scipy CSR matrix: row v holds 1/outdeg(u) for every edge u->v."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    keep = src != col
+    src, dst = src[keep], col[keep]
+    deg = np.bincount(src, minlength=n).astype(np.float64)
+    val = 1.0 / deg[src]
+    return sp.csr_matrix((val, (dst, src)), shape=(n, n))
+
+
+def pagerank_dense(n, row_ptr, col, c, W):
+    """R^(3) as the solution of (I - c A^T) R = W (Sec. 3.3, third method;
+    equivalent to Def. 3.5).  LAPACK via numpy; for small n only."""
+    A = transition_dense(n, row_ptr, col)
+    return np.linalg.solve(np.eye(n) - c * A.T, np.asarray(W, dtype=np.float64))
+
+
+def pagerank_r1(n, row_ptr, col, c, w):
+    """R^(1) of Def. 3.4: the eigenvector of M = c(A + g w^T)^T + (1-c) w e^T
+    for eigenvalue one, scaled to unit 1-norm (numpy eigen-solver)."""
+    A = transition_dense(n, row_ptr, col)
+    w = np.asarray(w, dtype=np.float64)
+    w = w / w.sum()
+    g = (A.sum(axis=1) == 0).astype(np.float64)
+    M = c * (A + np.outer(g, w)).T + (1.0 - c) * np.outer(w, np.ones(n))
+    vals, vecs = np.linalg.eig(M)
+    k = int(np.argmin(np.abs(vals - 1.0)))
+    r = np.real(vecs[:, k])
+    return r / r.sum()
+
+
+def r3_from_r1(n, row_ptr, col, c, R1, W):
+    """Def. 3.5: R^(3) = R^(1) ||W||_1 / d with d = 1 - sum(c A^T R^(1))."""
+    A = transition_dense(n, row_ptr, col)
+    d = 1.0 - np.sum(c * (A.T @ R1))
+    return R1 * np.sum(np.abs(W)) / d
+
+
+def pagerank_random_walks(n, row_ptr, col, c, W, walks_per_unit, seed):
+    """Monte-Carlo estimate of Def. 3.6: start round(W_i * walks_per_unit) walks
+    at every vertex; each step follows a uniformly chosen out-edge (loops
+    ignored) with probability c and stops otherwise or at a dangling vertex.
+    R_j is estimated by the number of visits to j divided by walks_per_unit."""
+    rng = np.random.default_rng(seed)
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    nbrs = []
+    for u in range(n):
+        nb = [int(v) for v in col[row_ptr[u]:row_ptr[u + 1]] if int(v) != u]
+        nbrs.append(np.array(nb, dtype=np.int64))
+    visits = np.zeros(n, dtype=np.float64)
+    for i in range(n):
+        k = int(round(W[i] * walks_per_unit))
+        pos = np.full(k, i, dtype=np.int64)
+        while pos.size:
+            np.add.at(visits, pos, 1.0)
+            cont = rng.random(pos.size) < c
+            pos = pos[cont]
+            nxt = np.empty_like(pos)
+            alive = np.ones(pos.size, dtype=bool)
+            for j, u in enumerate(pos):
+                nb = nbrs[u]
+                if nb.size == 0:
+                    alive[j] = False
+                else:
+                    nxt[j] = nb[rng.integers(0, nb.size)]
+            pos = nxt[alive]
+    return visits / walks_per_unit
+
+
+def pagerank_power_series(n, row_ptr, col, c, W, *, stop="cert", eps=1e-6, tol=None,
+                          max_iter=1_000_000, AT=None):
+    """The power series of Sec. 3.3.2 on the whole graph (the paper's baseline,
+    "method 1" of Sec. 4.2):  P_0 = W,  P_{k+1} = c A^T P_k,  R = sum_k P_k.
+
+    Stop rules (one term P_k is added per iteration, k >= 1):
+      "cert":  stop after the first k with ||P_k||_1 <= eps (1-c) ||W||_1.
+               Because ||c A^T x||_1 <= c ||x||_1 (Sec. 3.4), the neglected tail
+               is at most c/(1-c) ||P_k||_1 <= c eps ||W||_1 <= c eps ||R*||_1,
+               a relative 1-norm error below eps.
+      "paper": stop after the first k with max(P_k) < tol (the listing of
+               Sec. 3.3.2; an absolute max-norm rule).
+    Returns (R, iterations, ||P_K||_1).
+    """
+    if AT is None:
+        AT = transition_T_csr(n, row_ptr, col)
+    W = np.asarray(W, dtype=np.float64)
+    R = W.copy()
+    p = W.copy()
+    wnorm = float(np.sum(np.abs(W)))
+    k = 0
+    last = wnorm
+    while k < max_iter:
+        if stop == "cert" and wnorm == 0.0:
+            break
+        p = c * (AT @ p)
+        R += p
+        k += 1
+        last = float(np.sum(np.abs(p)))
+        if stop == "cert":
+            if last <= eps * (1.0 - c) * wnorm:
+                break
+        elif stop == "paper":
+            if p.size == 0 or float(np.max(p)) < tol:
+                break
+        else:
+            raise ValueError(stop)
+    return R, k, last

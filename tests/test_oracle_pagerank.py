@@ -1,0 +1,225 @@
+"""Pins for the oracle's PageRank routes (Defs. 3.4-3.6, Sec. 3.3, Sec. 3.4)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+from graphgen import config_graph, csr_from_edges, random_digraph
+from oracle import componentwise as CW
+from oracle import pagerank as PR
+
+C = 0.85
+
+
+def _g(n, edges):
+    return csr_from_edges(n, [a for a, _ in edges], [b for _, b in edges])
+
+
+def _all_routes(g, W, c=C):
+    """Every oracle route to R^(3), as (name, vector)."""
+    out = [("dense", PR.pagerank_dense(g.n, g.row_ptr, g.col, c, W))]
+    out.append(("series", PR.pagerank_power_series(g.n, g.row_ptr, g.col, c, W, eps=1e-15)[0]))
+    out.append(("componentwise", CW.componentwise_solve(g.n, g.row_ptr, g.col, c, W, eps=1e-15)))
+    return out
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("m", [2, 3, 7])
+def test_cycle_and_complete_digraph(m):
+    cyc = _g(m, [(i, (i + 1) % m) for i in range(m)])
+    full = _g(m, [(i, j) for i in range(m) for j in range(m) if i != j])
+    for g in (cyc, full):
+        for name, R in _all_routes(g, np.ones(m)):
+            assert np.allclose(R, 1.0 / (1.0 - C), rtol=1e-12), name
+
+
+def test_chain():
+    k = 9
+    g = _g(k, [(i, i + 1) for i in range(k - 1)])
+    expect = np.array([(1 - C ** (j + 1)) / (1 - C) for j in range(k)])
+    for name, R in _all_routes(g, np.ones(k)):
+        assert np.allclose(R, expect, rtol=1e-13), name
+
+
+def test_out_tree_and_in_tree():
+    b, depth = 3, 3
+    nodes = [(0,)]
+    edges, index = [], {(0,): 0}
+    frontier = [(0,)]
+    for _ in range(depth):
+        nxt = []
+        for p in frontier:
+            for j in range(b):
+                ch = p + (j,)
+                index[ch] = len(index)
+                edges.append((index[p], index[ch]))
+                nxt.append(ch)
+        frontier = nxt
+    n = len(index)
+    dep = np.array([len(k) - 1 for k in sorted(index, key=index.get)])
+    out_tree = _g(n, edges)
+    exp_out = np.array([sum((C / b) ** i for i in range(d + 1)) for d in dep])
+    for name, R in _all_routes(out_tree, np.ones(n)):
+        assert np.allclose(R, exp_out, rtol=1e-13), name
+    in_tree = _g(n, [(v, u) for u, v in edges])
+    height = depth - dep
+    exp_in = np.array([sum((b * C) ** i for i in range(h + 1)) for h in height])
+    for name, R in _all_routes(in_tree, np.ones(n)):
+        assert np.allclose(R, exp_in, rtol=1e-13), name
+
+
+def test_bidirected_star():
+    m = 6
+    g = _g(m + 1, [(0, i) for i in range(1, m + 1)] + [(i, 0) for i in range(1, m + 1)])
+    hub = (1 + C * m) / (1 - C * C)
+    leaf = 1 + C * hub / m
+    for name, R in _all_routes(g, np.ones(m + 1)):
+        assert np.isclose(R[0], hub, rtol=1e-12) and np.allclose(R[1:], leaf, rtol=1e-12), name
+
+
+def test_singletons_keep_their_weight():
+    # Sec. 3.3: a component of isolated vertices has R = W (loops ignored)
+    rp = np.array([0, 1, 1, 2], dtype=np.int64)
+    col = np.array([0, 2], dtype=np.int32)  # vertex 0 has a loop, 2 a loop
+    W = np.array([0.3, 2.0, 5.0])
+    assert np.allclose(PR.pagerank_dense(3, rp, col, C, W), W)
+    assert np.allclose(CW.componentwise_solve(3, rp, col, C, W), W)
+
+
+def test_duplicate_edges_count_with_multiplicity():
+    # 0 -> 1 twice, 0 -> 2 once: a_01 = 2/3, a_02 = 1/3
+    rp = np.array([0, 3, 3, 3], dtype=np.int64)
+    col = np.array([1, 1, 2], dtype=np.int32)
+    W = np.ones(3)
+    R = PR.pagerank_dense(3, rp, col, C, W)
+    assert np.allclose(R, [1.0, 1 + C * 2 / 3, 1 + C / 3])
+    assert np.allclose(CW.componentwise_solve(3, rp, col, C, W, eps=1e-15), R)
+
+
+# ------------------------------------------------------ independent routes
+
+@pytest.mark.parametrize("seed", range(6))
+def test_definition_routes_agree(seed):
+    """Def. 3.4 eigenvector rescaled by Def. 3.5 equals the linear solve."""
+    g = random_digraph(25, 55, seed)
+    rng = np.random.default_rng(seed)
+    W = rng.random(g.n) + 0.1
+    Rd = PR.pagerank_dense(g.n, g.row_ptr, g.col, C, W)
+    R1 = PR.pagerank_r1(g.n, g.row_ptr, g.col, C, W)
+    R3 = PR.r3_from_r1(g.n, g.row_ptr, g.col, C, R1, W)
+    assert np.allclose(R3, Rd, rtol=1e-10)
+    assert np.isclose(np.sum(Rd / np.sum(Rd)), 1.0) and np.allclose(Rd / Rd.sum(), R1, rtol=1e-9)
+
+
+def test_random_walk_definition():
+    """Def. 3.6: expected visit counts of stopped random walks."""
+    g = _g(6, [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 3), (1, 5)])
+    W = np.ones(6)
+    est = PR.pagerank_random_walks(g.n, g.row_ptr, g.col, C, W, walks_per_unit=6000, seed=11)
+    Rd = PR.pagerank_dense(g.n, g.row_ptr, g.col, C, W)
+    assert np.allclose(est, Rd, rtol=0.05)
+    # the transposed operator gives clearly different values
+    Rwrong = np.linalg.solve(np.eye(6) - C * PR.transition_dense(6, g.row_ptr, g.col), W)
+    assert not np.allclose(est, Rwrong, rtol=0.05)
+
+
+def _path_sums(n, edges, W, c):
+    """Sum over every directed path ending at u of W_start * prod c/outdeg."""
+    out = {u: [b for a, b in edges if a == u] for u in range(n)}
+    R = np.zeros(n)
+
+    def walk(u, weight):
+        R[u] += weight
+        for v in out[u]:
+            walk(v, weight * c / len(out[u]))
+
+    for s in range(n):
+        walk(s, W[s])
+    return R
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_brute_force_paths_on_dags(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = 9
+    edges = sorted({(int(a), int(b)) for a, b in rng.integers(0, n, size=(16, 2)) if a < b})
+    g = _g(n, edges)
+    W = rng.random(n)
+    expect = _path_sums(n, edges, W, C)
+    for name, R in _all_routes(g, W):
+        assert np.allclose(R, expect, rtol=1e-12), name
+
+
+# ---------------------------------------------------------- stop rules
+
+def test_paper_mode_iterations_on_a_cycle():
+    """Sec. 4.2: a bottom-level SCC needs about log(tol)/log(c) iterations;
+    on a cycle P_k = c^k exactly, so the listing's rule stops after 128."""
+    m = 10
+    g = _g(m, [(i, (i + 1) % m) for i in range(m)])
+    expect = math.ceil(math.log(1e-9) / math.log(C))
+    assert expect == 128
+    _, k, _ = PR.pagerank_power_series(g.n, g.row_ptr, g.col, C, np.ones(m), stop="paper", tol=1e-9)
+    assert k == expect
+    _, st_ = CW.componentwise_solve(g.n, g.row_ptr, g.col, C, np.ones(m), stop="paper", tol=1e-9,
+                                    return_stats=True)
+    assert st_["iters"].tolist() == [expect]
+
+
+def test_cert_rule_iterations_on_a_cycle():
+    m = 5
+    g = _g(m, [(i, (i + 1) % m) for i in range(m)])
+    _, k, _ = PR.pagerank_power_series(g.n, g.row_ptr, g.col, C, np.ones(m), eps=1e-6)
+    # ||P_k||_1 = c^k m <= eps (1-c) m
+    assert k == math.ceil(math.log(1e-6 * (1 - C)) / math.log(C))
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6, 1e-9])
+def test_certificate_bounds_relative_error(eps):
+    g = config_graph("c1_small", seed=2)
+    W = np.ones(g.n)
+    ref, _, _ = PR.pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-15)
+    Rp, _, _ = PR.pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=eps)
+    Rc = CW.componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=eps)
+    for R in (Rp, Rc):
+        err = np.sum(np.abs(R - ref)) / np.sum(ref)
+        assert err <= eps
+        assert np.all(R <= ref * (1 + 1e-12))  # monotone from below (Sec. 3.4)
+
+
+def test_linearity_in_w():
+    g = random_digraph(60, 150, 5)
+    rng = np.random.default_rng(0)
+    W1, W2 = rng.random(g.n), rng.random(g.n)
+    f = lambda W: CW.componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=1e-15)
+    assert np.allclose(f(2 * W1 + 3 * W2), 2 * f(W1) + 3 * f(W2), rtol=1e-11)
+
+
+edge_lists = st.integers(min_value=1, max_value=40).flatmap(
+    lambda n: st.tuples(st.just(n), st.lists(
+        st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=3 * n)))
+
+
+@settings(max_examples=80, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(edge_lists, st.floats(0.05, 0.99))
+def test_property_componentwise_equals_dense(ne, c):
+    n, edges = ne
+    g = _g(n, edges)
+    W = np.linspace(0.5, 1.5, n)
+    Rd = PR.pagerank_dense(g.n, g.row_ptr, g.col, c, W)
+    Rc = CW.componentwise_solve(g.n, g.row_ptr, g.col, c, W, eps=1e-15)
+    assert np.allclose(Rc, Rd, rtol=1e-9, atol=0)
+
+
+def test_planted_transpose_mistake_is_caught():
+    """Using A instead of A^T must fail the chain closed form."""
+    k = 6
+    g = _g(k, [(i, i + 1) for i in range(k - 1)])
+    A = PR.transition_dense(k, g.row_ptr, g.col)
+    wrong = np.linalg.solve(np.eye(k) - C * A, np.ones(k))
+    expect = np.array([(1 - C ** (j + 1)) / (1 - C) for j in range(k)])
+    assert not np.allclose(wrong, expect, rtol=1e-6)
