@@ -1,0 +1,227 @@
+/*
+ * pr.h -- C ABI of the componentwise PageRank library (libpr.so) for MI355X.
+ *
+ * Method: Engstrom & Silvestrov, "Graph partitioning and a componentwise
+ * PageRank algorithm" (arXiv 1609.09068).  The library computes the
+ * non-normalised PageRank R^(3) of Def. 3.5, i.e. the solution of
+ *
+ *        (I - c A^T) R = W                                          (Sec. 3.3)
+ *
+ * where A is the adjacency matrix of the input graph with every non-zero row
+ * scaled to sum to one (Def. 3.4).  Self-loops are ignored everywhere, as in
+ * the experiments (Sec. 4.2); a repeated edge counts with its multiplicity
+ * in A and in the out-degree.
+ *
+ * Conventions for every entry point
+ *  - A graph is CSR over out-edges: row_ptr[n+1] (int64, row_ptr[0] == 0,
+ *    non-decreasing) and col_idx[m] (int32 in [0, n)), m = row_ptr[n].
+ *    Host pointers; the caller keeps ownership and the library never keeps a
+ *    caller pointer beyond the call.
+ *  - Vertex ids are the caller's ids; every output that is indexed by vertex
+ *    uses them.
+ *  - Return value: PR_OK (0) on success, PR_NOT_CONVERGED (1) when an
+ *    iteration limit was hit (outputs are still written), a negative PR_E*
+ *    code on failure.  On failure nothing is written to outputs and
+ *    pr_last_error() describes the cause.
+ *  - Handles (pr_partition_t, pr_levels_t, pr_mlp_t) are owned by the library and
+ *    released with pr_free().  A handle must not be used by two threads at
+ *    the same time.
+ *  - hip_stream is a hipStream_t (NULL = the null stream).  Device buffers
+ *    passed in must be valid on the current HIP device.
+ */
+#ifndef PR_H_
+#define PR_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define PR_OK 0
+#define PR_NOT_CONVERGED 1
+#define PR_EINVAL (-1)  /* bad argument: CSR, c outside (0,1), eps <= 0, W < 0 or not finite */
+#define PR_ENOMEM (-2)  /* host or device allocation failed */
+#define PR_EHIP (-3)    /* a HIP runtime call failed; the message carries its error string */
+#define PR_EHANDLE (-4) /* NULL, unknown, freed, or wrong kind of handle */
+
+typedef struct pr_partition_s pr_partition_t;
+typedef struct pr_levels_s pr_levels_t;
+typedef struct pr_mlp_s pr_mlp_t;
+
+/* ------------------------------------------------------------- partition */
+
+/*
+ * pr_partition -- SCC/CAC partition of Sec. 3.1 (Theorem 3.1), on the host.
+ *
+ * Runs the modified Tarjan depth-first search of Sec. 3.1 (iterative, so a
+ * path of 10^7 vertices is fine): strongly connected components are found as
+ * in Tarjan's algorithm, levels are propagated during the search, and a
+ * one-vertex component that points to CACs one level below it (and to no SCC
+ * of two or more vertices on that level) is merged with all of them.
+ * flags: must be 0.
+ * Result (read with pr_partition_get) is the unique partition of
+ * Theorem 3.1 in canonical form:
+ *   comp[v]        component id, numbered in order of first appearance while
+ *                  scanning v = 0..n-1 (Sec. 3.1, numbering pass)
+ *   comp_level[k]  0-based level (Def. 3.3): a component with no edge to
+ *                  another component has level 0
+ *   comp_type[k]   1 = SCC of two or more vertices, 0 = CAC (one-vertex
+ *                  components are CACs)
+ *   comp_size[k]   number of vertices
+ * Errors: PR_EINVAL for a malformed CSR or n outside [0, 2^31-2].
+ */
+int32_t pr_partition(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                     uint32_t flags, pr_partition_t** out);
+
+/*
+ * pr_partition_get -- copy the partition out.  Every pointer may be NULL to
+ * skip that output; comp holds n entries, the per-component arrays hold
+ * *n_comp entries (query n_comp first with the other pointers NULL).
+ */
+int32_t pr_partition_get(const pr_partition_t* p, int32_t* comp, int32_t* comp_level,
+                         uint8_t* comp_type, int32_t* comp_size, int64_t* n_comp,
+                         int32_t* n_levels);
+
+/* ------------------------------------------------------------- the plan */
+
+typedef struct pr_build_opts {
+  /* SCCs with at most small_cutoff vertices (<= 256) are iterated by one
+     wavefront each, their vector kept in LDS; 0 = default (64). */
+  int32_t small_cutoff;
+  /* SCCs with more internal edges than team_edges are iterated by a team of
+     workgroups, one per team_edges internal edges (capped by the number of
+     workgroups the device keeps resident); smaller ones by one workgroup.
+     0 = default. */
+  int32_t team_edges;
+  /* wavefront lanes given to one row in the SCC product: rows_per_wave in
+     {1, 4, 16, 64} rows share a 64-lane wavefront; 0 = default (4). */
+  int32_t rows_per_wave;
+  /* 1 = also keep the whole-graph pull CSR needed by method PLAIN. */
+  int32_t build_plain;
+  /* 1 = run the autotuner (sweeps rows_per_wave and the small/medium/team
+     split with timed solves; results cached in a JSON file named by the
+     environment variable PR_AUTOTUNE_CACHE, if set). */
+  int32_t autotune;
+  int32_t reserved[7];
+} pr_build_opts;
+
+void pr_default_build_opts(pr_build_opts* o);
+
+/*
+ * pr_build_levels -- the intermediate step of Sec. 3.2, on the device.
+ *
+ * Copies the CSR to the device and builds, with HIP kernels, the solve
+ * plan: components sorted by level (descending), type and size (descending),
+ * ties by id (Sec. 3.2); vertices renumbered level-major and component-major
+ * (topological order inside CACs); edges split into the pull CSR of edges
+ * between components (used once, eq. PR:levels) and of edges inside
+ * components; 1/outdeg; the work list of the persistent solve kernel.
+ * p must come from pr_partition on the same graph (n and the CSR must match).
+ * opts NULL = defaults.  The plan stays resident on the current device.
+ * Errors: PR_EINVAL (mismatch, m >= 2^31), PR_ENOMEM, PR_EHIP.
+ */
+int32_t pr_build_levels(const pr_partition_t* p, int64_t n, const int64_t* row_ptr,
+                        const int32_t* col_idx, const pr_build_opts* opts, void* hip_stream,
+                        pr_levels_t** out);
+
+typedef struct pr_levels_info {
+  int64_t n, m;             /* vertices, edges without self-loops */
+  int64_t n_comp, n_levels;
+  int64_t n_scc, n_cac, n_singleton;  /* components by kind */
+  int64_t v_scc, v_cac, v_singleton;  /* vertices by kind of component */
+  int64_t m_scc_internal;   /* edges inside SCCs (iterated) */
+  int64_t m_cac_internal;   /* edges inside CACs (used once) */
+  int64_t m_between;        /* edges between components (used once) */
+  int64_t n_items;          /* work items of the persistent kernel */
+  int64_t n_teams, max_team;/* SCCs iterated by workgroup teams, largest team */
+  int32_t rows_per_wave, small_cutoff, team_edges, grid_wgs;
+} pr_levels_info;
+
+int32_t pr_levels_get_info(const pr_levels_t* lv, pr_levels_info* info);
+
+/* ------------------------------------------------------------- the solve */
+
+#define PR_METHOD_COMPONENTWISE 0 /* level by level, Sec. 3.3 */
+#define PR_METHOD_PLAIN 1         /* whole-graph power series, Sec. 3.3.2 / Sec. 4.2 method 1 */
+
+#define PR_STOP_CERT_L1 0      /* per component: ||P_k||_1 <= eps (1-c) ||W'_C||_1 */
+#define PR_STOP_PAPER_MAXABS 1 /* per component: max(P_k) < tol (listing of Sec. 3.3.2) */
+
+#define PR_PREC_MIXED 0 /* series terms and SpMV in FP32; R, sums, norms, boundary mass in FP64 */
+#define PR_PREC_FP64 1  /* everything in FP64 */
+
+typedef struct pr_solve_opts {
+  int32_t method;    /* PR_METHOD_* */
+  int32_t stop;      /* PR_STOP_* */
+  int32_t precision; /* PR_PREC_* */
+  int32_t use_graph; /* 1 = capture the launch sequence in a hipGraph and replay it */
+  double eps;        /* PR_STOP_CERT_L1 target (relative 1-norm error bound); default 1e-6 */
+  double tol;        /* PR_STOP_PAPER_MAXABS threshold; default 1e-9 */
+  int64_t max_iter;  /* per-component iteration cap; default 100000 */
+  pr_mlp_t* warm_start;/* NULL = start every SCC from P_0 = W' (Sec. 3.3.2) */
+  int32_t reserved[8];
+} pr_solve_opts;
+
+void pr_default_solve_opts(pr_solve_opts* o);
+
+typedef struct pr_solve_stats {
+  int64_t edge_iters;   /* edges touched: iterations x internal edges of each SCC, plus every other edge once */
+  int64_t iters_max;    /* most iterations of any SCC (PLAIN: the iteration count) */
+  int64_t iters_sum;    /* sum over SCCs of their iterations */
+  int64_t n_iterated;   /* SCCs iterated */
+  int64_t n_not_converged;
+  int64_t ws_accepted, ws_rejected; /* warm start: per-SCC accept / fallback counts */
+  double cert_abs;      /* c/(1-c) * sum_C ||P_{K_C}||_1: bound on ||R* - R||_1 (CERT rule) */
+  double r_sum;         /* ||R||_1 */
+  double cert_rel;      /* cert_abs / r_sum: bound on the relative 1-norm error */
+  double time_ms;       /* device time of the solve (HIP events) */
+  int32_t reserved[8];
+} pr_solve_stats;
+
+/*
+ * pr_solve -- R^(3) for damping c and weights W (Def. 3.5), on the device.
+ *
+ * W_dev: n doubles (device), the weight vector in the caller's vertex order,
+ *        non-negative and finite.
+ * R_dev: n doubles (device), written with R in the caller's vertex order.
+ * COMPONENTWISE follows Sec. 3.3: levels from the highest down, each vertex's
+ * weight raised by the rank flowing in from higher levels (eq. PR:levels),
+ * one-vertex components copied, CACs solved exactly in topological order
+ * (Sec. 3.3.1), SCCs by the power series (Sec. 3.3.2) with the chosen stop
+ * rule.  PLAIN runs the power series on the whole graph with the same rule.
+ * With PR_STOP_CERT_L1 the relative 1-norm error of R is below eps in exact
+ * arithmetic (Sec. 3.4); stats->cert_rel reports the bound for this run.
+ * The call returns after the stream work has completed.
+ * Errors: PR_EINVAL (c outside (0,1), eps <= 0, tol <= 0, W negative or not
+ * finite, method PLAIN without build_plain), PR_EHIP.
+ */
+int32_t pr_solve(pr_levels_t* lv, double c, const void* W_dev, void* R_dev,
+                 const pr_solve_opts* opts, void* hip_stream, pr_solve_stats* stats);
+
+/*
+ * pr_levels_debug -- copy an internal array of the last solve to the host
+ * (for tests).  what: 0 = W' per vertex (double[n], caller's order; the
+ * weight after eq. PR:levels), 1 = iterations per component (int32[n_comp],
+ * component ids of the partition; 0 for non-SCC components), 2 = the plan's
+ * vertex order (int32[n]: position -> caller's vertex id).
+ */
+int32_t pr_levels_debug(const pr_levels_t* lv, int32_t what, void* host_out);
+
+/* --------------------------------------------------------------- common */
+
+/* Release any handle; NULL, unknown and already-released handles are ignored. */
+void pr_free(void* handle);
+
+/* Thread-local description of the last failure on this thread. */
+const char* pr_last_error(void);
+
+/* Library version string. */
+const char* pr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PR_H_ */

@@ -1,0 +1,169 @@
+"""Componentwise PageRank on MI355X (gfx950).
+
+The SCC/CAC partition of Sec. 3.1 runs on the host (C++); the intermediate
+step (Sec. 3.2) and the level-by-level PageRank step (Sec. 3.3) run in HIP
+kernels.  Everything is reached through the C ABI of libpr.so (include/pr.h);
+this module only marshals arguments.  torch tensors provide device buffers
+and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (PR_METHOD_COMPONENTWISE, PR_METHOD_PLAIN, PR_PREC_FP64, PR_PREC_MIXED,  # noqa: F401
+                   PR_STOP_CERT_L1, PR_STOP_PAPER_MAXABS, PRError, PR_NOT_CONVERGED)
+
+
+class Partition:
+    """Owner of a pr_partition_t handle (freed with the object)."""
+
+    def __init__(self, handle, n):
+        self.handle = handle
+        self.n = n
+        lib = _lib.load()
+        k = C.c_int64()
+        L = C.c_int32()
+        _lib._check(lib.pr_partition_get(handle, None, None, None, None, C.byref(k), C.byref(L)))
+        K = k.value
+        self.n_comp = K
+        self.n_levels = L.value
+        self.comp = np.zeros(n, dtype=np.int32)
+        self.comp_level = np.zeros(K, dtype=np.int32)
+        self.comp_type = np.zeros(K, dtype=np.uint8)
+        self.comp_size = np.zeros(K, dtype=np.int32)
+        _lib._check(lib.pr_partition_get(handle, _lib._ptr(self.comp, C.c_int32),
+                                         _lib._ptr(self.comp_level, C.c_int32),
+                                         _lib._ptr(self.comp_type, C.c_uint8),
+                                         _lib._ptr(self.comp_size, C.c_int32), None, None))
+
+    def as_dict(self):
+        return dict(comp=self.comp, comp_level=self.comp_level, comp_type=self.comp_type,
+                    comp_size=self.comp_size, n_comp=self.n_comp, n_levels=self.n_levels)
+
+    def free(self):
+        if self.handle:
+            _lib.load().pr_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Levels:
+    """Owner of a pr_levels_t handle (the device plan)."""
+
+    def __init__(self, handle, n):
+        self.handle = handle
+        self.n = n
+
+    def info(self):
+        inf = _lib.LevelsInfo()
+        _lib._check(_lib.load().pr_levels_get_info(self.handle, C.byref(inf)))
+        return inf.as_dict()
+
+    def debug(self, what, n_comp=None):
+        lib = _lib.load()
+        if what == "wprime":
+            out = np.zeros(self.n, dtype=np.float64)
+            code = 0
+        elif what == "iters":
+            out = np.zeros(n_comp, dtype=np.int32)
+            code = 1
+        elif what == "perm":
+            out = np.zeros(self.n, dtype=np.int32)
+            code = 2
+        else:
+            raise ValueError(what)
+        _lib._check(lib.pr_levels_debug(self.handle, code, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def free(self):
+        if self.handle:
+            _lib.load().pr_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pr_partition(row_ptr, col) -> Partition:
+    row_ptr, col = _lib._as_csr(row_ptr, col)
+    n = len(row_ptr) - 1
+    h = C.c_void_p()
+    _lib._check(_lib.load().pr_partition(n, _lib._ptr(row_ptr, C.c_int64), _lib._ptr(col, C.c_int32), 0,
+                                         C.byref(h)))
+    return Partition(h.value, n)
+
+
+def build_opts(**kw):
+    o = _lib.BuildOpts()
+    _lib.load().pr_default_build_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def solve_opts(**kw):
+    o = _lib.SolveOpts()
+    _lib.load().pr_default_solve_opts(C.byref(o))
+    for k, v in kw.items():
+        if k == "warm_start":
+            v = v.handle if v is not None and not isinstance(v, int) else v
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def pr_build_levels(part: Partition, row_ptr, col, stream=None, **opts) -> Levels:
+    row_ptr, col = _lib._as_csr(row_ptr, col)
+    n = len(row_ptr) - 1
+    o = build_opts(**opts)
+    h = C.c_void_p()
+    _lib._check(_lib.load().pr_build_levels(part.handle, n, _lib._ptr(row_ptr, C.c_int64),
+                                            _lib._ptr(col, C.c_int32), C.byref(o),
+                                            C.c_void_p(_stream_ptr(stream)), C.byref(h)))
+    return Levels(h.value, n)
+
+
+def pr_solve(levels: Levels, c, W, R, stream=None, **opts):
+    """W, R: float64 device tensors of length n (caller's vertex order).
+    Returns (return code, stats dict); raises PRError on a negative code."""
+    if W.dtype.itemsize != 8 or R.dtype.itemsize != 8 or not W.is_cuda or not R.is_cuda:
+        raise TypeError("W and R must be float64 device tensors")
+    if W.numel() != levels.n or R.numel() != levels.n:
+        raise ValueError("W / R must have n entries")
+    if not (W.is_contiguous() and R.is_contiguous()):
+        raise ValueError("W / R must be contiguous")
+    o = solve_opts(**opts)
+    st = _lib.SolveStats()
+    rc = _lib.load().pr_solve(levels.handle, float(c), C.c_void_p(W.data_ptr()), C.c_void_p(R.data_ptr()),
+                              C.byref(o), C.c_void_p(_stream_ptr(stream)), C.byref(st))
+    _lib._check(rc, allow=(_lib.PR_OK, _lib.PR_NOT_CONVERGED))
+    return rc, st.as_dict()
+
+
+def pr_free(obj):
+    obj.free()
+
+
+def pr_last_error() -> str:
+    return _lib.load().pr_last_error().decode()
+
+
+def version() -> str:
+    return _lib.load().pr_version().decode()

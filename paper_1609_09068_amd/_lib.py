@@ -1,0 +1,125 @@
+"""ctypes binding of libpr.so (include/pr.h).
+
+Argument marshalling only: every step of the method runs in the library.
+PyTorch supplies device memory (tensors' data pointers) and the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpr.so")
+
+PR_OK = 0
+PR_NOT_CONVERGED = 1
+PR_EINVAL = -1
+PR_ENOMEM = -2
+PR_EHIP = -3
+PR_EHANDLE = -4
+
+PR_METHOD_COMPONENTWISE = 0
+PR_METHOD_PLAIN = 1
+PR_STOP_CERT_L1 = 0
+PR_STOP_PAPER_MAXABS = 1
+PR_PREC_MIXED = 0
+PR_PREC_FP64 = 1
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("small_cutoff", C.c_int32), ("team_edges", C.c_int32), ("rows_per_wave", C.c_int32),
+                ("build_plain", C.c_int32), ("autotune", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("method", C.c_int32), ("stop", C.c_int32), ("precision", C.c_int32),
+                ("use_graph", C.c_int32), ("eps", C.c_double), ("tol", C.c_double),
+                ("max_iter", C.c_int64), ("warm_start", C.c_void_p), ("reserved", C.c_int32 * 8)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("edge_iters", C.c_int64), ("iters_max", C.c_int64), ("iters_sum", C.c_int64),
+                ("n_iterated", C.c_int64), ("n_not_converged", C.c_int64), ("ws_accepted", C.c_int64),
+                ("ws_rejected", C.c_int64), ("cert_abs", C.c_double), ("r_sum", C.c_double),
+                ("cert_rel", C.c_double), ("time_ms", C.c_double), ("reserved", C.c_int32 * 8)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class LevelsInfo(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "n", "m", "n_comp", "n_levels", "n_scc", "n_cac", "n_singleton", "v_scc", "v_cac",
+        "v_singleton", "m_scc_internal", "m_cac_internal", "m_between", "n_items", "n_teams",
+        "max_team")] + [(k, C.c_int32) for k in ("rows_per_wave", "small_cutoff", "team_edges", "grid_wgs")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol include/pr.h declares
+EXPORTS = ["pr_partition", "pr_partition_get", "pr_default_build_opts", "pr_build_levels",
+           "pr_levels_get_info", "pr_default_solve_opts", "pr_solve", "pr_levels_debug", "pr_free",
+           "pr_last_error", "pr_version"]
+
+_lib = None
+
+
+def load():
+    """Load libpr.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1609_09068_amd.build_lib` (there is no fallback)")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, U32, VP = C.POINTER, C.c_int32, C.c_int64, C.c_uint32, C.c_void_p
+    lib.pr_partition.argtypes = [I64, P(I64), P(I32), U32, P(VP)]
+    lib.pr_partition.restype = I32
+    lib.pr_partition_get.argtypes = [VP, P(I32), P(I32), P(C.c_uint8), P(I32), P(I64), P(I32)]
+    lib.pr_partition_get.restype = I32
+    lib.pr_default_build_opts.argtypes = [P(BuildOpts)]
+    lib.pr_default_build_opts.restype = None
+    lib.pr_build_levels.argtypes = [VP, I64, P(I64), P(I32), P(BuildOpts), VP, P(VP)]
+    lib.pr_build_levels.restype = I32
+    lib.pr_levels_get_info.argtypes = [VP, P(LevelsInfo)]
+    lib.pr_levels_get_info.restype = I32
+    lib.pr_default_solve_opts.argtypes = [P(SolveOpts)]
+    lib.pr_default_solve_opts.restype = None
+    lib.pr_solve.argtypes = [VP, C.c_double, VP, VP, P(SolveOpts), VP, P(SolveStats)]
+    lib.pr_solve.restype = I32
+    lib.pr_levels_debug.argtypes = [VP, I32, VP]
+    lib.pr_levels_debug.restype = I32
+    lib.pr_free.argtypes = [VP]
+    lib.pr_free.restype = None
+    lib.pr_last_error.argtypes = []
+    lib.pr_last_error.restype = C.c_char_p
+    lib.pr_version.argtypes = []
+    lib.pr_version.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class PRError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _check(rc, allow=(PR_OK,)):
+    if rc not in allow:
+        raise PRError(rc, load().pr_last_error().decode())
+    return rc
+
+
+def _as_csr(row_ptr, col):
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    return row_ptr, col
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))

@@ -1,0 +1,139 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pr.h"
+
+namespace prlib {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
+#define PR_HIP_CHECK(expr)                                                          \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      prlib::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),       \
+                       __FILE__, __LINE__);                                         \
+      return PR_EHIP;                                                               \
+    }                                                                               \
+  } while (0)
+
+// ---------------------------------------------------------------- handles
+enum HandleKind : uint32_t { KIND_PARTITION = 0x50415254u, KIND_LEVELS = 0x4c45564cu, KIND_MLP = 0x4d4c5050u };
+
+void registry_add(void* h, HandleKind k);
+bool registry_has(const void* h, HandleKind k);
+bool registry_remove(void* h, HandleKind* k);
+
+// --------------------------------------------------------------- partition
+struct Partition {
+  int64_t n = 0;
+  int64_t n_comp = 0;
+  int32_t n_levels = 0;
+  std::vector<int32_t> comp;        // [n]
+  std::vector<int32_t> comp_level;  // [K]
+  std::vector<uint8_t> comp_type;   // [K]
+  std::vector<int32_t> comp_size;   // [K]
+  // position of each vertex in the order the depth-first search closed its
+  // strongly connected component; reversed, it is a topological order of
+  // the DAG of SCCs (used to lay out CAC vertices in dependency order)
+  std::vector<int32_t> emit_pos;    // [n]
+  uint64_t graph_hash = 0;
+};
+
+int32_t run_partition(int64_t n, const int64_t* row_ptr, const int32_t* col, Partition& out);
+int32_t validate_csr(int64_t n, const int64_t* row_ptr, const int32_t* col);
+uint64_t hash_csr(int64_t n, const int64_t* row_ptr, const int32_t* col);
+
+// ---------------------------------------------------------------- the plan
+// One work item of the persistent solve kernel.
+struct Item {
+  int32_t kind;  // ITEM_*
+  int32_t a, b, c;
+};
+enum : int32_t { ITEM_VERTS = 0, ITEM_SMALL = 1, ITEM_TEAM = 2 };
+
+// Team bookkeeping for one SCC iterated by several (or one) workgroups.
+struct TeamDesc {
+  int32_t rank;     // component rank (plan order); -1 for the whole-graph team
+  int32_t size;     // workgroups in the team
+  int32_t vbeg, vend;
+  int32_t poff;     // first slot of the team in the partial-sum array
+  int32_t sync;     // index of the team's TeamSync
+  int32_t pad[2];
+};
+
+// Per-team synchronisation area (zeroed before each solve).
+struct alignas(128) TeamSync {
+  unsigned long long count;    // barrier arrivals
+  unsigned long long acc[3];   // fixed-point 1-norm accumulators (triple buffered)
+  unsigned long long mx[3];    // max-norm accumulators (bits of non-negative doubles)
+};
+
+struct Levels {
+  int64_t n = 0, m = 0, n_comp = 0;
+  int32_t n_levels = 0;
+  int device = 0;
+  uint64_t graph_hash = 0;
+  pr_build_opts opts{};
+  pr_levels_info info{};
+  // device arrays (plan order unless stated)
+  int32_t* perm = nullptr;        // [n] plan position -> caller id
+  int32_t* comp_vbeg = nullptr;   // [K+1] first plan position of each component (by rank)
+  int32_t* comp_rank_of_id = nullptr;  // [K] caller component id -> rank
+  int32_t* comp_id_of_rank = nullptr;  // [K]
+  uint32_t* bnd_ptr = nullptr;    // [n+1] pull CSR of edges between components
+  int32_t* bnd_src = nullptr;
+  uint32_t* int_ptr = nullptr;    // [n+1] pull CSR of edges inside components
+  int32_t* int_src = nullptr;
+  uint32_t* full_ptr = nullptr;   // [n+1] whole-graph pull CSR (method PLAIN)
+  int32_t* full_src = nullptr;
+  float* inv_deg32 = nullptr;     // [n] 1/outdeg (0 for dangling)
+  double* inv_deg64 = nullptr;    // [n]
+  Item* items = nullptr;          // [n_items]
+  TeamDesc* teams = nullptr;      // [n_teams]
+  Item* plain_items = nullptr;    // [grid]
+  TeamDesc* plain_team = nullptr; // [1]
+  int64_t n_items = 0, n_teams = 0;
+  int32_t grid = 0;               // resident workgroups of the solve kernel
+  // host copies used for scheduling and stats
+  std::vector<int32_t> h_comp_vbeg;          // [K+1]
+  std::vector<uint8_t> h_comp_class;         // [K] by rank: 0 SCC, 1 CAC(>=2), 2 singleton
+  std::vector<int32_t> h_comp_level;         // [K] by rank
+  std::vector<int64_t> h_comp_int_edges;     // [K] by rank
+  std::vector<int32_t> h_comp_id_of_rank;    // [K]
+  // per-solve work areas
+  double* x = nullptr;            // [n] c R_v / outdeg(v), -1 = not ready
+  double* R = nullptr;            // [n] rank in plan order (teams)
+  double* wprime = nullptr;       // [n] W' in plan order (debug / features)
+  void* y0 = nullptr;             // [n] series terms (float or double), ping
+  void* y1 = nullptr;             // [n] pong
+  TeamSync* tsync = nullptr;      // [n_teams + 1]
+  double* tpartial = nullptr;     // [sum of team sizes + grid]
+  int32_t* iters = nullptr;       // [K] by rank
+  double* lastnorm = nullptr;     // [K] by rank
+  unsigned long long* counters = nullptr;  // [16] queue head, stats
+  double* red = nullptr;          // [64] reduction scratch
+  // hipGraph cache
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  uint64_t graph_key = 0;
+  ~Levels();
+};
+
+int32_t build_levels(const Partition& p, const int64_t* row_ptr, const int32_t* col,
+                     const pr_build_opts& opts, hipStream_t stream, Levels& lv);
+int32_t make_schedule(Levels& lv, hipStream_t stream);
+int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_solve_opts& o,
+                     hipStream_t stream, pr_solve_stats* st);
+int32_t solve_grid_size(int precision, int* grid);
+
+}  // namespace prlib
