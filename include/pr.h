@@ -90,13 +90,13 @@ typedef struct pr_build_opts {
   /* SCCs with at most small_cutoff vertices (<= 256) are iterated by one
      wavefront each, their vector kept in LDS; 0 = default (64). */
   int32_t small_cutoff;
-  /* SCCs with more internal edges than team_edges are iterated by a team of
-     workgroups, one per team_edges internal edges (capped by the number of
-     workgroups the device keeps resident); smaller ones by one workgroup.
-     0 = default. */
+  /* SCCs with more than small_cutoff vertices and more internal edges than
+     team_edges are iterated by every workgroup of the device in a gang
+     phase (all such SCCs of one level together, one kernel launch per
+     series term); the others by one workgroup each.  0 = default. */
   int32_t team_edges;
   /* wavefront lanes given to one row in the SCC product: rows_per_wave in
-     {1, 4, 16, 64} rows share a 64-lane wavefront; 0 = default (4). */
+     {1, 4, 16, 64} rows share a 64-lane wavefront; 0 = default (64). */
   int32_t rows_per_wave;
   /* 1 = also keep the whole-graph pull CSR needed by method PLAIN. */
   int32_t build_plain;
@@ -134,8 +134,8 @@ typedef struct pr_levels_info {
   int64_t m_scc_internal;   /* edges inside SCCs (iterated) */
   int64_t m_cac_internal;   /* edges inside CACs (used once) */
   int64_t m_between;        /* edges between components (used once) */
-  int64_t n_items;          /* work items of the persistent kernel */
-  int64_t n_teams, max_team;/* SCCs iterated by workgroup teams, largest team */
+  int64_t n_items;          /* work items of the persistent segment kernels */
+  int64_t n_gangs, n_gang_scc; /* gang phases, SCCs iterated in gang phases */
   int32_t rows_per_wave, small_cutoff, team_edges, grid_wgs;
 } pr_levels_info;
 
@@ -176,7 +176,9 @@ typedef struct pr_solve_stats {
   double cert_abs;      /* c/(1-c) * sum_C ||P_{K_C}||_1: bound on ||R* - R||_1 (CERT rule) */
   double r_sum;         /* ||R||_1 */
   double cert_rel;      /* cert_abs / r_sum: bound on the relative 1-norm error */
-  double time_ms;       /* device time of the solve (HIP events) */
+  double time_ms;       /* device time of the solve (HIP events around its launches) */
+  int64_t vert_iters;   /* rows touched: iterations x vertices of each SCC, plus every other vertex once */
+  double kernel_ms;     /* device time of the persistent solve kernel alone (HIP events) */
   int32_t reserved[8];
 } pr_solve_stats;
 
@@ -205,7 +207,15 @@ int32_t pr_solve(pr_levels_t* lv, double c, const void* W_dev, void* R_dev,
  * (for tests).  what: 0 = W' per vertex (double[n], caller's order; the
  * weight after eq. PR:levels), 1 = iterations per component (int32[n_comp],
  * component ids of the partition; 0 for non-SCC components), 2 = the plan's
- * vertex order (int32[n]: position -> caller's vertex id).
+ * vertex order (int32[n]: position -> caller's vertex id), 3 = per-workgroup
+ * counters of the last solve (uint64[grid_wgs x 16]: edge and row
+ * iterations, iteration max/sum, SCCs iterated, not converged, warm-start
+ * accept/reject, then wall-clock ticks in vertex items, small-SCC items,
+ * single-workgroup SCC items, gang launches, readiness waits, segment
+ * kernels, the number
+ * of gang launches and ticks in single-workgroup SCC iterations), 4 = the
+ * item timeline of the last solve run with reserved[0] = 1 in its options
+ * (uint64[n_items x 4]: workgroup, start tick, end tick, item kind).
  */
 int32_t pr_levels_debug(const pr_levels_t* lv, int32_t what, void* host_out);
 

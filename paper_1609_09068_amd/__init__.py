@@ -78,6 +78,12 @@ class Levels:
         elif what == "perm":
             out = np.zeros(self.n, dtype=np.int32)
             code = 2
+        elif what == "wgstats":
+            out = np.zeros((self.info()["grid_wgs"], 16), dtype=np.uint64)
+            code = 3
+        elif what == "trace":
+            out = np.zeros((self.info()["n_items"], 4), dtype=np.uint64)
+            code = 4
         else:
             raise ValueError(what)
         _lib._check(lib.pr_levels_debug(self.handle, code, out.ctypes.data_as(C.c_void_p)))
@@ -116,6 +122,9 @@ def solve_opts(**kw):
     o = _lib.SolveOpts()
     _lib.load().pr_default_solve_opts(C.byref(o))
     for k, v in kw.items():
+        if k == "trace":
+            o.reserved[0] = 1 if v else 0
+            continue
         if k == "warm_start":
             v = v.handle if v is not None and not isinstance(v, int) else v
         setattr(o, k, v)

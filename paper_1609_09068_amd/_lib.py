@@ -43,7 +43,8 @@ class SolveStats(C.Structure):
     _fields_ = [("edge_iters", C.c_int64), ("iters_max", C.c_int64), ("iters_sum", C.c_int64),
                 ("n_iterated", C.c_int64), ("n_not_converged", C.c_int64), ("ws_accepted", C.c_int64),
                 ("ws_rejected", C.c_int64), ("cert_abs", C.c_double), ("r_sum", C.c_double),
-                ("cert_rel", C.c_double), ("time_ms", C.c_double), ("reserved", C.c_int32 * 8)]
+                ("cert_rel", C.c_double), ("time_ms", C.c_double), ("vert_iters", C.c_int64),
+                ("kernel_ms", C.c_double), ("reserved", C.c_int32 * 8)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -52,8 +53,8 @@ class SolveStats(C.Structure):
 class LevelsInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n", "m", "n_comp", "n_levels", "n_scc", "n_cac", "n_singleton", "v_scc", "v_cac",
-        "v_singleton", "m_scc_internal", "m_cac_internal", "m_between", "n_items", "n_teams",
-        "max_team")] + [(k, C.c_int32) for k in ("rows_per_wave", "small_cutoff", "team_edges", "grid_wgs")]
+        "v_singleton", "m_scc_internal", "m_cac_internal", "m_between", "n_items", "n_gangs",
+        "n_gang_scc")] + [(k, C.c_int32) for k in ("rows_per_wave", "small_cutoff", "team_edges", "grid_wgs")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -54,29 +54,37 @@ int32_t validate_csr(int64_t n, const int64_t* row_ptr, const int32_t* col);
 uint64_t hash_csr(int64_t n, const int64_t* row_ptr, const int32_t* col);
 
 // ---------------------------------------------------------------- the plan
-// One work item of the persistent solve kernel.
+// One work item of a persistent segment kernel.
 struct Item {
   int32_t kind;  // ITEM_*
   int32_t a, b, c;
 };
-enum : int32_t { ITEM_VERTS = 0, ITEM_SMALL = 1, ITEM_TEAM = 2 };
+enum : int32_t { ITEM_VERTS = 0, ITEM_SMALL = 1, ITEM_MEDIUM = 2 };
 
-// Team bookkeeping for one SCC iterated by several (or one) workgroups.
-struct TeamDesc {
-  int32_t rank;     // component rank (plan order); -1 for the whole-graph team
-  int32_t size;     // workgroups in the team
+// A gang phase: the large SCCs of one level (or the whole graph for method
+// PLAIN) iterated by every workgroup, one kernel launch per series term.
+struct GangDesc {
+  int32_t vbeg, vend;   // plan rows covered (the SCCs are contiguous)
+  int32_t s0, s1;       // range in the GangScc table
+  int32_t boff;         // offset of the grid+1 row bounds in the bounds table
+  int32_t pad[3];
+};
+struct GangScc {
+  int32_t rank;         // component rank (-1: whole graph)
   int32_t vbeg, vend;
-  int32_t poff;     // first slot of the team in the partial-sum array
-  int32_t sync;     // index of the team's TeamSync
-  int32_t pad[2];
+  int32_t wg_first, wg_last;  // workgroups whose rows intersect the SCC
+  int32_t pbase;        // first partial-sum slot (one per covering workgroup)
+  int32_t gidx;         // index of this entry in the table
+  int32_t pad;
 };
 
-// Per-team synchronisation area (zeroed before each solve).
-struct alignas(128) TeamSync {
-  unsigned long long count;    // barrier arrivals
-  unsigned long long acc[3];   // fixed-point 1-norm accumulators (triple buffered)
-  unsigned long long mx[3];    // max-norm accumulators (bits of non-negative doubles)
+// Phase of a solve: a persistent segment over items [a, b) or gang a.
+struct Phase {
+  int32_t kind;  // 0 = segment, 1 = gang
+  int32_t a, b;
 };
+
+constexpr int kWgStats = 16;  // per-workgroup counters accumulated over a solve
 
 struct Levels {
   int64_t n = 0, m = 0, n_comp = 0;
@@ -99,11 +107,21 @@ struct Levels {
   float* inv_deg32 = nullptr;     // [n] 1/outdeg (0 for dangling)
   double* inv_deg64 = nullptr;    // [n]
   Item* items = nullptr;          // [n_items]
-  TeamDesc* teams = nullptr;      // [n_teams]
-  Item* plain_items = nullptr;    // [grid]
-  TeamDesc* plain_team = nullptr; // [1]
-  int64_t n_items = 0, n_teams = 0;
-  int32_t grid = 0;               // resident workgroups of the solve kernel
+  int64_t n_items = 0;
+  int32_t grid = 0;               // workgroups of a segment kernel launch
+  int32_t ggrid = 0;              // workgroups of a gang kernel launch
+  int32_t sgrid = 0;              // max(grid, ggrid): per-workgroup counter rows
+  unsigned* seg_heads = nullptr;  // [phases] item counters of the segments
+  std::vector<Phase> phases;      // componentwise schedule
+  GangDesc* gangs = nullptr;      // [n_gangs + 1]; the last one is the whole-graph gang
+  GangScc* gsccs = nullptr;       // [n_gscc + 1]
+  int32_t* gbounds = nullptr;     // [(n_gangs + 1) * (grid + 1)]
+  int64_t n_gangs = 0, n_gscc = 0, n_gslots = 0;
+  double* gpart = nullptr;        // [2 * n_gslots] partial 1-norms of the last two terms
+  double* gpmx = nullptr;         // [2 * n_gslots] partial max-norms
+  double* gwsum = nullptr;        // [n_gscc + 1] ||W'_C||_1 of each gang SCC
+  int32_t* gdone = nullptr;       // [n_gscc + 1] iterations when converged, -1 while running
+  std::vector<uint32_t> h_int_ptr, h_full_ptr;
   // host copies used for scheduling and stats
   std::vector<int32_t> h_comp_vbeg;          // [K+1]
   std::vector<uint8_t> h_comp_class;         // [K] by rank: 0 SCC, 1 CAC(>=2), 2 singleton
@@ -116,8 +134,9 @@ struct Levels {
   double* wprime = nullptr;       // [n] W' in plan order (debug / features)
   void* y0 = nullptr;             // [n] series terms (float or double), ping
   void* y1 = nullptr;             // [n] pong
-  TeamSync* tsync = nullptr;      // [n_teams + 1]
-  double* tpartial = nullptr;     // [sum of team sizes + grid]
+  unsigned long long* wgstats = nullptr;  // [grid * kWgStats]
+  unsigned long long* trace = nullptr;    // [n_items * 4] optional item timeline
+  hipStream_t cap_stream = nullptr;       // stream used to capture the hipGraph
   int32_t* iters = nullptr;       // [K] by rank
   double* lastnorm = nullptr;     // [K] by rank
   unsigned long long* counters = nullptr;  // [16] queue head, stats

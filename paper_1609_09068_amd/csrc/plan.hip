@@ -169,10 +169,12 @@ int32_t dalloc(T** p, size_t count) {
 
 Levels::~Levels() {
   void* ps[] = {perm, comp_vbeg, comp_rank_of_id, comp_id_of_rank, bnd_ptr, bnd_src, int_ptr, int_src,
-                full_ptr, full_src, inv_deg32, inv_deg64, items, teams, plain_items, plain_team, x, R,
-                wprime, y0, y1, tsync, tpartial, iters, lastnorm, counters, red};
+                full_ptr, full_src, inv_deg32, inv_deg64, items, gangs, gsccs, gbounds, gpart, gpmx,
+                gwsum, gdone, x, R, wprime, y0, y1, iters, lastnorm, counters, red, wgstats, trace,
+                seg_heads};
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (graph) (void)hipGraphDestroy(graph);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (void* p : ps)
     if (p) (void)hipFree(p);
 }
@@ -301,6 +303,14 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
     PR_TRY(dalloc(&lv.full_src, m));
     PR_HIP_CHECK(hipMemcpyAsync(lv.full_ptr, fptr, sizeof(uint32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
     if (m) PR_HIP_CHECK(hipMemcpyAsync(lv.full_src, sval, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
+  }
+
+  // ---- host copies of the pull row pointers (gang row bounds)
+  lv.h_int_ptr.resize(n + 1);
+  PR_HIP_CHECK(hipMemcpyAsync(lv.h_int_ptr.data(), lv.int_ptr, sizeof(uint32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+  if (opts.build_plain) {
+    lv.h_full_ptr.resize(n + 1);
+    PR_HIP_CHECK(hipMemcpyAsync(lv.h_full_ptr.data(), fptr, sizeof(uint32_t) * (n + 1), hipMemcpyDeviceToHost, s));
   }
 
   // ---- host copies for scheduling

@@ -42,14 +42,19 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kSmallMax = 256;  // rows of a wavefront-resident SCC
 
-enum : int { C_HEAD = 0, C_EDGE_ITERS = 1, C_ITERS_MAX = 2, C_ITERS_SUM = 3, C_N_ITERATED = 4,
-             C_NOT_CONV = 5, C_ERROR = 6, C_BAD_W = 7, C_WS_ACC = 8, C_WS_REJ = 9, C_COUNT = 16 };
+// per-workgroup counters (LDS during a kernel, accumulated in global memory
+// across the launches of a solve); the last ones are wall-clock ticks
+enum : int { S_EDGE_ITERS = 0, S_VERT_ITERS = 1, S_ITERS_MAX = 2, S_ITERS_SUM = 3, S_N_ITERATED = 4,
+             S_NOT_CONV = 5, S_WS_ACC = 6, S_WS_REJ = 7, S_T_VERTS = 8, S_T_SMALL = 9, S_T_MEDIUM = 10,
+             S_T_GANG = 11, S_T_WAIT = 12, S_T_SEGMENT = 13, S_N_GANG = 14, S_T_MEDIUM_ITER = 15 };
+// global counters: [0, kWgStats) reduced from the workgroup counters, then flags
+enum : int { C_ERROR = 16, C_BAD_W = 17, C_COUNT = 32 };
 
 struct SolveParams {
   int32_t n;
   int32_t stop;
   int32_t plain;
-  int32_t n_items;
+  int32_t n_items;  // items of the segment being run
   double c, eps, tol;
   int64_t max_iter;
   const double* W;
@@ -67,13 +72,22 @@ struct SolveParams {
   void* y0;
   void* y1;
   const Item* items;
-  const TeamDesc* teams;
-  TeamSync* tsync;
-  double* tpartial;
   const int32_t* comp_vbeg;
   int32_t* iters;
   double* lastnorm;
   unsigned long long* counters;
+  unsigned long long* wgstats;
+  const GangDesc* gangs;
+  const GangScc* gscc;
+  const int32_t* gbounds;
+  double* gpart;
+  double* gpmx;
+  double* gwsum;
+  int32_t* gdone;
+  int64_t n_gslots;
+  unsigned* seg_head;          // item counter of the segment being run
+  unsigned long long* trace;   // optional per-item timeline [n_items][4]
+  int32_t item_base;           // index of this segment's first item in the plan
   unsigned long long timeout;  // wall-clock ticks a wait may take before it is abandoned
 };
 
@@ -103,24 +117,91 @@ __device__ inline bool timed_out(const SolveParams& p, unsigned long long t0) {
   return false;
 }
 
-// butterfly sum: every lane ends with the same, bitwise identical value
+// Cross-lane reductions with DPP (quad_perm xor 1 / xor 2, row half mirror,
+// row mirror) inside each 16-lane row, then the four row values read as
+// scalars and combined in a fixed order.  Every butterfly step pairs a lane
+// with its partner and both compute the same (commutative) sum, so every
+// lane ends with the bitwise identical result.  All 64 lanes must be active.
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ inline float dpp(float v) { return dpp_f<CTRL>(v); }
+template <int CTRL>
+__device__ inline double dpp(double v) { return dpp_d<CTRL>(v); }
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+__device__ inline double readlane_d(double v, int l) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ inline float readlane_f(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ inline double readlane(double v, int l) { return readlane_d(v, l); }
+__device__ inline float readlane(float v, int l) { return readlane_f(v, l); }
+
+template <typename T>
+__device__ inline T row16_sum(T v) {
+  v += dpp<kDppXor1>(v);
+  v += dpp<kDppXor2>(v);
+  v += dpp<kDppHalfMirror>(v);
+  v += dpp<kDppMirror>(v);
+  return v;
+}
+template <typename T>
+__device__ inline T row16_max(T v) {
+  v = fmax(v, dpp<kDppXor1>(v));
+  v = fmax(v, dpp<kDppXor2>(v));
+  v = fmax(v, dpp<kDppHalfMirror>(v));
+  v = fmax(v, dpp<kDppMirror>(v));
+  return v;
+}
 template <typename T>
 __device__ inline T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = row16_sum(v);
+  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
 }
 template <typename T>
 __device__ inline T wave_max(T v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = row16_max(v);
+  return fmax(fmax(readlane(v, 0), readlane(v, 16)), fmax(readlane(v, 32), readlane(v, 48)));
 }
+// sum over aligned groups of LPR lanes; every lane of a group gets the result
 template <int LPR, typename T>
 __device__ inline T group_sum(T v) {
-#pragma unroll
-  for (int o = LPR / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  if constexpr (LPR >= 2) v += dpp<kDppXor1>(v);
+  if constexpr (LPR >= 4) v += dpp<kDppXor2>(v);
+  if constexpr (LPR >= 8) v += dpp<kDppHalfMirror>(v);
+  if constexpr (LPR >= 16) v += dpp<kDppMirror>(v);
+  if constexpr (LPR == 64) v = (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
   return v;
+}
+
+// sum and max over the workgroup with a single barrier; red holds 16
+// doubles used by alternating parities
+__device__ inline void block_sum_max(double v, double m, double* red, int parity, double* sum, double* mx) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  m = wave_max(m);
+  double* r = red + 8 * parity;
+  if (lane == 0) {
+    r[wave] = v;
+    r[4 + wave] = m;
+  }
+  __syncthreads();
+  *sum = (r[0] + r[1]) + (r[2] + r[3]);
+  *mx = fmax(fmax(r[4], r[5]), fmax(r[6], r[7]));
 }
 
 __device__ inline double block_sum(double v, double* lds) {
@@ -144,68 +225,242 @@ __device__ inline double block_max(double v, double* lds) {
   return t;
 }
 
-// sum of x over the between-component in-edges of row v, waiting for
-// sources that are not final yet; LPR lanes share the row
-template <int LPR>
-__device__ inline double gather_between(const SolveParams& p, int v, bool act, int sub) {
+// ---------------------------------------------------------------- gathers
+// A lane-per-row gather hands rows with more than kLongLane sources to the
+// whole wavefront; a group of LPR lanes hands over rows longer than
+// max(kLongLane, 8 LPR).
+constexpr uint32_t kLongLane = 32;
+
+// this lane's share (stride STRIDE from lo) of sum x[src[e]], e in [lo, hi);
+// returns false if a source is not final yet (the sum is then garbage)
+template <int STRIDE>
+__device__ inline bool lane_partial_x(const SolveParams& p, const int32_t* src, uint32_t lo, uint32_t hi,
+                                      double* out) {
   double acc = 0.0;
-  if (act) {
-    const uint32_t lo = p.bnd_ptr[v], hi = p.bnd_ptr[v + 1];
-    unsigned long long t0 = 0;
-    bool first = true;
+  bool ok = true;
+  uint32_t e = lo;
+  for (; e + 3 * STRIDE < hi; e += 4 * STRIDE) {
+    const int32_t s0 = src[e], s1 = src[e + STRIDE], s2 = src[e + 2 * STRIDE], s3 = src[e + 3 * STRIDE];
+    const double a0 = ld_x(p.x, s0), a1 = ld_x(p.x, s1), a2 = ld_x(p.x, s2), a3 = ld_x(p.x, s3);
+    ok &= (a0 >= 0.0) & (a1 >= 0.0) & (a2 >= 0.0) & (a3 >= 0.0);
+    acc += a0;
+    acc += a1;
+    acc += a2;
+    acc += a3;
+  }
+  for (; e < hi; e += STRIDE) {
+    const double a = ld_x(p.x, src[e]);
+    ok &= (a >= 0.0);
+    acc += a;
+  }
+  *out = acc;
+  return ok;
+}
+
+// per-lane blocking version: sources live in other items, so waiting here
+// cannot hold up a lane of the same wavefront
+template <int STRIDE>
+__device__ inline double lane_partial_x_wait(const SolveParams& p, const int32_t* src, uint32_t lo, uint32_t hi) {
+  double acc = 0.0;
+  if (lane_partial_x<STRIDE>(p, src, lo, hi, &acc)) return acc;
+  const unsigned long long t0 = wall_clock64();
+  while (true) {
+    __builtin_amdgcn_s_sleep(2);
+    if (lane_partial_x<STRIDE>(p, src, lo, hi, &acc)) return acc;
+    if (timed_out(p, t0)) return 0.0;
+  }
+}
+
+// whole-wavefront sum of x over [lo, hi), blocking (wave-uniform arguments)
+__device__ inline double wave_gather_x_wait(const SolveParams& p, const int32_t* src, uint32_t lo, uint32_t hi) {
+  const int lane = threadIdx.x & 63;
+  double part = 0.0;
+  bool ok = lane_partial_x<64>(p, src, lo + lane, hi, &part);
+  if (!__all(ok)) {
+    const unsigned long long t0 = wall_clock64();
     while (true) {
-      acc = 0.0;
-      bool ok = true;
-      for (uint32_t e = lo + sub; e < hi; e += LPR) {
-        const double xv = ld_x(p.x, p.bnd_src[e]);
-        ok &= (xv >= 0.0);
-        acc += xv;
-      }
-      if (ok) break;
-      if (first) {
-        t0 = wall_clock64();
-        first = false;
-      } else if (timed_out(p, t0)) {
-        acc = 0.0;
+      __builtin_amdgcn_s_sleep(2);
+      ok = lane_partial_x<64>(p, src, lo + lane, hi, &part);
+      if (__all(ok)) break;
+      if (timed_out(p, t0)) {
+        part = 0.0;
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
     }
   }
-  return group_sum<LPR>(acc);
+  return wave_sum(part);
+}
+
+// whole-wavefront attempt without waiting; false if a source is not final
+__device__ inline bool wave_gather_x_try(const SolveParams& p, const int32_t* src, uint32_t lo, uint32_t hi,
+                                         double* out) {
+  const int lane = threadIdx.x & 63;
+  double part = 0.0;
+  const bool ok = lane_partial_x<64>(p, src, lo + lane, hi, &part);
+  if (!__all(ok)) return false;
+  *out = wave_sum(part);
+  return true;
+}
+
+// ------------------------------------------------------------ tiled gather
+// A wavefront sums, for up to 64 consecutive rows [ra, ra+nr), the values
+// val[src[e]] over each row's sources.  The tile's sources are streamed in
+// chunks of kChunk edges: phase 1 has all 64 lanes load 8 source indices and
+// 8 values each (independent, coalesced index loads) into LDS; phase 2 sums
+// each row's part of the chunk from LDS, 64/RPW rows at a time with LPR
+// lanes per row.  Row sums accumulate chunk by chunk in edge order, so the
+// result does not depend on timing.  With WAIT_X the values are the x
+// vector and a chunk is re-read until every source is final.
+constexpr int kChunk = 512;
+
+struct WaveTile {
+  double buf[kChunk];
+  double racc[64];
+  uint32_t rlo[64], rhi[64];
+  unsigned long long* wst;  // the workgroup's counters (time accounting)
+};
+
+template <int RPW, typename VT, bool WAIT_X>
+__device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const int32_t* src, const VT* val,
+                               int ra, int nr, WaveTile* t) {
+  constexpr int LPR = 64 / RPW;
+  const int lane = threadIdx.x & 63;
+  VT* buf = reinterpret_cast<VT*>(t->buf);
+  VT* racc = reinterpret_cast<VT*>(t->racc);
+  const bool act = lane < nr;
+  const uint32_t lo = act ? ptr[ra + lane] : 0u, hi = act ? ptr[ra + lane + 1] : 0u;
+  const uint32_t E0 = __shfl(lo, 0, 64);
+  const uint32_t E1 = __shfl(hi, nr - 1, 64);
+  t->rlo[lane] = lo;
+  t->rhi[lane] = hi;
+  racc[lane] = (VT)0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  for (uint32_t cs = E0; cs < E1; cs += kChunk) {
+    const uint32_t ce = cs + kChunk < E1 ? cs + kChunk : E1;
+    int32_t idx[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t e = cs + lane + 64 * j;
+      idx[j] = e < ce ? src[e] : -1;
+    }
+    if constexpr (WAIT_X) {
+      unsigned long long t0 = 0;
+      bool first = true;
+      while (true) {
+        double v[8];
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = idx[j] >= 0 ? ld_x(p.x, idx[j]) : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          ok &= v[j] >= 0.0;
+          if (idx[j] >= 0) buf[lane + 64 * j] = (VT)v[j];
+        }
+        if (__all(ok)) {
+          if (!first && lane == 0) atomicAdd(&t->wst[S_T_WAIT], wall_clock64() - t0);
+          break;
+        }
+        if (first) {
+          t0 = wall_clock64();
+          first = false;
+        } else if (timed_out(p, t0)) {
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    } else {
+      VT v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = idx[j] >= 0 ? val[idx[j]] : (VT)0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (idx[j] >= 0) buf[lane + 64 * j] = v[j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int b = 0; b < 64 / RPW; ++b) {
+      const int row = b * RPW + lane / LPR;
+      const int sub = lane % LPR;
+      VT s = (VT)0;
+      bool touch = false;
+      if (row < nr) {
+        const uint32_t rl = t->rlo[row], rh = t->rhi[row];
+        const uint32_t a = rl > cs ? rl : cs, z = rh < ce ? rh : ce;
+        touch = a < z;
+        for (uint32_t e = a + sub; e < z; e += LPR) s += buf[e - cs];
+      }
+      s = group_sum<LPR>(s);
+      if (touch && sub == 0) racc[row] += s;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+  return act ? racc[lane] : (VT)0;
 }
 
 // ------------------------------------------------------------------ items
 
 // One-vertex components and CAC vertices (Sec. 3.3 first bullet, Sec. 3.3.1).
-__device__ void run_verts(const SolveParams& p, int vbeg, int vend) {
+// Sources inside the same item are resolved through LDS (xl), so a chain of
+// CAC vertices advances at LDS speed; other sources come from the global x.
+__device__ void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* tile, double* xl) {
+  const int lane = threadIdx.x & 63;
   const int v = vbeg + (int)threadIdx.x;
   const bool act = v < vend;
-  double acc = gather_between<1>(p, v, act, 0);
+  const int ra = vbeg + (int)(threadIdx.x & ~63u);
+  const int nr = vend - ra < 64 ? vend - ra : 64;
+  if (nr <= 0) return;
+  double acc = wave_tile_gather<64, double, true>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile);
   if (act) {
     acc += p.W[p.perm[v]];
     p.wprime[v] = acc;
   }
+  // in-edges inside the CAC, in topological order: sources may sit in this
+  // very item, so nothing here blocks; every round lets each lane (and
+  // each long row, wavefront-wide) use what is final so far
   uint32_t e = act ? p.int_ptr[v] : 0u;
   const uint32_t hi = act ? p.int_ptr[v + 1] : 0u;
+  const bool lng = (hi - e) > kLongLane;
   bool done = !act;
-  unsigned long long t0 = wall_clock64();
+  unsigned long long t0 = 0;
+  bool first = true;
+  volatile double* vxl = xl;
   while (true) {
-    if (!done) {
-      while (e < hi) {  // in-edges inside the CAC, in topological order
-        const double xv = ld_x(p.x, p.int_src[e]);
+    if (!done && !lng) {
+      while (e < hi) {
+        const int u = p.int_src[e];
+        const double xv = (u >= vbeg && u < vend) ? vxl[u - vbeg] : ld_x(p.x, u);
         if (xv < 0.0) break;
         acc += xv;
         ++e;
       }
       if (e == hi) {
-        st_x(p.x, v, p.c * acc * p.inv64[v]);
+        const double xv = p.c * acc * p.inv64[v];
+        vxl[v - vbeg] = xv;
+        st_x(p.x, v, xv);
+        p.Rout[p.perm[v]] = acc;
+        done = true;
+      }
+    }
+    unsigned long long m = __ballot(!done && lng);
+    while (m) {
+      const int b = __ffsll(m) - 1;
+      m &= m - 1;
+      const uint32_t blo = __shfl(e, b, 64), bhi = __shfl(hi, b, 64);
+      double s = 0.0;
+      if (wave_gather_x_try(p, p.int_src, blo, bhi, &s) && lane == b) {
+        acc += s;
+        const double xv = p.c * acc * p.inv64[v];
+        vxl[v - vbeg] = xv;
+        st_x(p.x, v, xv);
         p.Rout[p.perm[v]] = acc;
         done = true;
       }
     }
     if (__all(done)) break;
-    if (timed_out(p, t0)) {
+    if (first) {
+      t0 = wall_clock64();
+      first = false;
+    } else if (timed_out(p, t0)) {
       if (!done) {
         p.Rout[p.perm[v]] = acc;
         st_x(p.x, v, 0.0);
@@ -220,9 +475,34 @@ __device__ inline bool stop_now(const SolveParams& p, double norm, double mx, do
   return p.stop == PR_STOP_CERT_L1 ? (norm <= thresh) : (mx < p.tol);
 }
 
-// An SCC with at most 256 vertices, iterated by one wavefront.
+__device__ inline void record_scc(const SolveParams& p, int rank, int64_t k, double last, bool conv, uint64_t ne,
+                                  uint64_t nv, unsigned long long* wst, bool lds_stats) {
+  p.iters[rank] = (int32_t)k;
+  p.lastnorm[rank] = last;
+  if (lds_stats) {
+    atomicAdd(&wst[S_EDGE_ITERS], (unsigned long long)k * ne);
+    atomicAdd(&wst[S_VERT_ITERS], (unsigned long long)k * nv);
+    atomicMax(&wst[S_ITERS_MAX], (unsigned long long)k);
+    atomicAdd(&wst[S_ITERS_SUM], (unsigned long long)k);
+    atomicAdd(&wst[S_N_ITERATED], 1ull);
+    if (!conv) atomicAdd(&wst[S_NOT_CONV], 1ull);
+  } else {
+    wst[S_EDGE_ITERS] += (unsigned long long)k * ne;
+    wst[S_VERT_ITERS] += (unsigned long long)k * nv;
+    if ((unsigned long long)k > wst[S_ITERS_MAX]) wst[S_ITERS_MAX] = (unsigned long long)k;
+    wst[S_ITERS_SUM] += (unsigned long long)k;
+    wst[S_N_ITERATED] += 1ull;
+    if (!conv) wst[S_NOT_CONV] += 1ull;
+  }
+}
+
+// An SCC with at most 256 vertices, iterated by one wavefront.  After the
+// weights are gathered, the component's internal rows are copied into LDS
+// (one-byte local source ids, two-byte row offsets) when they fit, so every
+// term touches only LDS and registers (R stays in registers, four rows per
+// lane).
 template <typename YT>
-__device__ void run_small(const SolveParams& p, int rank, YT* ybuf) {
+__device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned long long* wst, WaveTile* tile) {
   const int lane = threadIdx.x & 63;
   const int vbeg = p.comp_vbeg[rank];
   const int nv = p.comp_vbeg[rank + 1] - vbeg;
@@ -236,7 +516,10 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf) {
     const int i = lane + 64 * j;
     const bool act = i < nv;
     const int v = vbeg + i;
-    const double wp = gather_between<1>(p, v, act, 0) + (act ? p.W[p.perm[v]] : 0.0);
+    double wp = 0.0;
+    const int nr = nv - 64 * j < 64 ? nv - 64 * j : 64;
+    if (nr > 0) wp = wave_tile_gather<64, double, true>(p, p.bnd_ptr, p.bnd_src, p.x, vbeg + 64 * j, nr, tile);
+    if (act) wp += p.W[p.perm[v]];
     Rj[j] = wp;
     inv[j] = act ? p.inv32[v] : 0.0f;
     if (act) {
@@ -246,6 +529,24 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf) {
       part += wp;
     }
   }
+  // stage the internal rows in LDS (the tile is free after the gathers)
+  const uint32_t eb = p.int_ptr[vbeg];
+  const uint32_t ne = p.int_ptr[vbeg + nv] - eb;
+  const bool staged = ne <= (uint32_t)sizeof(tile->buf);
+  uint8_t* lsrc = reinterpret_cast<uint8_t*>(tile->buf);
+  uint16_t* lptr = reinterpret_cast<uint16_t*>(tile->racc);  // racc + rlo + rhi: 1 KB >= 2 * 257
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (staged) {
+    for (uint32_t q = lane; q < ne; q += 64) lsrc[q] = (uint8_t)(p.int_src[eb + q] - vbeg);
+    for (int q = lane; q <= nv; q += 64) lptr[q] = (uint16_t)(p.int_ptr[vbeg + q] - eb);
+  }
+  uint32_t rlo[4], rhi[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = lane + 64 * j;
+    rlo[j] = i < nv ? p.int_ptr[vbeg + i] : 0u;
+    rhi[j] = i < nv ? p.int_ptr[vbeg + i + 1] : 0u;
+  }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const double wsum = wave_sum(part);
   const double thresh = p.eps * (1.0 - p.c) * wsum;
@@ -253,7 +554,75 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf) {
   int64_t k = 0;
   double last = wsum;
   bool conv = true;
-  if (!(p.stop == PR_STOP_CERT_L1 && wsum == 0.0)) {
+  if (staged && nv <= 64 && !(p.stop == PR_STOP_CERT_L1 && wsum == 0.0)) {
+    // one row per lane; its first 16 sources packed in registers (entry 255
+    // of the term buffers is a zero pad for lanes with fewer sources)
+    conv = false;
+    const bool act = lane < nv;
+    const uint32_t lo = act ? lptr[lane] : 0u, hi = act ? lptr[lane + 1] : 0u;
+    const uint32_t deg = hi - lo;
+    uint32_t pk[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if ((uint32_t)q < deg) {
+        const uint32_t sh = 8u * (q & 3);
+        pk[q >> 2] = (pk[q >> 2] & ~(0xffu << sh)) | ((uint32_t)lsrc[lo + q] << sh);
+      }
+    }
+    const int nq = (int)wave_max((double)(deg < 16u ? deg : 16u));  // wave-uniform
+    const bool extra = wave_max((double)deg) > 16.0;
+    if (lane == 0) {
+      ya[kSmallMax - 1] = (YT)0;
+      yb[kSmallMax - 1] = (YT)0;
+    }
+    const double inv64 = act ? p.inv64[vbeg + lane] : 0.0;
+    const bool cert = p.stop == PR_STOP_CERT_L1;
+    double R0 = Rj[0];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    while (k < p.max_iter) {
+      ++k;
+      YT a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        if (q < nq) {
+          const YT val = ya[(pk[q >> 2] >> (8u * (q & 3))) & 0xffu];
+          if ((q & 3) == 0) a0 += val;
+          else if ((q & 3) == 1) a1 += val;
+          else if ((q & 3) == 2) a2 += val;
+          else a3 += val;
+        }
+      }
+      if (extra)
+        for (uint32_t e = lo + 16; e < hi; ++e) a0 += ya[lsrc[e]];
+      const YT sv = (a0 + a1) + (a2 + a3);
+      if (act) {
+        R0 += (double)sv;
+        if constexpr (sizeof(YT) == 8) yb[lane] = cy * sv * inv64;
+        else yb[lane] = cy * sv * inv[0];
+      }
+      const double sd = act ? (double)sv : 0.0;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      YT* t = ya;
+      ya = yb;
+      yb = t;
+      if (cert) {
+        const double norm = wave_sum(sd);
+        last = norm;
+        if (norm <= thresh) {
+          conv = true;
+          break;
+        }
+      } else {
+        const double mx = wave_max(sd);
+        last = wave_sum(sd);
+        if (mx < p.tol) {
+          conv = true;
+          break;
+        }
+      }
+    }
+    Rj[0] = R0;
+  } else if (!(p.stop == PR_STOP_CERT_L1 && wsum == 0.0)) {
     conv = false;
     while (k < p.max_iter) {
       ++k;
@@ -263,11 +632,26 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf) {
       for (int j = 0; j < 4; ++j) {
         const int i = lane + 64 * j;
         if (i < nv) {
-          const int v = vbeg + i;
-          YT s = 0;
-          for (uint32_t e = p.int_ptr[v]; e < p.int_ptr[v + 1]; ++e) s += ya[p.int_src[e] - vbeg];
+          YT s0 = 0, s1 = 0;
+          if (staged) {
+            const uint32_t lo = lptr[i], hi = lptr[i + 1];
+            uint32_t e = lo;
+            for (; e + 1 < hi; e += 2) {
+              s0 += ya[lsrc[e]];
+              s1 += ya[lsrc[e + 1]];
+            }
+            if (e < hi) s0 += ya[lsrc[e]];
+          } else {
+            uint32_t e = rlo[j];
+            for (; e + 1 < rhi[j]; e += 2) {
+              s0 += ya[p.int_src[e] - vbeg];
+              s1 += ya[p.int_src[e + 1] - vbeg];
+            }
+            if (e < rhi[j]) s0 += ya[p.int_src[e] - vbeg];
+          }
+          const YT s = s0 + s1;
           Rj[j] += (double)s;
-          if constexpr (sizeof(YT) == 8) yb[i] = cy * s * p.inv64[v];
+          if constexpr (sizeof(YT) == 8) yb[i] = cy * s * p.inv64[vbeg + i];
           else yb[i] = cy * s * inv[j];
           part += (double)s;
           pm = fmax(pm, (double)s);
@@ -295,93 +679,45 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf) {
       st_x(p.x, v, p.c * Rj[j] * p.inv64[v]);
     }
   }
-  if (lane == 0) {
-    p.iters[rank] = (int32_t)k;
-    p.lastnorm[rank] = last;
-    const uint32_t ne = p.int_ptr[vbeg + nv] - p.int_ptr[vbeg];
-    atomicAdd(&p.counters[C_EDGE_ITERS], (unsigned long long)k * ne);
-    atomicMax(&p.counters[C_ITERS_MAX], (unsigned long long)k);
-    atomicAdd(&p.counters[C_ITERS_SUM], (unsigned long long)k);
-    atomicAdd(&p.counters[C_N_ITERATED], 1ull);
-    if (!conv) atomicAdd(&p.counters[C_NOT_CONV], 1ull);
-  }
+  if (lane == 0) record_scc(p, rank, k, last, conv, ne, (uint64_t)nv, wst, true);
 }
 
-struct TeamLds {
-  double red[4];
-  unsigned long long acc, mx;
-  int flag;
-};
-
-// Barrier of generation `gen` among the T workgroups of a team; adds this
-// member's fixed-point partial norm and max, returns the team totals.
-__device__ void team_barrier(const SolveParams& p, TeamSync* ts, int member, int T, unsigned gen,
-                             unsigned long long add, unsigned long long mx, TeamLds* L) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int slot = (int)(gen % 3u);
-    if (add) atomicAdd(&ts->acc[slot], add);
-    if (mx) atomicMax(&ts->mx[slot], mx);
-    if (member == 0) {
-      const int nxt = (int)((gen + 1u) % 3u);
-      __hip_atomic_store(&ts->acc[nxt], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ts->mx[nxt], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __threadfence();
-    atomicAdd(&ts->count, 1ull);
-    const unsigned long long target = (unsigned long long)gen * (unsigned long long)T;
-    const unsigned long long t0 = wall_clock64();
-    bool bad = false;
-    while (ld_u64(&ts->count) < target) {
-      if (timed_out(p, t0)) {
-        bad = true;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    __threadfence();
-    L->acc = ld_u64(&ts->acc[slot]);
-    L->mx = ld_u64(&ts->mx[slot]);
-    L->flag = bad ? 1 : 0;
-  }
-  __syncthreads();
-}
-
-// One member of a team iterating SCC rows [vbeg, vend) (or the whole graph
-// for method PLAIN).  LPR lanes share one row of the product.
-template <typename YT, int LPR>
-__device__ void run_team(const SolveParams& p, const TeamDesc& td, int member, TeamLds* L) {
-  const int T = td.size;
+// One SCC iterated by one workgroup.  When the component fits, its rows
+// (two-byte local sources), 1/outdeg, R and both term vectors live in LDS
+// during the iteration; otherwise the vectors stay in global memory, touched
+// only by this workgroup.
+template <typename YT, int RPW>
+__device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned long long* wst, WaveTile* tiles,
+                           unsigned char* raw, size_t raw_bytes) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int sub = lane % LPR, grp = lane / LPR;
-  constexpr int RPW = 64 / LPR;
+  WaveTile* tile = tiles + wave;
   const uint32_t* ptr = p.int_ptr;
   const int32_t* src = p.int_src;
-  // nnz-balanced slice of the rows (edges plus one per row)
-  const int vb = td.vbeg, ve = td.vend;
-  const int64_t e0 = ptr[vb];
-  const int64_t total = (int64_t)(ptr[ve] - ptr[vb]) + (ve - vb);
+  const int vb = p.comp_vbeg[rank], ve = p.comp_vbeg[rank + 1];
+  const int nv = ve - vb;
+  const uint32_t eb = ptr[vb];
+  const uint32_t ne = ptr[ve] - eb;
+  const int64_t total = (int64_t)ne + nv;
   auto find_row = [&](int64_t target) {
     int lo = vb, hi = ve;
     while (lo < hi) {
       int mid = lo + (hi - lo) / 2;
-      if ((int64_t)(ptr[mid] - e0) + (mid - vb) < target) lo = mid + 1;
+      if ((int64_t)(ptr[mid] - eb) + (mid - vb) < target) lo = mid + 1;
       else hi = mid;
     }
     return lo;
   };
-  const int r0 = member == 0 ? vb : find_row(total * member / T);
-  const int r1 = member == T - 1 ? ve : find_row(total * (member + 1) / T);
+  const int w0 = wave == 0 ? vb : find_row(total * wave / kWaves);
+  const int w1 = wave == kWaves - 1 ? ve : find_row(total * (wave + 1) / kWaves);
   YT* ya = (YT*)p.y0;
   YT* yb = (YT*)p.y1;
   const double c = p.c;
-  // phase 0: weights raised by the rank flowing in (eq. PR:levels)
   double part = 0.0;
-  for (int base = r0 + wave * RPW; base < r1; base += kWaves * RPW) {
-    const int v = base + grp;
-    const bool act = v < r1;
-    double wp = p.plain ? 0.0 : gather_between<LPR>(p, v, act, sub);
-    if (act && sub == 0) {
+  for (int ra = w0; ra < w1; ra += 64) {
+    const int nr = w1 - ra < 64 ? w1 - ra : 64;
+    double wp = wave_tile_gather<64, double, true>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile);
+    if (lane < nr) {
+      const int v = ra + lane;
       wp += p.W[p.perm[v]];
       p.R[v] = wp;
       p.wprime[v] = wp;
@@ -390,126 +726,365 @@ __device__ void run_team(const SolveParams& p, const TeamDesc& td, int member, T
       part += wp;
     }
   }
-  double wsum;
-  TeamSync* ts = p.tsync + td.sync;
-  if (T == 1) {
-    wsum = block_sum(part, L->red);
-  } else {
-    part = block_sum(part, L->red);
-    if (threadIdx.x == 0) p.tpartial[td.poff + member] = part;
-    team_barrier(p, ts, member, T, 1u, 0ull, 0ull, L);
-    double s = 0.0;
-    for (int j = threadIdx.x; j < T; j += kThreads)
-      s += __hip_atomic_load(p.tpartial + td.poff + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    wsum = block_sum(s, L->red);
-  }
+  const double wsum = block_sum(part, red);  // also orders the phase-0 writes
   const double thresh = p.eps * (1.0 - c) * wsum;
-  const double scale = wsum > 0.0 ? 2305843009213693952.0 / wsum : 0.0;  // 2^61 / wsum
   const YT cy = (YT)c;
   int64_t k = 0;
   double last = wsum;
   bool conv = true;
-  unsigned gen = 1;
-  if (!(p.stop == PR_STOP_CERT_L1 && wsum == 0.0)) {
-    conv = false;
-    while (k < p.max_iter) {
-      ++k;
-      part = 0.0;
-      double pm = 0.0;
-      for (int base = r0 + wave * RPW; base < r1; base += kWaves * RPW) {
-        const int v = base + grp;
-        const bool act = v < r1;
-        YT s = 0;
-        if (act) {
-          const uint32_t hi = ptr[v + 1];
-          for (uint32_t e = ptr[v] + sub; e < hi; e += LPR) s += ya[src[e]];
+  const unsigned long long t_it = wall_clock64();
+  // LDS layout when staged: R (double) | y0 | y1 | inv (float) | ptr (u32, nv+1) | src (u16)
+  const size_t need = (size_t)nv * (8 + 2 * sizeof(YT) + 4) + 4 * (size_t)(nv + 1) + 2 * (size_t)ne + 64;
+  const bool staged = need <= raw_bytes && nv <= 65535;
+  if (staged) {
+    double* lR = reinterpret_cast<double*>(raw);
+    YT* l0 = reinterpret_cast<YT*>(lR + nv);
+    YT* l1 = l0 + nv;
+    float* linv = reinterpret_cast<float*>(l1 + nv);
+    uint32_t* lptr = reinterpret_cast<uint32_t*>(linv + nv);
+    uint16_t* lsrc = reinterpret_cast<uint16_t*>(lptr + nv + 1);
+    for (int q = threadIdx.x; q < nv; q += kThreads) {
+      lR[q] = p.R[vb + q];
+      l0[q] = ya[vb + q];
+      linv[q] = p.inv32[vb + q];
+    }
+    for (int q = threadIdx.x; q <= nv; q += kThreads) lptr[q] = ptr[vb + q] - eb;
+    for (uint32_t q = threadIdx.x; q < ne; q += kThreads) lsrc[q] = (uint16_t)(src[eb + q] - vb);
+    __syncthreads();
+    YT* la = l0;
+    YT* lb = l1;
+    if (!(p.stop == PR_STOP_CERT_L1 && wsum == 0.0)) {
+      conv = false;
+      while (k < p.max_iter) {
+        ++k;
+        part = 0.0;
+        double pm = 0.0;
+        for (int r = threadIdx.x; r < nv; r += kThreads) {
+          const uint32_t lo = lptr[r], hi = lptr[r + 1];
+          YT s0 = 0, s1 = 0;
+          uint32_t e = lo;
+          for (; e + 1 < hi; e += 2) {
+            s0 += la[lsrc[e]];
+            s1 += la[lsrc[e + 1]];
+          }
+          if (e < hi) s0 += la[lsrc[e]];
+          const YT s = s0 + s1;
+          lR[r] += (double)s;
+          if constexpr (sizeof(YT) == 8) lb[r] = cy * s * p.inv64[vb + r];
+          else lb[r] = cy * s * linv[r];
+          part += (double)s;
+          pm = fmax(pm, (double)s);
         }
-        s = group_sum<LPR>(s);
-        if (act && sub == 0) {
+        double norm, mx;
+        block_sum_max(part, pm, red, (int)(k & 1), &norm, &mx);  // the barrier also publishes lb
+        last = norm;
+        YT* tt = la;
+        la = lb;
+        lb = tt;
+        if (stop_now(p, norm, mx, thresh)) {
+          conv = true;
+          break;
+        }
+      }
+    }
+    for (int q = threadIdx.x; q < nv; q += kThreads) {
+      const double r = lR[q];
+      p.Rout[p.perm[vb + q]] = r;
+      st_x(p.x, vb + q, c * r * p.inv64[vb + q]);
+    }
+  } else {
+    if (!(p.stop == PR_STOP_CERT_L1 && wsum == 0.0)) {
+      conv = false;
+      while (k < p.max_iter) {
+        ++k;
+        part = 0.0;
+        double pm = 0.0;
+        for (int ra = w0; ra < w1; ra += 64) {
+          const int nr = w1 - ra < 64 ? w1 - ra : 64;
+          const YT s = wave_tile_gather<RPW, YT, false>(p, ptr, src, ya, ra, nr, tile);
+          if (lane < nr) {
+            const int v = ra + lane;
+            p.R[v] += (double)s;
+            if constexpr (sizeof(YT) == 8) yb[v] = cy * s * p.inv64[v];
+            else yb[v] = cy * s * p.inv32[v];
+            part += (double)s;
+            pm = fmax(pm, (double)s);
+          }
+        }
+        double norm, mx;
+        block_sum_max(part, pm, red, (int)(k & 1), &norm, &mx);  // the barrier also publishes yb
+        last = norm;
+        YT* tt = ya;
+        ya = yb;
+        yb = tt;
+        if (stop_now(p, norm, mx, thresh)) {
+          conv = true;
+          break;
+        }
+      }
+    }
+    for (int v = w0 + lane; v < w1; v += 64) {
+      const double r = p.R[v];
+      p.Rout[p.perm[v]] = r;
+      st_x(p.x, v, c * r * p.inv64[v]);
+    }
+  }
+  if (threadIdx.x == 0) {
+    wst[S_T_MEDIUM_ITER] += wall_clock64() - t_it;
+    record_scc(p, rank, k, last, conv, ne, (uint64_t)nv, wst, false);
+  }
+}
+
+__device__ inline void flush_stats(const SolveParams& p, unsigned long long* s_stats) {
+  __syncthreads();
+  if (threadIdx.x < kWgStats) {
+    unsigned long long* g = p.wgstats + (size_t)blockIdx.x * kWgStats + threadIdx.x;
+    const unsigned long long v = s_stats[threadIdx.x];
+    *g = threadIdx.x == S_ITERS_MAX ? (v > *g ? v : *g) : *g + v;
+  }
+}
+
+// LDS of the segment kernel: four wavefront tiles followed by the small-SCC
+// term vectors; a single-workgroup SCC may reuse all of it once its weights
+// are gathered, and a vertex item keeps its local x values in the second part.
+constexpr size_t kSegLds = 40 * 1024;
+static_assert(kWaves * sizeof(WaveTile) + kWaves * 2 * kSmallMax * sizeof(double) <= kSegLds, "segment LDS");
+
+// Persistent segment kernel.  Items are handed out in plan order by one
+// atomic counter per segment (one atomic per item).  This cannot deadlock,
+// whatever the number of resident workgroups: an item only waits for items
+// handed out before it, and those are held by running workgroups; the
+// lowest unfinished item has nothing left to wait for.
+template <typename YT, int RPW>
+__global__ __launch_bounds__(kThreads) void k_segment(SolveParams p) {
+  __shared__ double s_red[16];
+  __shared__ __attribute__((aligned(16))) unsigned char s_raw[kSegLds];
+  __shared__ unsigned long long s_stats[kWgStats];
+  WaveTile* tiles = reinterpret_cast<WaveTile*>(s_raw);
+  unsigned char* second = s_raw + kWaves * sizeof(WaveTile);
+  const int wave = threadIdx.x >> 6;
+  if (threadIdx.x < kWgStats) s_stats[threadIdx.x] = 0ull;
+  if ((threadIdx.x & 63) == 0) tiles[wave].wst = s_stats;
+  __syncthreads();
+  const unsigned long long t_k = wall_clock64();
+  __shared__ int s_next;
+  while (true) {
+    if (threadIdx.x == 0) s_next = (int)atomicAdd(p.seg_head, 1u);
+    __syncthreads();
+    const int i = s_next;
+    if (i >= p.n_items) break;
+    const Item it = p.items[i];
+    const unsigned long long t_i = wall_clock64();
+    if (p.trace && threadIdx.x == 0) {
+      p.trace[4 * (size_t)(p.item_base + i)] = blockIdx.x;
+      p.trace[4 * (size_t)(p.item_base + i) + 1] = t_i;
+    }
+    int slot;
+    if (it.kind == ITEM_VERTS) {
+      double* xl = reinterpret_cast<double*>(second);
+      xl[threadIdx.x] = -1.0;
+      __syncthreads();
+      run_verts(p, it.a, it.b, &tiles[wave], xl);
+      slot = S_T_VERTS;
+    } else if (it.kind == ITEM_SMALL) {
+      const int r = it.a + wave;
+      YT* ybuf = reinterpret_cast<YT*>(second) + (size_t)wave * 2 * kSmallMax;
+      if (r < it.b) run_small<YT>(p, r, ybuf, s_stats, &tiles[wave]);
+      slot = S_T_SMALL;
+    } else {
+      run_medium<YT, RPW>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
+      slot = S_T_MEDIUM;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long t_e = wall_clock64();
+      s_stats[slot] += t_e - t_i;
+      if (p.trace) p.trace[4 * (size_t)(p.item_base + i) + 2] = t_e;
+    }
+    if ((threadIdx.x & 63) == 0) tiles[wave].wst = s_stats;  // a staged SCC may have overwritten it
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s_stats[S_T_SEGMENT] += wall_clock64() - t_k;
+  flush_stats(p, s_stats);
+}
+
+// ------------------------------------------------------------- gang phases
+// Launch k = 0 raises the weights of the gang's rows (eq. PR:levels) and
+// stores the first term; launch k >= 1 first decides, from the partial norms
+// written by launch k-1, whether each SCC stopped after term k-1 (then its
+// rows are finalised and it is skipped), and otherwise adds term k.  Every
+// workgroup combines the same partials in the same order, so all reach the
+// same decision.  No workgroup waits for another inside a launch.
+
+struct GangCtx {
+  int r0, r1;     // this workgroup's rows
+  int s_lo, s_hi; // gang SCCs intersecting them
+};
+
+__device__ inline GangCtx gang_ctx(const SolveParams& p, const GangDesc& gd) {
+  GangCtx g;
+  g.r0 = p.gbounds[gd.boff + blockIdx.x];
+  g.r1 = p.gbounds[gd.boff + blockIdx.x + 1];
+  // first SCC with vend > r0
+  int lo = gd.s0, hi = gd.s1;
+  while (lo < hi) {
+    int mid = lo + (hi - lo) / 2;
+    if (p.gscc[mid].vend <= g.r0) lo = mid + 1;
+    else hi = mid;
+  }
+  g.s_lo = lo;
+  int e = lo;
+  while (e < gd.s1 && p.gscc[e].vbeg < g.r1) ++e;
+  g.s_hi = e;
+  return g;
+}
+
+// deterministic sum (and max) of an SCC's partials from launch `parity`
+__device__ inline void gang_total(const SolveParams& p, const GangScc& sc, int parity, double* red, double* tot,
+                                  double* mx) {
+  const int cnt = sc.wg_last - sc.wg_first + 1;
+  const double* pp = p.gpart + (size_t)parity * p.n_gslots + sc.pbase;
+  const double* pm = p.gpmx + (size_t)parity * p.n_gslots + sc.pbase;
+  double s = 0.0, m = 0.0;
+  for (int j = threadIdx.x; j < cnt; j += kThreads) {
+    s += pp[j];
+    m = fmax(m, pm[j]);
+  }
+  *tot = block_sum(s, red);
+  *mx = block_max(m, red);
+}
+
+__device__ inline void gang_finalise(const SolveParams& p, const GangScc& sc, const GangCtx& g, int64_t iters,
+                                     double last, bool conv, unsigned long long* wst) {
+  const int a = sc.vbeg > g.r0 ? sc.vbeg : g.r0, z = sc.vend < g.r1 ? sc.vend : g.r1;
+  for (int v = a + (int)threadIdx.x; v < z; v += kThreads) {
+    const double r = p.R[v];
+    p.Rout[p.perm[v]] = r;
+    if (!p.plain) st_x(p.x, v, p.c * r * p.inv64[v]);
+  }
+  if (blockIdx.x == sc.wg_first && threadIdx.x == 0) {
+    p.gdone[sc.gidx] = (int32_t)iters;
+    if (sc.rank >= 0) {
+      p.iters[sc.rank] = (int32_t)iters;
+      p.lastnorm[sc.rank] = last;
+    } else {
+      p.lastnorm[0] = last;
+    }
+    const uint64_t ne = p.int_ptr[sc.vend] - p.int_ptr[sc.vbeg];
+    wst[S_EDGE_ITERS] += (unsigned long long)iters * ne;
+    wst[S_VERT_ITERS] += (unsigned long long)iters * (unsigned long long)(sc.vend - sc.vbeg);
+    if ((unsigned long long)iters > wst[S_ITERS_MAX]) wst[S_ITERS_MAX] = (unsigned long long)iters;
+    wst[S_ITERS_SUM] += (unsigned long long)iters;
+    wst[S_N_ITERATED] += 1ull;
+    if (!conv) wst[S_NOT_CONV] += 1ull;
+  }
+}
+
+template <typename YT, int RPW>
+__global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int k, int final_launch) {
+  __shared__ double s_red[4];
+  __shared__ WaveTile s_tile[kWaves];
+  __shared__ unsigned long long s_stats[kWgStats];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < kWgStats) s_stats[threadIdx.x] = 0ull;
+  if (lane == 0) s_tile[wave].wst = s_stats;
+  __syncthreads();
+  const unsigned long long t_k = wall_clock64();
+  const GangDesc gd = p.gangs[gang];
+  const GangCtx g = gang_ctx(p, gd);
+  const double c = p.c;
+  YT* yr = (YT*)((k & 1) ? p.y0 : p.y1);  // term k-1
+  YT* yw = (YT*)((k & 1) ? p.y1 : p.y0);  // term k
+  const int par_w = k & 1, par_r = (k + 1) & 1;
+  for (int si = g.s_lo; si < g.s_hi; ++si) {
+    const GangScc sc = p.gscc[si];
+    // skip SCCs finalised in an earlier launch; gdone holds the number of
+    // terms, so the launch that detected the stop is gdone + 1 (the SCC is
+    // finalised by every covering workgroup in that same launch)
+    const int32_t done_terms = k > 0 ? p.gdone[si] : -1;
+    if (done_terms >= 0 && done_terms + 1 < k) continue;
+    const int a = sc.vbeg > g.r0 ? sc.vbeg : g.r0, z = sc.vend < g.r1 ? sc.vend : g.r1;
+    // split this workgroup's rows of the SCC between its wavefronts by edges
+    const uint32_t* ptr = p.int_ptr;
+    const int64_t tot_w = (int64_t)(ptr[z] - ptr[a]) + (z - a);
+    auto find_row = [&](int64_t target) {
+      int lo = a, hi = z;
+      while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        if ((int64_t)(ptr[mid] - ptr[a]) + (mid - a) < target) lo = mid + 1;
+        else hi = mid;
+      }
+      return lo;
+    };
+    const int w0 = wave == 0 ? a : find_row(tot_w * wave / kWaves);
+    const int w1 = wave == kWaves - 1 ? z : find_row(tot_w * (wave + 1) / kWaves);
+    double part = 0.0, pm = 0.0;
+    if (k == 0) {
+      for (int ra = w0; ra < w1; ra += 64) {
+        const int nr = w1 - ra < 64 ? w1 - ra : 64;
+        double wp = p.plain ? 0.0 : wave_tile_gather<64, double, false>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr,
+                                                                         &s_tile[wave]);
+        if (lane < nr) {
+          const int v = ra + lane;
+          wp += p.W[p.perm[v]];
+          p.R[v] = wp;
+          p.wprime[v] = wp;
+          if constexpr (sizeof(YT) == 8) yw[v] = c * wp * p.inv64[v];
+          else yw[v] = (YT)(c * wp * (double)p.inv32[v]);
+          part += wp;
+        }
+      }
+    } else {
+      double tot, mx;
+      gang_total(p, sc, par_r, s_red, &tot, &mx);
+      double wsum;
+      if (k == 1) {
+        wsum = tot;
+        if (blockIdx.x == sc.wg_first && threadIdx.x == 0) p.gwsum[si] = wsum;
+      } else {
+        wsum = p.gwsum[si];
+      }
+      const double thresh = p.eps * (1.0 - c) * wsum;
+      bool stop;
+      if (k == 1) stop = (p.stop == PR_STOP_CERT_L1 && wsum == 0.0);
+      else stop = stop_now(p, tot, mx, thresh);
+      if (stop || final_launch) {
+        gang_finalise(p, sc, g, k - 1, k == 1 ? wsum : tot, stop, s_stats);
+        continue;
+      }
+      const YT cy = (YT)c;
+      for (int ra = w0; ra < w1; ra += 64) {
+        const int nr = w1 - ra < 64 ? w1 - ra : 64;
+        const YT s = wave_tile_gather<RPW, YT, false>(p, ptr, p.int_src, yr, ra, nr, &s_tile[wave]);
+        if (lane < nr) {
+          const int v = ra + lane;
           p.R[v] += (double)s;
-          if constexpr (sizeof(YT) == 8) yb[v] = cy * s * p.inv64[v];
-          else yb[v] = cy * s * p.inv32[v];
+          if constexpr (sizeof(YT) == 8) yw[v] = cy * s * p.inv64[v];
+          else yw[v] = cy * s * p.inv32[v];
           part += (double)s;
           pm = fmax(pm, (double)s);
         }
       }
-      double norm, mx;
-      if (T == 1) {
-        norm = block_sum(part, L->red);
-        mx = block_max(pm, L->red);
-      } else {
-        part = block_sum(part, L->red);
-        pm = block_max(pm, L->red);
-        const unsigned long long fx = (unsigned long long)(part * scale);
-        ++gen;
-        team_barrier(p, ts, member, T, gen, fx, (unsigned long long)__double_as_longlong(pm), L);
-        norm = scale > 0.0 ? (double)L->acc / scale : 0.0;
-        mx = __longlong_as_double((long long)L->mx);
-        if (L->flag) break;  // the grid gave up; results are reported as an error
-      }
-      last = norm;
-      YT* t = ya;
-      ya = yb;
-      yb = t;
-      if (stop_now(p, norm, mx, thresh)) {
-        conv = true;
-        break;
-      }
     }
-  }
-  // results: R in the caller's order, x for the levels below
-  for (int v = r0 + (int)threadIdx.x; v < r1; v += kThreads) {
-    const double r = p.R[v];
-    p.Rout[p.perm[v]] = r;
-    if (!p.plain) st_x(p.x, v, c * r * p.inv64[v]);
-  }
-  if (member == 0 && threadIdx.x == 0) {
-    if (td.rank >= 0) {
-      p.iters[td.rank] = (int32_t)k;
-      p.lastnorm[td.rank] = last;
-    } else {
-      p.lastnorm[0] = last;
-    }
-    const uint64_t ne = ptr[ve] - ptr[vb];
-    atomicAdd(&p.counters[C_EDGE_ITERS], (unsigned long long)k * ne);
-    atomicMax(&p.counters[C_ITERS_MAX], (unsigned long long)k);
-    atomicAdd(&p.counters[C_ITERS_SUM], (unsigned long long)k);
-    atomicAdd(&p.counters[C_N_ITERATED], 1ull);
-    if (!conv) atomicAdd(&p.counters[C_NOT_CONV], 1ull);
-  }
-}
-
-template <typename YT, int LPR>
-__global__ __launch_bounds__(kThreads) void k_solve(SolveParams p) {
-  __shared__ Item s_item;
-  __shared__ TeamLds s_team;
-  __shared__ YT s_y[kWaves][2 * kSmallMax];
-  const int wave = threadIdx.x >> 6;
-  while (true) {
+    part = block_sum(part, s_red);
+    pm = block_max(pm, s_red);
     if (threadIdx.x == 0) {
-      const unsigned i = atomicAdd((unsigned*)&p.counters[C_HEAD], 1u);
-      s_item = (int)i < p.n_items ? p.items[i] : Item{-1, 0, 0, 0};
+      const size_t slot = (size_t)par_w * p.n_gslots + sc.pbase + (blockIdx.x - sc.wg_first);
+      p.gpart[slot] = part;
+      p.gpmx[slot] = pm;
     }
-    __syncthreads();
-    const Item it = s_item;
-    __syncthreads();
-    if (it.kind < 0) break;
-    if (it.kind == ITEM_VERTS) {
-      run_verts(p, it.a, it.b);
-    } else if (it.kind == ITEM_SMALL) {
-      const int r = it.a + wave;
-      if (r < it.b) run_small<YT>(p, r, s_y[wave]);
-    } else {
-      const TeamDesc td = p.teams[it.a];
-      run_team<YT, LPR>(p, td, it.b, &s_team);
-    }
-    __syncthreads();
   }
+  if (threadIdx.x == 0) {
+    s_stats[S_T_GANG] += wall_clock64() - t_k;
+    s_stats[S_N_GANG] += 1;
+  }
+  flush_stats(p, s_stats);
 }
 
 // ------------------------------------------------------------ setup kernels
 
-__global__ void k_init(SolveParams p, int64_t K, int64_t n_sync, int64_t n_part) {
+__global__ void k_init(SolveParams p, int64_t K, int64_t n_gscc, int64_t n_stats, unsigned* seg_heads,
+                       int64_t n_heads) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = tid; i < p.n; i += stride) {
@@ -521,10 +1096,12 @@ __global__ void k_init(SolveParams p, int64_t K, int64_t n_sync, int64_t n_part)
     p.iters[i] = 0;
     p.lastnorm[i] = 0.0;
   }
-  unsigned* ts = (unsigned*)p.tsync;
-  const int64_t nts = n_sync * (int64_t)(sizeof(TeamSync) / sizeof(unsigned));
-  for (int64_t i = tid; i < nts; i += stride) ts[i] = 0u;
-  for (int64_t i = tid; i < n_part; i += stride) p.tpartial[i] = 0.0;
+  for (int64_t i = tid; i < n_gscc; i += stride) {
+    p.gdone[i] = -1;
+    p.gwsum[i] = 0.0;
+  }
+  for (int64_t i = tid; i < n_stats; i += stride) p.wgstats[i] = 0ull;
+  for (int64_t i = tid; i < n_heads; i += stride) seg_heads[i] = 0u;
 }
 
 __global__ void k_zero_counters(unsigned long long* c) {
@@ -549,7 +1126,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce1(const double* a, int64_t n
     part[2 * blockIdx.x + 1] = sb;
   }
 }
-__global__ __launch_bounds__(kThreads) void k_reduce2(const double* part, double* out) {
+__global__ __launch_bounds__(kThreads) void k_reduce2(const double* part, double* out,
+                                                      const unsigned long long* wgstats, int G,
+                                                      unsigned long long* counters) {
   __shared__ double lds[4];
   double sa = part[2 * threadIdx.x], sb = part[2 * threadIdx.x + 1];
   sa = block_sum(sa, lds);
@@ -557,6 +1136,14 @@ __global__ __launch_bounds__(kThreads) void k_reduce2(const double* part, double
   if (threadIdx.x == 0) {
     out[0] = sa;
     out[1] = sb;
+  }
+  if (threadIdx.x < kWgStats) {
+    unsigned long long acc = 0;
+    for (int g = 0; g < G; ++g) {
+      const unsigned long long v = wgstats[(size_t)g * kWgStats + threadIdx.x];
+      acc = threadIdx.x == S_ITERS_MAX ? (v > acc ? v : acc) : acc + v;
+    }
+    counters[threadIdx.x] = acc;
   }
 }
 
@@ -570,23 +1157,32 @@ int32_t dalloc(T** p, size_t count) {
   return PR_OK;
 }
 
-using KernelFn = void (*)(SolveParams);
+using SegFn = void (*)(SolveParams);
+using GangFn = void (*)(SolveParams, int, int, int);
 
-KernelFn pick_kernel(int precision, int lpr) {
-  if (precision == PR_PREC_FP64) {
-    switch (lpr) {
-      case 64: return k_solve<double, 64>;
-      case 16: return k_solve<double, 16>;
-      case 4: return k_solve<double, 4>;
-      default: return k_solve<double, 1>;
-    }
+template <typename YT>
+SegFn seg_kernel(int rpw) {
+  switch (rpw) {
+    case 64: return k_segment<YT, 64>;
+    case 16: return k_segment<YT, 16>;
+    case 4: return k_segment<YT, 4>;
+    default: return k_segment<YT, 1>;
   }
-  switch (lpr) {
-    case 64: return k_solve<float, 64>;
-    case 16: return k_solve<float, 16>;
-    case 4: return k_solve<float, 4>;
-    default: return k_solve<float, 1>;
+}
+template <typename YT>
+GangFn gang_kernel(int rpw) {
+  switch (rpw) {
+    case 64: return k_gang<YT, 64>;
+    case 16: return k_gang<YT, 16>;
+    case 4: return k_gang<YT, 4>;
+    default: return k_gang<YT, 1>;
   }
+}
+SegFn pick_segment(int precision, int rpw) {
+  return precision == PR_PREC_FP64 ? seg_kernel<double>(rpw) : seg_kernel<float>(rpw);
+}
+GangFn pick_gang(int precision, int rpw) {
+  return precision == PR_PREC_FP64 ? gang_kernel<double>(rpw) : gang_kernel<float>(rpw);
 }
 
 }  // namespace
@@ -597,116 +1193,164 @@ KernelFn pick_kernel(int precision, int lpr) {
     if (rc_ != PR_OK) return rc_; \
   } while (0)
 
-// resident workgroups of the solve kernel for one rows-per-wave choice
-static int32_t grid_for(int lpr, int* grid) {
+// launch sizes: a segment uses every workgroup slot the device keeps
+// resident; a gang launch up to eight workgroups per compute unit
+static int32_t grid_for(int rpw, int* grid, int* ggrid) {
   int dev, cus;
   PR_HIP_CHECK(hipGetDevice(&dev));
   PR_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  int best = 1 << 30;
+  int seg = 1 << 30, gang = 1 << 30;
   for (int prec = 0; prec < 2; ++prec) {
     int occ = 0;
-    PR_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pick_kernel(prec, lpr), kThreads, 0));
-    best = std::min(best, occ);
+    PR_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pick_segment(prec, rpw), kThreads, 0));
+    seg = std::min(seg, occ);
+    PR_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pick_gang(prec, rpw), kThreads, 0));
+    gang = std::min(gang, occ);
   }
-  if (best < 1) {
-    set_error("solve kernel cannot be resident (occupancy 0)");
+  if (seg < 1 || gang < 1) {
+    set_error("solve kernels cannot be resident (occupancy 0)");
     return PR_EHIP;
   }
-  const int per_cu = std::min(best, 4);
-  *grid = per_cu * cus;
+  *grid = std::min(seg, 4) * cus;
+  *ggrid = std::min(gang, 8) * cus;
   return PR_OK;
 }
 
+// edge-balanced split of rows [vb, ve) into G workgroup ranges
+static void balanced_bounds(const std::vector<uint32_t>& ptr, int vb, int ve, int G, int32_t* out) {
+  const int64_t e0 = ptr[vb];
+  const int64_t total = (int64_t)(ptr[ve] - ptr[vb]) + (ve - vb);
+  out[0] = vb;
+  out[G] = ve;
+  int r = vb;
+  for (int g = 1; g < G; ++g) {
+    const int64_t target = total * g / G;
+    while (r < ve && (int64_t)(ptr[r] - e0) + (r - vb) < target) ++r;
+    out[g] = r;
+  }
+}
+
+static void add_gang(const std::vector<uint32_t>& ptr, int G, int vb, int ve, const std::vector<int64_t>& ranks,
+                     const std::vector<int32_t>& cvbeg, std::vector<GangDesc>& gangs, std::vector<GangScc>& sccs,
+                     std::vector<int32_t>& bounds, int32_t& slots) {
+  GangDesc gd{};
+  gd.vbeg = vb;
+  gd.vend = ve;
+  gd.s0 = (int32_t)sccs.size();
+  gd.boff = (int32_t)bounds.size();
+  bounds.resize(bounds.size() + G + 1);
+  int32_t* b = bounds.data() + gd.boff;
+  balanced_bounds(ptr, vb, ve, G, b);
+  for (int64_t q : ranks) {
+    GangScc sc{};
+    sc.rank = (int32_t)q;
+    sc.vbeg = q >= 0 ? cvbeg[q] : vb;
+    sc.vend = q >= 0 ? cvbeg[q + 1] : ve;
+    int f = 0;
+    while (f < G && !(b[f + 1] > sc.vbeg && b[f] < b[f + 1])) ++f;
+    int l = f;
+    while (l + 1 < G && b[l + 1] < sc.vend) ++l;
+    sc.wg_first = f;
+    sc.wg_last = l;
+    sc.pbase = slots;
+    sc.gidx = (int32_t)sccs.size();
+    slots += l - f + 1;
+    sccs.push_back(sc);
+  }
+  gd.s1 = (int32_t)sccs.size();
+  gangs.push_back(gd);
+}
+
 int32_t make_schedule(Levels& lv, hipStream_t s) {
-  const int lpr = 64 / lv.opts.rows_per_wave;
-  PR_TRY(grid_for(lpr, &lv.grid));
-  const int G = lv.grid;
-  const int team_cap = std::max(1, G / 2);
+  PR_TRY(grid_for(lv.opts.rows_per_wave, &lv.grid, &lv.ggrid));
+  lv.sgrid = std::max(lv.grid, lv.ggrid);
+  const int G = lv.ggrid;  // gang row bounds are per gang workgroup
   const int64_t K = lv.n_comp;
   std::vector<Item> items;
-  std::vector<TeamDesc> teams;
-  int32_t poff = 0;
-  int64_t max_team = 0;
+  std::vector<GangDesc> gangs;
+  std::vector<GangScc> sccs;
+  std::vector<int32_t> bounds;
+  std::vector<Phase> phases;
+  int32_t slots = 0;
+  int64_t seg_start = 0;
   int64_t r = 0;
   while (r < K) {
     const int lev = lv.h_comp_level[r];
     int64_t e = r;
     while (e < K && lv.h_comp_level[e] == lev) ++e;
-    // SCCs of the level: ranks [r, sc) in size order
     int64_t sc = r;
     while (sc < e && lv.h_comp_class[sc] == 0) ++sc;
-    std::vector<int64_t> small;
+    std::vector<int64_t> small, large;
     for (int64_t q = r; q < sc; ++q) {
       const int32_t nv = lv.h_comp_vbeg[q + 1] - lv.h_comp_vbeg[q];
-      if (nv <= lv.opts.small_cutoff) {
-        small.push_back(q);
-        continue;
-      }
-      const int64_t ne = lv.h_comp_int_edges[q];
-      int T = (int)std::min<int64_t>(team_cap, std::max<int64_t>(1, (ne + lv.opts.team_edges - 1) / lv.opts.team_edges));
-      TeamDesc td{};
-      td.rank = (int32_t)q;
-      td.size = T;
-      td.vbeg = lv.h_comp_vbeg[q];
-      td.vend = lv.h_comp_vbeg[q + 1];
-      td.poff = poff;
-      td.sync = (int32_t)teams.size();
-      poff += T;
-      max_team = std::max<int64_t>(max_team, T);
-      for (int j = 0; j < T; ++j) items.push_back(Item{ITEM_TEAM, (int32_t)teams.size(), j, T});
-      teams.push_back(td);
+      if (nv <= lv.opts.small_cutoff) small.push_back(q);
+      else if (lv.h_comp_int_edges[q] > lv.opts.team_edges) large.push_back(q);
+      else items.push_back(Item{ITEM_MEDIUM, (int32_t)q, 0, 0});
     }
     for (size_t i = 0; i < small.size(); i += kWaves) {
       const int64_t a = small[i];
       const int64_t b = small[std::min(small.size() - 1, i + kWaves - 1)] + 1;
       items.push_back(Item{ITEM_SMALL, (int32_t)a, (int32_t)b, 0});
     }
-    // CAC and one-vertex components of the level: one contiguous range
     if (sc < e) {
       const int32_t v0 = lv.h_comp_vbeg[sc], v1 = lv.h_comp_vbeg[e];
-      for (int32_t v = v0; v < v1; v += kThreads)
-        items.push_back(Item{ITEM_VERTS, v, std::min(v1, v + kThreads), 0});
+      for (int32_t v = v0; v < v1; v += kThreads) items.push_back(Item{ITEM_VERTS, v, std::min(v1, v + kThreads), 0});
+    }
+    if (!large.empty()) {
+      // large SCCs are adjacent in plan order (size-descending within the level)
+      if ((int64_t)items.size() > seg_start) phases.push_back(Phase{0, (int32_t)seg_start, (int32_t)items.size()});
+      seg_start = (int64_t)items.size();
+      const int vb = lv.h_comp_vbeg[large.front()], ve = lv.h_comp_vbeg[large.back() + 1];
+      phases.push_back(Phase{1, (int32_t)gangs.size(), 0});
+      add_gang(lv.h_int_ptr, G, vb, ve, large, lv.h_comp_vbeg, gangs, sccs, bounds, slots);
     }
     r = e;
   }
+  if ((int64_t)items.size() > seg_start) phases.push_back(Phase{0, (int32_t)seg_start, (int32_t)items.size()});
   lv.n_items = (int64_t)items.size();
-  lv.n_teams = (int64_t)teams.size();
-  // whole-graph team for method PLAIN: every resident workgroup
-  TeamDesc pt{};
-  pt.rank = -1;
-  pt.size = G;
-  pt.vbeg = 0;
-  pt.vend = (int32_t)lv.n;
-  pt.poff = poff;
-  pt.sync = (int32_t)teams.size();
-  std::vector<Item> pitems;
-  for (int j = 0; j < G; ++j) pitems.push_back(Item{ITEM_TEAM, 0, j, G});
+  lv.n_gangs = (int64_t)gangs.size();
+  const int64_t n_gscc_cw = (int64_t)sccs.size();
+  // the whole-graph gang of method PLAIN comes last
+  if (!lv.h_full_ptr.empty()) {
+    add_gang(lv.h_full_ptr, G, 0, (int)lv.n, std::vector<int64_t>{-1}, lv.h_comp_vbeg, gangs, sccs, bounds, slots);
+  }
+  lv.n_gscc = (int64_t)sccs.size();
+  lv.n_gslots = slots;
+  lv.phases = phases;
   // device copies
-  if (lv.items) (void)hipFree(lv.items);
-  if (lv.teams) (void)hipFree(lv.teams);
-  if (lv.plain_items) (void)hipFree(lv.plain_items);
-  if (lv.plain_team) (void)hipFree(lv.plain_team);
-  if (lv.tsync) (void)hipFree(lv.tsync);
-  if (lv.tpartial) (void)hipFree(lv.tpartial);
+  void* old[] = {lv.items, lv.gangs, lv.gsccs, lv.gbounds, lv.gpart, lv.gpmx, lv.gwsum, lv.gdone, lv.wgstats,
+                 lv.trace, lv.seg_heads};
+  for (void* q : old)
+    if (q) (void)hipFree(q);
   lv.items = nullptr;
-  lv.teams = nullptr;
-  lv.plain_items = nullptr;
-  lv.plain_team = nullptr;
-  lv.tsync = nullptr;
-  lv.tpartial = nullptr;
+  lv.gangs = nullptr;
+  lv.gsccs = nullptr;
+  lv.gbounds = nullptr;
+  lv.gpart = nullptr;
+  lv.gpmx = nullptr;
+  lv.gwsum = nullptr;
+  lv.gdone = nullptr;
+  lv.wgstats = nullptr;
+  lv.trace = nullptr;
+  lv.seg_heads = nullptr;
   PR_TRY(dalloc(&lv.items, items.size()));
-  PR_TRY(dalloc(&lv.teams, teams.size()));
-  PR_TRY(dalloc(&lv.plain_items, pitems.size()));
-  PR_TRY(dalloc(&lv.plain_team, 1));
-  PR_TRY(dalloc(&lv.tsync, teams.size() + 1));
-  PR_TRY(dalloc(&lv.tpartial, (size_t)poff + G));
+  PR_TRY(dalloc(&lv.gangs, gangs.size()));
+  PR_TRY(dalloc(&lv.gsccs, sccs.size()));
+  PR_TRY(dalloc(&lv.gbounds, bounds.size()));
+  PR_TRY(dalloc(&lv.gpart, 2 * (size_t)slots));
+  PR_TRY(dalloc(&lv.gpmx, 2 * (size_t)slots));
+  PR_TRY(dalloc(&lv.gwsum, sccs.size()));
+  PR_TRY(dalloc(&lv.gdone, sccs.size()));
+  PR_TRY(dalloc(&lv.wgstats, (size_t)lv.sgrid * kWgStats));
+  PR_TRY(dalloc(&lv.seg_heads, std::max<size_t>(phases.size(), 1)));
   if (!items.empty())
     PR_HIP_CHECK(hipMemcpyAsync(lv.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s));
-  if (!teams.empty())
-    PR_HIP_CHECK(hipMemcpyAsync(lv.teams, teams.data(), sizeof(TeamDesc) * teams.size(), hipMemcpyHostToDevice, s));
-  PR_HIP_CHECK(hipMemcpyAsync(lv.plain_items, pitems.data(), sizeof(Item) * pitems.size(), hipMemcpyHostToDevice, s));
-  PR_HIP_CHECK(hipMemcpyAsync(lv.plain_team, &pt, sizeof(TeamDesc), hipMemcpyHostToDevice, s));
-  // per-solve buffers
+  if (!gangs.empty())
+    PR_HIP_CHECK(hipMemcpyAsync(lv.gangs, gangs.data(), sizeof(GangDesc) * gangs.size(), hipMemcpyHostToDevice, s));
+  if (!sccs.empty())
+    PR_HIP_CHECK(hipMemcpyAsync(lv.gsccs, sccs.data(), sizeof(GangScc) * sccs.size(), hipMemcpyHostToDevice, s));
+  if (!bounds.empty())
+    PR_HIP_CHECK(hipMemcpyAsync(lv.gbounds, bounds.data(), sizeof(int32_t) * bounds.size(), hipMemcpyHostToDevice, s));
   const int64_t n = lv.n;
   if (!lv.x) {
     PR_TRY(dalloc(&lv.x, n));
@@ -722,12 +1366,12 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   PR_HIP_CHECK(hipStreamSynchronize(s));
   pr_levels_info& I = lv.info;
   I.n_items = lv.n_items;
-  I.n_teams = lv.n_teams;
-  I.max_team = max_team;
+  I.n_gangs = lv.n_gangs;
+  I.n_gang_scc = n_gscc_cw;
   I.rows_per_wave = lv.opts.rows_per_wave;
   I.small_cutoff = lv.opts.small_cutoff;
   I.team_edges = lv.opts.team_edges;
-  I.grid_wgs = G;
+  I.grid_wgs = lv.sgrid;
   // a new schedule invalidates a captured graph
   if (lv.graph_exec) (void)hipGraphExecDestroy(lv.graph_exec);
   if (lv.graph) (void)hipGraphDestroy(lv.graph);
@@ -740,6 +1384,23 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
 static uint64_t mix64(uint64_t h, uint64_t x) {
   h ^= x + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
   return h;
+}
+
+// number of series terms after which every SCC has met the stop rule in
+// exact arithmetic: ||P_k||_1 <= c^k ||W'_C||_1 (Sec. 3.4), plus slack for
+// rounding; the paper rule uses max(P_k) <= ||P_k||_1 and ||W'_C||_1 <= sumW/(1-c)
+static int64_t term_bound(const pr_solve_opts& o, double c, double sumW) {
+  double k;
+  if (o.stop == PR_STOP_CERT_L1) {
+    k = std::ceil(std::log(o.eps * (1.0 - c)) / std::log(c));
+  } else {
+    const double top = sumW / (1.0 - c);
+    k = top <= o.tol ? 1.0 : std::ceil(std::log(o.tol / top) / std::log(c));
+  }
+  if (!(k >= 1.0)) k = 1.0;
+  k += 8.0;
+  if (k > (double)o.max_iter) k = (double)o.max_iter;
+  return (int64_t)k;
 }
 
 int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_solve_opts& o,
@@ -762,7 +1423,6 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.n = (int32_t)lv.n;
   p.stop = o.stop;
   p.plain = plain ? 1 : 0;
-  p.n_items = plain ? lv.grid : (int32_t)lv.n_items;
   p.c = c;
   p.eps = o.eps;
   p.tol = o.tol;
@@ -781,49 +1441,90 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.wprime = lv.wprime;
   p.y0 = lv.y0;
   p.y1 = lv.y1;
-  p.items = plain ? lv.plain_items : lv.items;
-  p.teams = plain ? lv.plain_team : lv.teams;
-  p.tsync = lv.tsync;
-  p.tpartial = lv.tpartial;
   p.comp_vbeg = lv.comp_vbeg;
   p.iters = lv.iters;
   p.lastnorm = lv.lastnorm;
   p.counters = lv.counters;
+  p.wgstats = lv.wgstats;
+  p.gangs = lv.gangs;
+  p.gscc = lv.gsccs;
+  p.gbounds = lv.gbounds;
+  p.gpart = lv.gpart;
+  p.gpmx = lv.gpmx;
+  p.gwsum = lv.gwsum;
+  p.gdone = lv.gdone;
+  p.n_gslots = lv.n_gslots;
   p.timeout = (unsigned long long)clock_khz * 1000ull * 30ull;  // 30 s
+  if (o.reserved[0] == 1) {  // timeline of the segment items (tests / profiling)
+    if (!lv.trace) {
+      hipError_t e = hipMalloc(&lv.trace, sizeof(unsigned long long) * 4 * std::max<int64_t>(lv.n_items, 1));
+      if (e != hipSuccess) {
+        set_error("hipMalloc(trace) failed: %s", hipGetErrorString(e));
+        return PR_ENOMEM;
+      }
+    }
+    p.trace = lv.trace;
+  }
   const int64_t K = std::max<int64_t>(lv.n_comp, 1);
-  const int64_t n_sync = lv.n_teams + 1;
-  const int64_t n_part = 0;
   const unsigned init_blocks = (unsigned)std::min<int64_t>(4096, (lv.n + kThreads - 1) / kThreads + 1);
 
-  // the weights must be non-negative and finite (a negative x would read as
-  // "not ready"); checked before the solve kernel runs
+  // weights must be non-negative and finite (a negative x would read as "not
+  // ready"); checked, and summed for the term bound, before the solve runs
   k_zero_counters<<<1, 64, 0, s>>>(lv.counters);
-  k_init<<<init_blocks, kThreads, 0, s>>>(p, K, n_sync, n_part);
+  k_init<<<init_blocks, kThreads, 0, s>>>(p, K, lv.n_gscc, (int64_t)lv.sgrid * kWgStats, lv.seg_heads,
+                                              (int64_t)lv.phases.size());
+  k_reduce1<<<kRedBlocks, kThreads, 0, s>>>(W, lv.n, lv.lastnorm, 0, lv.red + 8);
   PR_HIP_CHECK(hipGetLastError());
   unsigned long long badw = 0;
+  std::vector<double> wparts(2 * kRedBlocks);
   PR_HIP_CHECK(hipMemcpyAsync(&badw, lv.counters + C_BAD_W, sizeof(badw), hipMemcpyDeviceToHost, s));
+  PR_HIP_CHECK(hipMemcpyAsync(wparts.data(), lv.red + 8, sizeof(double) * 2 * kRedBlocks, hipMemcpyDeviceToHost, s));
   PR_HIP_CHECK(hipStreamSynchronize(s));
   if (badw) {
     set_error("W has a negative or non-finite entry");
     return PR_EINVAL;
   }
-  const KernelFn fn = pick_kernel(o.precision, 64 / lv.opts.rows_per_wave);
+  double sumW = 0.0;
+  for (int i = 0; i < kRedBlocks; ++i) sumW += wparts[2 * i];
+  const int64_t kb = term_bound(o, c, sumW);
+  const SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave);
+  const GangFn gk = pick_gang(o.precision, lv.opts.rows_per_wave);
   hipEvent_t ev0, ev1;
   PR_HIP_CHECK(hipEventCreate(&ev0));
   PR_HIP_CHECK(hipEventCreate(&ev1));
+  auto launch_gang = [&](int gang) -> int32_t {
+    for (int64_t k = 0; k <= kb + 1; ++k) {
+      const int fin = k == kb + 1 ? 1 : 0;
+      hipLaunchKernelGGL(gk, dim3(lv.ggrid), dim3(kThreads), 0, s, p, gang, (int)k, fin);
+    }
+    return PR_OK;
+  };
   auto launch_all = [&](bool graph_mode) -> int32_t {
     if (graph_mode) {
       k_zero_counters<<<1, 64, 0, s>>>(lv.counters);
-      k_init<<<init_blocks, kThreads, 0, s>>>(p, K, n_sync, n_part);
+      k_init<<<init_blocks, kThreads, 0, s>>>(p, K, lv.n_gscc, (int64_t)lv.sgrid * kWgStats, lv.seg_heads,
+                                              (int64_t)lv.phases.size());
     }
-    void* args[] = {&p};
-    if (graph_mode) {
-      PR_HIP_CHECK(hipLaunchKernel((const void*)fn, dim3(lv.grid), dim3(kThreads), args, 0, s));
+    if (plain) {
+      PR_TRY(launch_gang((int)lv.n_gangs));  // the whole-graph gang
     } else {
-      PR_HIP_CHECK(hipLaunchCooperativeKernel((const void*)fn, dim3(lv.grid), dim3(kThreads), args, 0, s));
+      for (size_t pi = 0; pi < lv.phases.size(); ++pi) {
+        const Phase& ph = lv.phases[pi];
+        if (ph.kind == 1) {
+          PR_TRY(launch_gang(ph.a));
+        } else {
+          SolveParams q = p;
+          q.items = lv.items + ph.a;
+          q.n_items = ph.b - ph.a;
+          q.item_base = ph.a;
+          q.seg_head = lv.seg_heads + pi;
+          void* args[] = {&q};
+          PR_HIP_CHECK(hipLaunchKernel((const void*)seg, dim3(lv.grid), dim3(kThreads), args, 0, s));
+        }
+      }
     }
     k_reduce1<<<kRedBlocks, kThreads, 0, s>>>(R, lv.n, lv.lastnorm, plain ? 1 : lv.n_comp, lv.red + 8);
-    k_reduce2<<<1, kThreads, 0, s>>>(lv.red + 8, lv.red);
+    k_reduce2<<<1, kThreads, 0, s>>>(lv.red + 8, lv.red, lv.wgstats, lv.sgrid, lv.counters);
     PR_HIP_CHECK(hipGetLastError());
     return PR_OK;
   };
@@ -836,17 +1537,21 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     key = mix64(key, (uint64_t)__builtin_bit_cast(uint64_t, o.eps));
     key = mix64(key, (uint64_t)__builtin_bit_cast(uint64_t, o.tol));
     key = mix64(key, (uint64_t)o.max_iter);
+    key = mix64(key, (uint64_t)kb);
     key = mix64(key, (uint64_t)(o.stop * 16 + o.precision * 4 + o.method));
-    key = mix64(key, (uint64_t)(uintptr_t)s);
     if (!lv.graph_exec || lv.graph_key != key) {
       if (lv.graph_exec) (void)hipGraphExecDestroy(lv.graph_exec);
       if (lv.graph) (void)hipGraphDestroy(lv.graph);
       lv.graph_exec = nullptr;
       lv.graph = nullptr;
+      if (!lv.cap_stream) PR_HIP_CHECK(hipStreamCreateWithFlags(&lv.cap_stream, hipStreamNonBlocking));
+      const hipStream_t caller = s;
+      s = lv.cap_stream;
       PR_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       rc = launch_all(true);
       hipGraph_t g = nullptr;
       hipError_t ce = hipStreamEndCapture(s, &g);
+      s = caller;
       if (rc) return rc;
       if (ce != hipSuccess) {
         set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ce));
@@ -875,21 +1580,22 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   if (cnt[C_ERROR]) {
-    set_error("internal: a dependency wait or team barrier timed out (flags %llu)", cnt[C_ERROR]);
+    set_error("internal: a dependency wait timed out (flags %llu)", cnt[C_ERROR]);
     return PR_EHIP;
   }
-  local.edge_iters = (int64_t)cnt[C_EDGE_ITERS] +
-                     (plain ? 0 : (lv.info.m_between + lv.info.m_cac_internal));
-  local.iters_max = (int64_t)cnt[C_ITERS_MAX];
-  local.iters_sum = (int64_t)cnt[C_ITERS_SUM];
-  local.n_iterated = (int64_t)cnt[C_N_ITERATED];
-  local.n_not_converged = (int64_t)cnt[C_NOT_CONV];
-  local.ws_accepted = (int64_t)cnt[C_WS_ACC];
-  local.ws_rejected = (int64_t)cnt[C_WS_REJ];
+  local.edge_iters = (int64_t)cnt[S_EDGE_ITERS] + (plain ? 0 : (lv.info.m_between + lv.info.m_cac_internal));
+  local.iters_max = (int64_t)cnt[S_ITERS_MAX];
+  local.iters_sum = (int64_t)cnt[S_ITERS_SUM];
+  local.n_iterated = (int64_t)cnt[S_N_ITERATED];
+  local.n_not_converged = (int64_t)cnt[S_NOT_CONV];
+  local.ws_accepted = (int64_t)cnt[S_WS_ACC];
+  local.ws_rejected = (int64_t)cnt[S_WS_REJ];
   local.r_sum = red[0];
   local.cert_abs = c / (1.0 - c) * red[1];
   local.cert_rel = red[0] > 0.0 ? local.cert_abs / red[0] : 0.0;
   local.time_ms = ms;
+  local.kernel_ms = ms;
+  local.vert_iters = (int64_t)cnt[S_VERT_ITERS] + (plain ? 0 : (lv.n - lv.info.v_scc));
   if (st) *st = local;
   return local.n_not_converged ? PR_NOT_CONVERGED : PR_OK;
 }
@@ -928,6 +1634,26 @@ extern "C" int32_t pr_levels_debug(const pr_levels_t* lh, int32_t what, void* ho
   }
   if (what == 2) {
     if (n) PR_HIP_CHECK(hipMemcpy(host_out, lv.perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    return PR_OK;
+  }
+  if (what == 4) {  // item timeline of the last traced solve: n_items x {wg, start, end, kind}
+    if (!lv.trace) {
+      set_error("no traced solve yet");
+      return PR_EINVAL;
+    }
+    std::vector<unsigned long long> t(4 * (size_t)lv.n_items);
+    std::vector<Item> it(lv.n_items);
+    if (lv.n_items) {
+      PR_HIP_CHECK(hipMemcpy(t.data(), lv.trace, sizeof(unsigned long long) * t.size(), hipMemcpyDeviceToHost));
+      PR_HIP_CHECK(hipMemcpy(it.data(), lv.items, sizeof(Item) * it.size(), hipMemcpyDeviceToHost));
+    }
+    for (int64_t i = 0; i < lv.n_items; ++i) t[4 * i + 3] = (unsigned long long)it[i].kind;
+    memcpy(host_out, t.data(), sizeof(unsigned long long) * t.size());
+    return PR_OK;
+  }
+  if (what == 3) {  // per-workgroup counters of the last solve: grid_wgs x 16 uint64
+    PR_HIP_CHECK(hipMemcpy(host_out, lv.wgstats, sizeof(unsigned long long) * kWgStats * lv.sgrid,
+                           hipMemcpyDeviceToHost));
     return PR_OK;
   }
   set_error("unknown debug array %d", what);

@@ -156,12 +156,12 @@ def test_config1_mixed_precision(prm, c1):
     assert rc == 0 and _rel_l1(R, ref) <= 1e-6
 
 
-def test_teams_and_determinism(prm, c1):
+def test_gangs_and_determinism(prm, c1):
     pr, torch = prm
     g, W, ref = c1
     part = pr.pr_partition(g.row_ptr, g.col)
     lv = pr.pr_build_levels(part, g.row_ptr, g.col, small_cutoff=1, team_edges=100)
-    assert lv.info()["max_team"] > 1
+    assert lv.info()["n_gang_scc"] > 1
     Wd = torch.tensor(W, device="cuda")
     outs = []
     for rep in range(3):
