@@ -96,7 +96,7 @@ typedef struct pr_build_opts {
      series term); the others by one workgroup each.  0 = default. */
   int32_t team_edges;
   /* wavefront lanes given to one row in the SCC product: rows_per_wave in
-     {1, 4, 16, 64} rows share a 64-lane wavefront; 0 = default (64). */
+     {1, 4, 16, 64} rows share a 64-lane wavefront; 0 = default (16). */
   int32_t rows_per_wave;
   /* 1 = also keep the whole-graph pull CSR needed by method PLAIN. */
   int32_t build_plain;

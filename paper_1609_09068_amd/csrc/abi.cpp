@@ -128,7 +128,7 @@ void pr_default_build_opts(pr_build_opts* o) {
   memset(o, 0, sizeof(*o));
   o->small_cutoff = 64;
   o->team_edges = 65536;
-  o->rows_per_wave = 64;
+  o->rows_per_wave = 16;
   o->build_plain = 1;
   o->autotune = 0;
 }

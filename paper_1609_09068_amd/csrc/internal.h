@@ -67,14 +67,29 @@ struct GangDesc {
   int32_t vbeg, vend;   // plan rows covered (the SCCs are contiguous)
   int32_t s0, s1;       // range in the GangScc table
   int32_t boff;         // offset of the grid+1 row bounds in the bounds table
-  int32_t pad[3];
+  int32_t h0, h1;       // range in the GangHub table (sorted by row)
+  int32_t poff;         // offset of the grid+1 per-workgroup piece pointers
 };
 struct GangScc {
   int32_t rank;         // component rank (-1: whole graph)
   int32_t vbeg, vend;
   int32_t wg_first, wg_last;  // workgroups whose rows intersect the SCC
-  int32_t pbase;        // first partial-sum slot (one per covering workgroup)
+  int32_t pbase;        // first partial-sum slot: one per covering workgroup, then one per hub row
   int32_t gidx;         // index of this entry in the table
+  int32_t nslot;        // number of partial-sum slots
+};
+// A row whose in-degree exceeds the hub threshold is summed in pieces spread
+// over the gang's workgroups, then combined by a separate small launch.
+struct GangHub {
+  int32_t row;
+  int32_t scc;          // GangScc index
+  int32_t p0, p1;       // its pieces [p0, p1) in the piece table
+  int32_t slot;         // its partial-sum slot
+  int32_t pad[3];
+};
+struct GangPiece {
+  uint32_t ebeg, eend;  // edges of the hub row summed by this piece
+  int32_t hub;          // GangHub index
   int32_t pad;
 };
 
@@ -120,6 +135,13 @@ struct Levels {
   double* gpart = nullptr;        // [2 * n_gslots] partial 1-norms of the last two terms
   double* gpmx = nullptr;         // [2 * n_gslots] partial max-norms
   double* gwsum = nullptr;        // [n_gscc + 1] ||W'_C||_1 of each gang SCC
+  GangHub* ghubs = nullptr;       // hub rows of all gangs
+  GangPiece* gpieces = nullptr;   // hub pieces, grouped by workgroup within a gang
+  int32_t* gpiece_ptr = nullptr;  // per gang: grid+1 offsets into gpieces
+  int32_t* ghub_pieces = nullptr; // per hub: its piece positions in edge order
+  double* gpiece_part = nullptr;  // [n_pieces] piece sums of the current term
+  std::vector<int32_t> h_gang_nhub;  // hubs per gang (host)
+  int64_t n_ghubs = 0, n_gpieces = 0;
   int32_t* gdone = nullptr;       // [n_gscc + 1] iterations when converged, -1 while running
   std::vector<uint32_t> h_int_ptr, h_full_ptr;
   // host copies used for scheduling and stats

@@ -84,6 +84,11 @@ struct SolveParams {
   double* gpmx;
   double* gwsum;
   int32_t* gdone;
+  const GangHub* ghubs;
+  const GangPiece* gpieces;
+  const int32_t* gpiece_ptr;
+  const int32_t* ghub_pieces;
+  double* gpiece_part;
   int64_t n_gslots;
   unsigned* seg_head;          // item counter of the segment being run
   unsigned long long* trace;   // optional per-item timeline [n_items][4]
@@ -942,7 +947,7 @@ __device__ inline GangCtx gang_ctx(const SolveParams& p, const GangDesc& gd) {
 // deterministic sum (and max) of an SCC's partials from launch `parity`
 __device__ inline void gang_total(const SolveParams& p, const GangScc& sc, int parity, double* red, double* tot,
                                   double* mx) {
-  const int cnt = sc.wg_last - sc.wg_first + 1;
+  const int cnt = sc.nslot;
   const double* pp = p.gpart + (size_t)parity * p.n_gslots + sc.pbase;
   const double* pm = p.gpmx + (size_t)parity * p.n_gslots + sc.pbase;
   double s = 0.0, m = 0.0;
@@ -978,6 +983,20 @@ __device__ inline void gang_finalise(const SolveParams& p, const GangScc& sc, co
     wst[S_N_ITERATED] += 1ull;
     if (!conv) wst[S_NOT_CONV] += 1ull;
   }
+}
+
+constexpr uint32_t kHubRow = 2048;   // rows with more in-edges are summed in pieces
+constexpr uint32_t kHubPiece = 1024; // edges per piece
+
+// first hub row >= r in the gang's (row-sorted) hub table
+__device__ inline int first_hub(const SolveParams& p, const GangDesc& gd, int r) {
+  int lo = gd.h0, hi = gd.h1;
+  while (lo < hi) {
+    int mid = lo + (hi - lo) / 2;
+    if (p.ghubs[mid].row < r) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
 }
 
 template <typename YT, int RPW>
@@ -1053,17 +1072,28 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
         continue;
       }
       const YT cy = (YT)c;
-      for (int ra = w0; ra < w1; ra += 64) {
-        const int nr = w1 - ra < 64 ? w1 - ra : 64;
-        const YT s = wave_tile_gather<RPW, YT, false>(p, ptr, p.int_src, yr, ra, nr, &s_tile[wave]);
+      int hidx = first_hub(p, gd, w0);  // hub rows are summed in pieces below
+      int ra = w0;
+      while (ra < w1) {
+        const int nexth = hidx < gd.h1 ? p.ghubs[hidx].row : 0x7fffffff;
+        if (ra == nexth) {
+          ++ra;
+          ++hidx;
+          continue;
+        }
+        int rb = ra + 64 < w1 ? ra + 64 : w1;
+        if (nexth < rb) rb = nexth;
+        const int nr = rb - ra;
+        const YT sv = wave_tile_gather<RPW, YT, false>(p, ptr, p.int_src, yr, ra, nr, &s_tile[wave]);
         if (lane < nr) {
           const int v = ra + lane;
-          p.R[v] += (double)s;
-          if constexpr (sizeof(YT) == 8) yw[v] = cy * s * p.inv64[v];
-          else yw[v] = cy * s * p.inv32[v];
-          part += (double)s;
-          pm = fmax(pm, (double)s);
+          p.R[v] += (double)sv;
+          if constexpr (sizeof(YT) == 8) yw[v] = cy * sv * p.inv64[v];
+          else yw[v] = cy * sv * p.inv32[v];
+          part += (double)sv;
+          pm = fmax(pm, (double)sv);
         }
+        ra = rb;
       }
     }
     part = block_sum(part, s_red);
@@ -1074,11 +1104,59 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
       p.gpmx[slot] = pm;
     }
   }
+  // pieces of hub rows assigned to this workgroup (terms k >= 1); a piece
+  // of an SCC that has stopped is computed anyway and ignored by the combine
+  if (k > 0 && !final_launch && gd.h1 > gd.h0) {
+    const int pb = p.gpiece_ptr[gd.poff + blockIdx.x], pe = p.gpiece_ptr[gd.poff + blockIdx.x + 1];
+    for (int q = pb + wave; q < pe; q += kWaves) {
+      const GangPiece pc = p.gpieces[q];
+      YT a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      uint32_t e = pc.ebeg + lane;
+      for (; e + 192 < pc.eend; e += 256) {
+        const int32_t s0 = p.int_src[e], s1 = p.int_src[e + 64], s2 = p.int_src[e + 128], s3 = p.int_src[e + 192];
+        a0 += yr[s0];
+        a1 += yr[s1];
+        a2 += yr[s2];
+        a3 += yr[s3];
+      }
+      for (; e < pc.eend; e += 64) a0 += yr[p.int_src[e]];
+      const YT sum = wave_sum((a0 + a1) + (a2 + a3));
+      if (lane == 0) p.gpiece_part[q] = (double)sum;
+    }
+  }
   if (threadIdx.x == 0) {
     s_stats[S_T_GANG] += wall_clock64() - t_k;
     s_stats[S_N_GANG] += 1;
   }
   flush_stats(p, s_stats);
+}
+
+// Combine the pieces of every hub row of a gang after launch k: one
+// wavefront per hub sums its pieces in order and applies the row update
+// (k = 0: the hub slots of the first launch are cleared).
+template <typename YT>
+__global__ __launch_bounds__(kThreads) void k_gang_hubs(SolveParams p, int gang, int k) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const GangDesc gd = p.gangs[gang];
+  const int h = gd.h0 + blockIdx.x * kWaves + wave;
+  if (h >= gd.h1 || lane != 0) return;
+  const GangHub hb = p.ghubs[h];
+  const size_t slot = (size_t)(k & 1) * p.n_gslots + hb.slot;
+  if (k == 0) {
+    p.gpart[slot] = 0.0;
+    p.gpmx[slot] = 0.0;
+    return;
+  }
+  if (p.gdone[hb.scc] >= 0) return;  // its SCC stopped in launch k
+  YT s = 0;
+  for (int q = hb.p0; q < hb.p1; ++q) s += (YT)p.gpiece_part[p.ghub_pieces[q]];
+  YT* yw = (YT*)((k & 1) ? p.y1 : p.y0);
+  const int v = hb.row;
+  p.R[v] += (double)s;
+  if constexpr (sizeof(YT) == 8) yw[v] = (YT)p.c * s * p.inv64[v];
+  else yw[v] = (YT)p.c * s * p.inv32[v];
+  p.gpart[slot] = (double)s;
+  p.gpmx[slot] = (double)s;
 }
 
 // ------------------------------------------------------------ setup kernels
@@ -1178,6 +1256,10 @@ GangFn gang_kernel(int rpw) {
     default: return k_gang<YT, 1>;
   }
 }
+using HubFn = void (*)(SolveParams, int, int);
+HubFn pick_hubs(int precision) {
+  return precision == PR_PREC_FP64 ? (HubFn)k_gang_hubs<double> : (HubFn)k_gang_hubs<float>;
+}
 SegFn pick_segment(int precision, int rpw) {
   return precision == PR_PREC_FP64 ? seg_kernel<double>(rpw) : seg_kernel<float>(rpw);
 }
@@ -1216,31 +1298,51 @@ static int32_t grid_for(int rpw, int* grid, int* ggrid) {
   return PR_OK;
 }
 
-// edge-balanced split of rows [vb, ve) into G workgroup ranges
+// edge-balanced split of rows [vb, ve) into G workgroup ranges; a hub row
+// (summed in pieces) counts as one unit
 static void balanced_bounds(const std::vector<uint32_t>& ptr, int vb, int ve, int G, int32_t* out) {
-  const int64_t e0 = ptr[vb];
-  const int64_t total = (int64_t)(ptr[ve] - ptr[vb]) + (ve - vb);
+  auto w = [&](int r) -> int64_t {
+    const uint32_t d = ptr[r + 1] - ptr[r];
+    return (d > kHubRow ? 0 : (int64_t)d) + 1;
+  };
+  int64_t total = 0;
+  for (int r = vb; r < ve; ++r) total += w(r);
   out[0] = vb;
   out[G] = ve;
   int r = vb;
+  int64_t acc = 0;
   for (int g = 1; g < G; ++g) {
     const int64_t target = total * g / G;
-    while (r < ve && (int64_t)(ptr[r] - e0) + (r - vb) < target) ++r;
+    while (r < ve && acc < target) acc += w(r++);
     out[g] = r;
   }
 }
 
+struct GangTables {
+  std::vector<GangDesc> gangs;
+  std::vector<GangScc> sccs;
+  std::vector<int32_t> bounds;
+  std::vector<GangHub> hubs;
+  std::vector<GangPiece> pieces;
+  std::vector<int32_t> piece_ptr;
+  std::vector<int32_t> hub_pieces;  // per hub, its piece positions in edge order
+  int32_t slots = 0;
+};
+
 static void add_gang(const std::vector<uint32_t>& ptr, int G, int vb, int ve, const std::vector<int64_t>& ranks,
-                     const std::vector<int32_t>& cvbeg, std::vector<GangDesc>& gangs, std::vector<GangScc>& sccs,
-                     std::vector<int32_t>& bounds, int32_t& slots) {
+                     const std::vector<int32_t>& cvbeg, GangTables& T) {
   GangDesc gd{};
   gd.vbeg = vb;
   gd.vend = ve;
-  gd.s0 = (int32_t)sccs.size();
-  gd.boff = (int32_t)bounds.size();
-  bounds.resize(bounds.size() + G + 1);
-  int32_t* b = bounds.data() + gd.boff;
+  gd.s0 = (int32_t)T.sccs.size();
+  gd.boff = (int32_t)T.bounds.size();
+  gd.h0 = (int32_t)T.hubs.size();
+  T.bounds.resize(T.bounds.size() + G + 1);
+  int32_t* b = T.bounds.data() + gd.boff;
   balanced_bounds(ptr, vb, ve, G, b);
+  // pieces per workgroup of this gang, filled below
+  std::vector<std::vector<GangPiece>> per_wg(G);
+  int rot = 0;
   for (int64_t q : ranks) {
     GangScc sc{};
     sc.rank = (int32_t)q;
@@ -1252,26 +1354,64 @@ static void add_gang(const std::vector<uint32_t>& ptr, int G, int vb, int ve, co
     while (l + 1 < G && b[l + 1] < sc.vend) ++l;
     sc.wg_first = f;
     sc.wg_last = l;
-    sc.pbase = slots;
-    sc.gidx = (int32_t)sccs.size();
-    slots += l - f + 1;
-    sccs.push_back(sc);
+    sc.pbase = T.slots;
+    sc.gidx = (int32_t)T.sccs.size();
+    const int nw = l - f + 1;
+    int nh = 0;
+    for (int r = sc.vbeg; r < sc.vend; ++r) {
+      const uint32_t d = ptr[r + 1] - ptr[r];
+      if (d <= kHubRow) continue;
+      GangHub hb{};
+      hb.row = r;
+      hb.scc = sc.gidx;
+      hb.slot = sc.pbase + nw + nh;
+      const int hidx = (int)T.hubs.size();
+      const uint32_t np = (d + kHubPiece - 1) / kHubPiece;
+      hb.p0 = (int32_t)np;  // piece count for now; turned into a range below
+      for (uint32_t j = 0; j < np; ++j) {
+        GangPiece pc{};
+        pc.ebeg = ptr[r] + j * kHubPiece;
+        pc.eend = std::min(ptr[r + 1], pc.ebeg + kHubPiece);
+        pc.hub = hidx;
+        pc.pad = (int32_t)j;
+        per_wg[f + (rot++ % nw)].push_back(pc);
+      }
+      T.hubs.push_back(hb);
+      ++nh;
+    }
+    sc.nslot = nw + nh;
+    T.slots += sc.nslot;
+    T.sccs.push_back(sc);
   }
-  gd.s1 = (int32_t)sccs.size();
-  gangs.push_back(gd);
+  gd.s1 = (int32_t)T.sccs.size();
+  gd.h1 = (int32_t)T.hubs.size();
+  // lay the pieces out by workgroup, and give each hub the positions of its
+  // pieces in edge order (the combine sums them in that fixed order)
+  for (int h = gd.h0; h < gd.h1; ++h) {
+    const int32_t np = T.hubs[h].p0;
+    T.hubs[h].p0 = (int32_t)T.hub_pieces.size();
+    T.hubs[h].p1 = T.hubs[h].p0 + np;
+    T.hub_pieces.resize(T.hub_pieces.size() + np);
+  }
+  gd.poff = (int32_t)T.piece_ptr.size();
+  T.piece_ptr.push_back((int32_t)T.pieces.size());
+  for (int g = 0; g < G; ++g) {
+    for (const GangPiece& pc : per_wg[g]) {
+      T.hub_pieces[T.hubs[pc.hub].p0 + pc.pad] = (int32_t)T.pieces.size();
+      T.pieces.push_back(pc);
+    }
+    T.piece_ptr.push_back((int32_t)T.pieces.size());
+  }
+  T.gangs.push_back(gd);
 }
-
 int32_t make_schedule(Levels& lv, hipStream_t s) {
   PR_TRY(grid_for(lv.opts.rows_per_wave, &lv.grid, &lv.ggrid));
   lv.sgrid = std::max(lv.grid, lv.ggrid);
   const int G = lv.ggrid;  // gang row bounds are per gang workgroup
   const int64_t K = lv.n_comp;
   std::vector<Item> items;
-  std::vector<GangDesc> gangs;
-  std::vector<GangScc> sccs;
-  std::vector<int32_t> bounds;
+  GangTables T;
   std::vector<Phase> phases;
-  int32_t slots = 0;
   int64_t seg_start = 0;
   int64_t r = 0;
   while (r < K) {
@@ -1297,29 +1437,30 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
       for (int32_t v = v0; v < v1; v += kThreads) items.push_back(Item{ITEM_VERTS, v, std::min(v1, v + kThreads), 0});
     }
     if (!large.empty()) {
-      // large SCCs are adjacent in plan order (size-descending within the level)
       if ((int64_t)items.size() > seg_start) phases.push_back(Phase{0, (int32_t)seg_start, (int32_t)items.size()});
       seg_start = (int64_t)items.size();
       const int vb = lv.h_comp_vbeg[large.front()], ve = lv.h_comp_vbeg[large.back() + 1];
-      phases.push_back(Phase{1, (int32_t)gangs.size(), 0});
-      add_gang(lv.h_int_ptr, G, vb, ve, large, lv.h_comp_vbeg, gangs, sccs, bounds, slots);
+      phases.push_back(Phase{1, (int32_t)T.gangs.size(), 0});
+      add_gang(lv.h_int_ptr, G, vb, ve, large, lv.h_comp_vbeg, T);
     }
     r = e;
   }
   if ((int64_t)items.size() > seg_start) phases.push_back(Phase{0, (int32_t)seg_start, (int32_t)items.size()});
   lv.n_items = (int64_t)items.size();
-  lv.n_gangs = (int64_t)gangs.size();
-  const int64_t n_gscc_cw = (int64_t)sccs.size();
+  lv.n_gangs = (int64_t)T.gangs.size();
+  const int64_t n_gscc_cw = (int64_t)T.sccs.size();
   // the whole-graph gang of method PLAIN comes last
-  if (!lv.h_full_ptr.empty()) {
-    add_gang(lv.h_full_ptr, G, 0, (int)lv.n, std::vector<int64_t>{-1}, lv.h_comp_vbeg, gangs, sccs, bounds, slots);
-  }
-  lv.n_gscc = (int64_t)sccs.size();
-  lv.n_gslots = slots;
+  if (!lv.h_full_ptr.empty()) add_gang(lv.h_full_ptr, G, 0, (int)lv.n, std::vector<int64_t>{-1}, lv.h_comp_vbeg, T);
+  lv.n_gscc = (int64_t)T.sccs.size();
+  lv.n_gslots = T.slots;
+  lv.n_ghubs = (int64_t)T.hubs.size();
+  lv.n_gpieces = (int64_t)T.pieces.size();
+  lv.h_gang_nhub.clear();
+  for (const GangDesc& gd : T.gangs) lv.h_gang_nhub.push_back(gd.h1 - gd.h0);
   lv.phases = phases;
   // device copies
   void* old[] = {lv.items, lv.gangs, lv.gsccs, lv.gbounds, lv.gpart, lv.gpmx, lv.gwsum, lv.gdone, lv.wgstats,
-                 lv.trace, lv.seg_heads};
+                 lv.trace, lv.seg_heads, lv.ghubs, lv.gpieces, lv.gpiece_ptr, lv.gpiece_part, lv.ghub_pieces};
   for (void* q : old)
     if (q) (void)hipFree(q);
   lv.items = nullptr;
@@ -1333,24 +1474,33 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   lv.wgstats = nullptr;
   lv.trace = nullptr;
   lv.seg_heads = nullptr;
-  PR_TRY(dalloc(&lv.items, items.size()));
-  PR_TRY(dalloc(&lv.gangs, gangs.size()));
-  PR_TRY(dalloc(&lv.gsccs, sccs.size()));
-  PR_TRY(dalloc(&lv.gbounds, bounds.size()));
-  PR_TRY(dalloc(&lv.gpart, 2 * (size_t)slots));
-  PR_TRY(dalloc(&lv.gpmx, 2 * (size_t)slots));
-  PR_TRY(dalloc(&lv.gwsum, sccs.size()));
-  PR_TRY(dalloc(&lv.gdone, sccs.size()));
+  lv.ghubs = nullptr;
+  lv.gpieces = nullptr;
+  lv.gpiece_ptr = nullptr;
+  lv.gpiece_part = nullptr;
+  lv.ghub_pieces = nullptr;
+  auto upload = [&](auto** dst, const auto& vec) -> int32_t {
+    using T0 = typename std::remove_reference<decltype(vec)>::type::value_type;
+    PR_TRY(dalloc(reinterpret_cast<T0**>(dst), vec.size()));
+    if (!vec.empty())
+      PR_HIP_CHECK(hipMemcpyAsync(*dst, vec.data(), sizeof(T0) * vec.size(), hipMemcpyHostToDevice, s));
+    return PR_OK;
+  };
+  PR_TRY(upload(&lv.items, items));
+  PR_TRY(upload(&lv.gangs, T.gangs));
+  PR_TRY(upload(&lv.gsccs, T.sccs));
+  PR_TRY(upload(&lv.gbounds, T.bounds));
+  PR_TRY(upload(&lv.ghubs, T.hubs));
+  PR_TRY(upload(&lv.gpieces, T.pieces));
+  PR_TRY(upload(&lv.gpiece_ptr, T.piece_ptr));
+  PR_TRY(upload(&lv.ghub_pieces, T.hub_pieces));
+  PR_TRY(dalloc(&lv.gpiece_part, T.pieces.size()));
+  PR_TRY(dalloc(&lv.gpart, 2 * (size_t)T.slots));
+  PR_TRY(dalloc(&lv.gpmx, 2 * (size_t)T.slots));
+  PR_TRY(dalloc(&lv.gwsum, T.sccs.size()));
+  PR_TRY(dalloc(&lv.gdone, T.sccs.size()));
   PR_TRY(dalloc(&lv.wgstats, (size_t)lv.sgrid * kWgStats));
   PR_TRY(dalloc(&lv.seg_heads, std::max<size_t>(phases.size(), 1)));
-  if (!items.empty())
-    PR_HIP_CHECK(hipMemcpyAsync(lv.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s));
-  if (!gangs.empty())
-    PR_HIP_CHECK(hipMemcpyAsync(lv.gangs, gangs.data(), sizeof(GangDesc) * gangs.size(), hipMemcpyHostToDevice, s));
-  if (!sccs.empty())
-    PR_HIP_CHECK(hipMemcpyAsync(lv.gsccs, sccs.data(), sizeof(GangScc) * sccs.size(), hipMemcpyHostToDevice, s));
-  if (!bounds.empty())
-    PR_HIP_CHECK(hipMemcpyAsync(lv.gbounds, bounds.data(), sizeof(int32_t) * bounds.size(), hipMemcpyHostToDevice, s));
   const int64_t n = lv.n;
   if (!lv.x) {
     PR_TRY(dalloc(&lv.x, n));
@@ -1453,6 +1603,11 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.gpmx = lv.gpmx;
   p.gwsum = lv.gwsum;
   p.gdone = lv.gdone;
+  p.ghubs = lv.ghubs;
+  p.gpieces = lv.gpieces;
+  p.gpiece_ptr = lv.gpiece_ptr;
+  p.ghub_pieces = lv.ghub_pieces;
+  p.gpiece_part = lv.gpiece_part;
   p.n_gslots = lv.n_gslots;
   p.timeout = (unsigned long long)clock_khz * 1000ull * 30ull;  // 30 s
   if (o.reserved[0] == 1) {  // timeline of the segment items (tests / profiling)
@@ -1492,10 +1647,14 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   hipEvent_t ev0, ev1;
   PR_HIP_CHECK(hipEventCreate(&ev0));
   PR_HIP_CHECK(hipEventCreate(&ev1));
+  const HubFn hk = pick_hubs(o.precision);
   auto launch_gang = [&](int gang) -> int32_t {
+    const int nh = lv.h_gang_nhub[gang];
     for (int64_t k = 0; k <= kb + 1; ++k) {
       const int fin = k == kb + 1 ? 1 : 0;
       hipLaunchKernelGGL(gk, dim3(lv.ggrid), dim3(kThreads), 0, s, p, gang, (int)k, fin);
+      if (nh > 0 && !fin)
+        hipLaunchKernelGGL(hk, dim3((nh + kWaves - 1) / kWaves), dim3(kThreads), 0, s, p, gang, (int)k);
     }
     return PR_OK;
   };
