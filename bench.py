@@ -24,28 +24,144 @@ sys.path.insert(0, ROOT)
 METRIC = "GEdge-iter/s + time to 1e-6 rel err: componentwise(+warm start) vs plain PR"
 HBM_PEAK_GBS = 8000.0
 
-# algorithmic bytes: series terms FP32 (mixed) or FP64
-B_EDGE_ITER = {0: 8, 1: 12}       # source index + term gather
-B_VERT_ITER = {0: 28, 1: 36}      # row ptr, 1/outdeg, term write, R read+write
-B_EDGE_ONCE = 12                  # between/CAC edge: source index + x gather
-B_VERT_ONCE = 44                  # W, perm, two row ptrs, R out, x, 1/outdeg
+# Algorithmic bytes per unit of work (int32 indices, FP32 or FP64 terms, FP64 R):
+#  term edge  4 B source index + one term gather (4 B mixed, 8 B FP64)
+#  term row   row pointer 4 + 1/outdeg 4 + term write (4 | 8) + R read and write 16
+#  once edge  4 B source index + 8 B x gather (boundary and CAC edges, and the
+#             one compulsory load of an LDS-resident SCC's edges)
+#  once row   W 8 + perm 4 + two row pointers 8 + R out 8 + x 8 + 1/outdeg 8
+B_TERM_EDGE = {0: 8, 1: 12}
+B_TERM_ROW = {0: 28, 1: 32}
+B_ONCE_EDGE = 12
+B_ONCE_ROW = 44
+FAMILIES = ["k_segment", "k_gang", "k_gang_hubs", "k_reduce"]
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def alg_bytes(st, info, prec, plain):
-    b = st["edge_iters"] * 0
-    if plain:
-        b = st["edge_iters"] * B_EDGE_ITER[prec] + st["vert_iters"] * B_VERT_ITER[prec]
-        b += info["n"] * 28
-        return b
-    e_once = info["m_between"] + info["m_cac_internal"]
-    e_it = st["edge_iters"] - e_once
-    v_once = info["n"]
-    v_it = st["vert_iters"] - (info["n"] - info["v_scc"])
-    return e_it * B_EDGE_ITER[prec] + v_it * B_VERT_ITER[prec] + e_once * B_EDGE_ONCE + v_once * B_VERT_ONCE
+def family_bytes(fam, info, st, prec, plain):
+    """Algorithmic bytes moved by all launches of one kernel family in one solve."""
+    if fam == 0:  # segments: every row and edge outside the gangs once
+        rows = info["n"] - info["v_gang"]
+        edges = info["m"] - info["m_gang_internal"] - info["m_gang_between"]
+        return rows * B_ONCE_ROW + edges * B_ONCE_EDGE
+    if fam == 1:  # gang terms
+        if plain:
+            terms = st["iters_max"] + 1
+            return terms * (info["m"] * B_TERM_EDGE[prec] + info["n"] * B_TERM_ROW[prec]) + info["n"] * B_ONCE_ROW
+        gang_term_edges = st["gang_edge_iters"]
+        gang_term_rows = st["gang_vert_iters"]
+        return (gang_term_edges * B_TERM_EDGE[prec] + gang_term_rows * B_TERM_ROW[prec]
+                + info["v_gang"] * B_ONCE_ROW + info["m_gang_between"] * B_ONCE_EDGE)
+    return 0
+
+
+def roofline(fam, info, st, prec, plain, traffic):
+    cnt = st["kt_count"][fam]
+    ms = st["kt_ms"][fam]
+    b = family_bytes(fam, info, st, prec, plain)
+    per_launch = b / max(cnt, 1)
+    avg_ms = ms / max(cnt, 1)
+    ach = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": FAMILIES[fam], "launches_per_solve": cnt, "avg_launch_us": round(avg_ms * 1e3, 3),
+            "alg_bytes_per_launch": int(per_launch)}
+
+
+def load_traffic(path, kernel):
+    """HBM bytes per launch of `kernel` ("family/method") from a committed
+    counter summary, or None when there is none or the kernel sources changed
+    since the counters were taken."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash() or kernel not in d.get("kernels", {}):
+        return None
+    k = d["kernels"][kernel]
+    return k["hbm_bytes_per_launch"]
+
+
+def source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1609_09068_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def summarize_pmc(fetch_dir, write_dir, calib_mb, out, method):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) into bytes per launch per kernel family, scaled by what the
+    same counters read for a plain device copy of calib_mb MiB."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = []
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as f:
+                for r in csv.DictReader(f):
+                    if r.get("Counter_Name") == counter:
+                        rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return rows
+
+    res = {}
+    calib = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = read(d, counter)
+        copy = [v for k, v in rows if "elementwise" in k.lower() or "copy" in k.lower()]
+        copy = [v for v in copy if v > 0.5 * calib_mb * 1024]
+        if not copy:
+            raise SystemExit(f"no calibration copy dispatch found for {counter}")
+        factor = calib_mb * 1024.0 / float(np.median(copy))
+        calib[counter] = {"copy_mib": calib_mb, "counter_kib_median": float(np.median(copy)), "factor": factor}
+        for fam in FAMILIES:
+            vals = [v for k, v in rows if (fam + "<") in k or k.endswith(fam) or (fam + "(") in k]
+            if fam == "k_gang":
+                vals = [v for k, v in rows if "k_gang<" in k]
+            if vals:
+                res.setdefault(fam, {})[counter] = {"dispatches": len(vals), "kib_mean": float(np.mean(vals)),
+                                                    "bytes_per_launch": float(np.mean(vals)) * 1024 * factor}
+    kern = {}
+    for fam, d in res.items():
+        if "FETCH_SIZE" in d and "WRITE_SIZE" in d:
+            r = d["FETCH_SIZE"]["bytes_per_launch"]
+            w = d["WRITE_SIZE"]["bytes_per_launch"]
+            kern[fam] = {"read_bytes_per_launch": int(r), "write_bytes_per_launch": int(w),
+                         "hbm_bytes_per_launch": int(r + w), "dispatches": d["FETCH_SIZE"]["dispatches"]}
+    doc = {}
+    if os.path.exists(out):
+        with open(out) as f:
+            doc = json.load(f)
+        if doc.get("source_hash") != source_hash():
+            doc = {}
+    doc["source_hash"] = source_hash()
+    doc.setdefault("calibration", {})[method] = calib
+    for fam, v in kern.items():
+        doc.setdefault("kernels", {})[f"{fam}/{method}"] = v
+    with open(out, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(json.dumps(doc))
+
+
+def calib_copy(torch, mib):
+    """A plain device copy of known size: what FETCH_SIZE / WRITE_SIZE read for it
+    scales the kernel's counters to bytes."""
+    nb = mib * (1 << 20) // 4
+    a = torch.ones(nb, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {mib} MiB read + {mib} MiB write")
 
 
 def main():
@@ -58,13 +174,25 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-check", action="store_true", help="skip the accuracy check against the oracle")
     ap.add_argument("--graph", type=int, default=0, help="replay a captured hipGraph")
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--small-cutoff", type=int, default=0)
     ap.add_argument("--team-edges", type=int, default=0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "hbm_traffic_c2_web_1m.json"),
+                    help="committed counter summary that supplies roofline.traffic")
+    ap.add_argument("--only", choices=["componentwise", "plain"],
+                    help="run one method only (counter runs: one kernel family per method)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
+                    help="write a counter summary from two rocprofv3 --pmc runs and exit "
+                         "(with --only: the method those runs used)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.calib_copy_mb or 1024,
+                      args.summarize_pmc[2], args.only or "componentwise")
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -103,59 +231,79 @@ def main():
     W = torch.ones(g.n, dtype=torch.float64, device="cuda")
     R = torch.empty_like(W)
     Rp = torch.empty_like(W)
-    common = dict(eps=args.eps, precision=args.precision, use_graph=args.graph)
+    common = dict(eps=args.eps, precision=args.precision, use_graph=args.graph,
+                  kernel_timing=0 if args.graph else 1)
 
-    def run(method, Rout, steps):
+    def run(method, Rout, steps, **extra):
         stats = []
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
-            rc, st = pr.pr_solve(lv, args.c, W, Rout, method=method, **common)
+            rc, st = pr.pr_solve(lv, args.c, W, Rout, method=method, **{**common, **extra})
             stats.append(st)
         torch.cuda.synchronize()
         return (time.perf_counter() - t), stats
 
+    if args.only:
+        # counter runs: a few solves of one method, then the calibration copy
+        meth = 0 if args.only == "componentwise" else 1
+        for _ in range(args.warmup + args.steps):
+            run(meth, R, 1)
+        if args.calib_copy_mb:
+            calib_copy(torch, args.calib_copy_mb)
+        log(f"{args.only}: {args.warmup + args.steps} solves done")
+        return
     for _ in range(args.warmup):
         run(0, R, 1)
         run(1, Rp, 1)
-    log("warmup done")
+    # the same solve without per-launch events: shows what the events cost
+    t_ne, _ = run(0, R, 2, kernel_timing=0)
+    log(f"warmup done; componentwise without launch events {t_ne / 2 * 1e3:.3f} ms")
     t_cw, st_cw = run(0, R, args.steps)
     log(f"componentwise: {t_cw / args.steps * 1e3:.3f} ms/step")
     t_pl, st_pl = run(1, Rp, args.steps)
     log(f"plain: {t_pl / args.steps * 1e3:.3f} ms/step")
 
     if args.calib_copy_mb:
-        nb = args.calib_copy_mb * (1 << 20) // 4
-        a = torch.ones(nb, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB write")
-
-    # accuracy against the FP64 oracle reference
-    from oracle.pagerank import pagerank_power_series
-
-    t0 = time.perf_counter()
-    ref, kref, _ = pagerank_power_series(g.n, g.row_ptr, g.col, args.c, np.ones(g.n), eps=1e-12)
-    log(f"oracle reference (eps 1e-12, {kref} iterations) {time.perf_counter() - t0:.1f}s")
-    Rc = R.cpu().numpy()
-    Rpl = Rp.cpu().numpy()
-    err_cw = float(np.abs(Rc - ref).sum() / ref.sum())
-    err_pl = float(np.abs(Rpl - ref).sum() / ref.sum())
-    ref_part = None
+        calib_copy(torch, args.calib_copy_mb)
 
     ms_cw = t_cw / args.steps * 1e3
     ms_pl = t_pl / args.steps * 1e3
     s = st_cw[-1]
     sp = st_pl[-1]
-    kms_cw = float(np.mean([x["kernel_ms"] for x in st_cw]))
-    kms_pl = float(np.mean([x["kernel_ms"] for x in st_pl]))
+
+    def mean_stats(sts):
+        d = dict(sts[-1])
+        d["kt_ms"] = list(np.mean([x["kt_ms"] for x in sts], axis=0))
+        d["kernel_ms"] = float(np.mean([x["kernel_ms"] for x in sts]))
+        return d
+
+    mcw = mean_stats(st_cw)
+    mpl = mean_stats(st_pl)
     value = s["edge_iters"] / (ms_cw * 1e-3) / 1e9
-    bytes_cw = alg_bytes(s, info, args.precision, False)
-    bytes_pl = alg_bytes(sp, info, args.precision, True)
-    ach_cw = bytes_cw / (kms_cw * 1e-3) / 1e9
-    ach_pl = bytes_pl / (kms_pl * 1e-3) / 1e9
+    dom = int(np.argmax(mcw["kt_ms"])) if any(mcw["kt_ms"]) else 0
+    traffic_cw = load_traffic(args.traffic, FAMILIES[dom] + "/componentwise")
+    roof = roofline(dom, info, mcw, args.precision, False, traffic_cw)
+    roof_spmv = roofline(1, info, mpl, args.precision, True, load_traffic(args.traffic, "k_gang/plain"))
+    roof_spmv["what"] = "plain whole-graph power series, one launch per term (the SpMV phase)"
+    kt = {"componentwise": {FAMILIES[i]: {"ms": round(mcw["kt_ms"][i], 4), "launches": mcw["kt_count"][i]}
+                            for i in range(4)},
+          "plain": {FAMILIES[i]: {"ms": round(mpl["kt_ms"][i], 4), "launches": mpl["kt_count"][i]}
+                    for i in range(4)}}
+
+    acc = None
+    if not args.no_check:
+        from oracle.pagerank import pagerank_power_series
+
+        t0 = time.perf_counter()
+        ref, kref, _ = pagerank_power_series(g.n, g.row_ptr, g.col, args.c, np.ones(g.n), eps=1e-12)
+        log(f"oracle reference (eps 1e-12, {kref} iterations) {time.perf_counter() - t0:.1f}s")
+        Rc = R.cpu().numpy()
+        Rpl = Rp.cpu().numpy()
+        acc = {"componentwise": float(np.abs(Rc - ref).sum() / ref.sum()),
+               "plain": float(np.abs(Rpl - ref).sum() / ref.sum()),
+               "cert_componentwise": s["cert_rel"], "cert_plain": sp["cert_rel"],
+               "reference": f"oracle plain power series, FP64, eps 1e-12 ({kref} terms)"}
 
     cpu = None
     if not args.no_cpu:
@@ -171,15 +319,14 @@ def main():
         part_d = part.as_dict()
         scc = part_d["comp_type"] == 1
         e_int = np.zeros(part.n_comp)
-        # internal edges per SCC from the oracle's own partition arrays
         src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
         keep = (src != g.col) & (part_d["comp"][src] == part_d["comp"][g.col])
         np.add.at(e_int, part_d["comp"][src[keep]], 1)
         e_iter_or = float(np.sum(sto["iters"][scc] * e_int[scc])) + (info["m_between"] + info["m_cac_internal"])
-        cpu = {"value": e_iter_or / t_or / 1e9, "unit": "GEdge-iter/s", "cores": 1, "kind": "oracle",
-               "sample": f"full {args.config} graph, serial componentwise oracle (numpy/scipy FP64, "
-                         f"1 thread), eps {args.eps}: {t_or:.2f} s",
-               "time_to_1e-6_ms": t_or * 1e3, "host_cores_available": len(os.sched_getaffinity(0))}
+        cpu = {"value": round(e_iter_or / t_or / 1e9, 5), "unit": "GEdge-iter/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole {args.config} solve: serial componentwise oracle (numpy/scipy, FP64, "
+                         f"1 thread), eps {args.eps}, {t_or:.2f} s",
+               "time_to_1e-6_ms": round(t_or * 1e3, 1), "host_cores_available": len(os.sched_getaffinity(0))}
         log(f"cpu oracle {t_or:.2f}s")
 
     out = {
@@ -196,33 +343,31 @@ def main():
         "dtype": "f32+f64" if args.precision == 0 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: web-like graph n={g.n} m={g.m}, c={args.c}, "
-                               f"1-norm certificate eps={args.eps}, W=1, solve with plan resident",
+                               f"1-norm certificate eps={args.eps}, W=1, solve with the plan resident",
                    "n": g.n, "m": g.m, "levels": info["n_levels"], "components": info["n_comp"],
                    "scc": info["n_scc"], "scc_vertices": info["v_scc"], "m_scc_internal": info["m_scc_internal"],
                    "m_between": info["m_between"], "m_cac_internal": info["m_cac_internal"],
-                   "rows_per_wave": info["rows_per_wave"], "small_cutoff": info["small_cutoff"],
-                   "team_edges": info["team_edges"], "grid_wgs": info["grid_wgs"], "hipgraph": bool(args.graph)},
+                   "gang_vertices": info["v_gang"], "rows_per_wave": info["rows_per_wave"],
+                   "small_cutoff": info["small_cutoff"], "team_edges": info["team_edges"],
+                   "grid_wgs": info["grid_wgs"], "hipgraph": bool(args.graph)},
         "time_to_1e-6_ms": {"componentwise": round(ms_cw, 4), "plain": round(ms_pl, 4),
-                            "componentwise_kernel": round(kms_cw, 4), "plain_kernel": round(kms_pl, 4)},
+                            "componentwise_device": round(mcw["kernel_ms"], 4),
+                            "plain_device": round(mpl["kernel_ms"], 4),
+                            "componentwise_no_launch_events": round(t_ne / 2 * 1e3, 4)},
         "speedup_vs_plain": round(ms_pl / ms_cw, 3),
         "plain_gedge_iter_s": round(sp["edge_iters"] / (ms_pl * 1e-3) / 1e9, 4),
         "plain_equivalent_gedge_iter_s": round(sp["edge_iters"] / (ms_cw * 1e-3) / 1e9, 4),
         "iterations": {"componentwise_max": s["iters_max"], "plain": sp["iters_max"],
                        "edge_iters_cw": s["edge_iters"], "edge_iters_plain": sp["edge_iters"]},
-        "rel_l1_vs_fp64_oracle": {"componentwise": err_cw, "plain": err_pl,
-                                  "cert_componentwise": s["cert_rel"], "cert_plain": sp["cert_rel"]},
+        "rel_l1_vs_fp64_oracle": acc,
         "partition_ms": round(t_part * 1e3, 2),
         "build_ms": round(t_build * 1e3, 2),
-        "roofline": {"bound": "hbm", "achieved": round(ach_cw, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach_cw / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_solve (componentwise)", "alg_bytes_per_launch": int(bytes_cw),
-                     "kernel_ms": round(kms_cw, 4),
-                     "plain": {"achieved": round(ach_pl, 2), "frac": round(ach_pl / HBM_PEAK_GBS, 4),
-                               "alg_bytes_per_launch": int(bytes_pl), "kernel_ms": round(kms_pl, 4)}},
+        "kernel_times": kt,
+        "roofline": roof,
+        "roofline_spmv": roof_spmv,
         "cpu_baseline": cpu,
         "device": dev_name,
     }
-    del ref_part
     print(json.dumps(out), flush=True)
 
 

@@ -136,6 +136,11 @@ typedef struct pr_levels_info {
   int64_t m_between;        /* edges between components (used once) */
   int64_t n_items;          /* work items of the persistent segment kernels */
   int64_t n_gangs, n_gang_scc; /* gang phases, SCCs iterated in gang phases */
+  int64_t v_gang;           /* vertices of the SCCs iterated in gang phases */
+  int64_t m_gang_internal;  /* their internal edges (touched once per term) */
+  int64_t m_gang_between;   /* edges entering them from higher levels */
+  int64_t n_phases;         /* segment and gang phases of the componentwise solve */
+  int64_t n_hubs;           /* rows summed in pieces (more than 2048 in-edges), all gangs */
   int32_t rows_per_wave, small_cutoff, team_edges, grid_wgs;
 } pr_levels_info;
 
@@ -161,7 +166,10 @@ typedef struct pr_solve_opts {
   double tol;        /* PR_STOP_PAPER_MAXABS threshold; default 1e-9 */
   int64_t max_iter;  /* per-component iteration cap; default 100000 */
   pr_mlp_t* warm_start;/* NULL = start every SCC from P_0 = W' (Sec. 3.3.2) */
-  int32_t reserved[8];
+  int32_t trace;        /* 1 = record the item timeline (pr_levels_debug what = 4); slows the solve */
+  int32_t kernel_timing;/* 1 = HIP events around every launch; per-family times land in the stats
+                           (ignored with use_graph) */
+  int32_t reserved[6];
 } pr_solve_opts;
 
 void pr_default_solve_opts(pr_solve_opts* o);
@@ -176,9 +184,16 @@ typedef struct pr_solve_stats {
   double cert_abs;      /* c/(1-c) * sum_C ||P_{K_C}||_1: bound on ||R* - R||_1 (CERT rule) */
   double r_sum;         /* ||R||_1 */
   double cert_rel;      /* cert_abs / r_sum: bound on the relative 1-norm error */
-  double time_ms;       /* device time of the solve (HIP events around its launches) */
+  double time_ms;       /* host wall time of the pr_solve call, weight check included */
   int64_t vert_iters;   /* rows touched: iterations x vertices of each SCC, plus every other vertex once */
-  double kernel_ms;     /* device time of the persistent solve kernel alone (HIP events) */
+  double kernel_ms;     /* device time of the launches after the weight check (HIP events) */
+  /* with kernel_timing = 1: device time and launch count per kernel family,
+     [0] persistent segment kernel, [1] gang term kernel, [2] hub-row combine
+     kernel, [3] final reductions; zero otherwise */
+  double kt_ms[4];
+  int64_t kt_count[4];
+  int64_t gang_edge_iters; /* with kernel_timing = 1, COMPONENTWISE: the part of edge_iters */
+  int64_t gang_vert_iters; /* and vert_iters done by gang launches */
   int32_t reserved[8];
 } pr_solve_stats;
 
@@ -214,7 +229,7 @@ int32_t pr_solve(pr_levels_t* lv, double c, const void* W_dev, void* R_dev,
  * single-workgroup SCC items, gang launches, readiness waits, segment
  * kernels, the number
  * of gang launches and ticks in single-workgroup SCC iterations), 4 = the
- * item timeline of the last solve run with reserved[0] = 1 in its options
+ * item timeline of the last solve run with trace = 1 in its options
  * (uint64[n_items x 4]: workgroup, start tick, end tick, item kind).
  */
 int32_t pr_levels_debug(const pr_levels_t* lv, int32_t what, void* host_out);

@@ -31,7 +31,7 @@ from .partition import partition_theorem
 
 
 def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e-6,
-                        tol=None, max_iter=1_000_000, return_stats=False):
+                        tol=None, max_iter=1_000_000, return_stats=False, warm=None, warm_fn=None):
     """Componentwise R^(3).
 
     Stop rule per SCC C (one term added per iteration, k >= 1):
@@ -40,6 +40,13 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
                computed R is non-zero only on SCC rows, where it equals the
                next, unused term of each component's series)
       "paper": max(P_k) < tol.
+
+    warm: parameters of the starting-guess network (oracle.warmstart); each
+    SCC then starts from its prediction R_0 when that passes the residual
+    test, else from W'_C as usual.  warm_fn(F, Vs, s) -> y may replace the
+    network (F: feature rows of the vertices Vs, s: their component scale),
+    e.g. to plant a perfect or a useless guess.  The stats then also hold, per component, the accept flag
+    (1 kept, 0 fell back, -1 not an SCC).
     """
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
@@ -58,8 +65,20 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
     iters = np.zeros(len(csize), dtype=np.int64)
     last = np.zeros(len(csize), dtype=np.float64)
     wprime = np.zeros(n, dtype=np.float64)
+    accepted = np.full(len(csize), -1, dtype=np.int64)
+    if warm is not None and warm_fn is None:
+        from .warmstart import forward
+
+        def warm_fn(F, Vs, sv):
+            return forward(warm, F)
+    feat = None
+    if warm_fn is not None:
+        from .warmstart import in_degree
+
+        feat = dict(fn=warm_fn, W=W, indeg=in_degree(n, row_ptr, col), outdeg=out_degree(n, row_ptr, col),
+                    accepted=accepted)
     if n == 0:
-        return (R, dict(iters=iters, last=last, wprime=wprime)) if return_stats else R
+        return (R, dict(iters=iters, last=last, wprime=wprime, accepted=accepted)) if return_stats else R
     order = np.argsort(-vlevel, kind="stable")
     lev_sorted = vlevel[order]
     top = int(vlevel.max())
@@ -83,9 +102,9 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
         scc_mask = ctype[cV] == 1
         if np.any(scc_mask):
             Vs = V[scc_mask]
-            _scc_series(Vs, Wp[scc_mask], comp, c, AT, R, iters, last, stop, eps, tol, max_iter)
+            _scc_series(Vs, Wp[scc_mask], comp, c, AT, R, iters, last, stop, eps, tol, max_iter, feat)
     if return_stats:
-        return R, dict(iters=iters, last=last, wprime=wprime)
+        return R, dict(iters=iters, last=last, wprime=wprime, accepted=accepted)
     return R
 
 
@@ -124,8 +143,14 @@ def _cac_sweep(Vc, Wp, comp, c, deg, nbr_ptr, nbr, R):
     R[Vc] = rank
 
 
-def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter):
-    """Power series of Sec. 3.3.2 on each SCC of one level."""
+def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter, feat=None):
+    """Power series of Sec. 3.3.2 on each SCC of one level.
+
+    With a starting guess (feat), a component whose guess passes the residual
+    test starts from p = r_0 and R = R_0 + r_0 with no term counted yet; one
+    that falls back continues from the state after the plain first term
+    (p = P_1, R = W' + P_1, one term counted).  Either way the stop rule is
+    then tested on the current term before the next one is formed."""
     sub = AT[Vs, :][:, Vs]  # block diagonal over the level's SCCs
     cid = comp[Vs]
     uniq, local = np.unique(cid, return_inverse=True)
@@ -137,6 +162,48 @@ def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter):
     it = np.zeros(nc, dtype=np.int64)
     lastn = wnorm.copy()
     k = 0
+
+    def stop_test(pv):
+        if stop == "cert":
+            return np.bincount(local, weights=np.abs(pv), minlength=nc) <= eps * (1.0 - c) * wnorm
+        pm = np.zeros(nc)
+        np.maximum.at(pm, local, np.abs(pv))
+        return pm < tol
+
+    if feat is not None:
+        from .warmstart import scc_features
+
+        F, s, R1 = scc_features(Vs, Wp, feat["W"], local, nc, sub, c, feat["indeg"], feat["outdeg"])
+        live = s > 0
+        y = np.asarray(feat["fn"](F, Vs, s[local]), dtype=np.float64)
+        R0 = s[local] * np.exp(y)
+        r0 = Wp + c * (sub @ R0) - R0
+        p1 = R1 - Wp
+        n_r0 = np.bincount(local, weights=np.abs(r0), minlength=nc)
+        n_p1 = np.bincount(local, weights=np.abs(p1), minlength=nc)
+        keep = live & (n_r0 < n_p1)
+        kv = keep[local]
+        p = np.where(kv, r0, p1)
+        acc = np.where(kv, R0 + r0, R1)
+        it = np.where(keep, 0, 1).astype(np.int64)
+        lastn = np.where(keep, n_r0, n_p1)
+        feat["accepted"][uniq] = keep.astype(np.int64)
+        active = live.copy()
+        active &= ~stop_test(p)
+        p[~active[local]] = 0.0
+        while np.any(active) and int(it[active].max()) < max_iter:
+            p = c * (sub @ p)
+            p[~active[local]] = 0.0
+            acc += p
+            it[active] += 1
+            pn = np.bincount(local, weights=np.abs(p), minlength=nc)
+            lastn[active] = pn[active]
+            active &= ~stop_test(p)
+            active &= it < max_iter
+        R[Vs] = acc
+        iters[uniq] = it
+        last[uniq] = lastn
+        return
     while np.any(active) and k < max_iter:
         p = c * (sub @ p)
         p[~active[local]] = 0.0
@@ -145,12 +212,7 @@ def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter):
         it[active] = k
         pn = np.bincount(local, weights=np.abs(p), minlength=nc)
         lastn[active] = pn[active]
-        if stop == "cert":
-            done = pn <= eps * (1.0 - c) * wnorm
-        else:
-            pm = np.zeros(nc)
-            np.maximum.at(pm, local, p)
-            done = pm < tol
+        done = stop_test(p)
         active &= ~done
     R[Vs] = acc
     iters[uniq] = it

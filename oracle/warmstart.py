@@ -1,0 +1,149 @@
+"""Learned starting guess for the SCC power series, in float64.
+
+Test infrastructure only (see the package docstring).
+
+The paper starts every SCC's series from P_0 = W'_C (Sec. 3.3.2) and notes
+that a previous ranking could serve as the initial rank (Sec. 5).  Here a
+small network predicts, per SCC vertex, the logarithm of its rank relative to
+the component's mean weight, from four local quantities.  The prediction R_0
+is only a starting point: the series is then run on the residual
+    r_0 = W'_C + c A_CC^T R_0 - R_0,     R = R_0 + sum_k (c A_CC^T)^k r_0,
+which converges to the same R_C = (I - c A_CC^T)^{-1} W'_C (Def. 3.5,
+Sec. 3.3) whatever R_0 is.  The guess is kept for a component only when
+||r_0||_1 < ||c A_CC^T W'_C||_1, the norm of the first term the plain start
+would add; otherwise the component falls back to the plain series.
+
+Features of an SCC vertex v (s_C = ||W'_C||_1 / |C|, loops ignored,
+repeated edges counted):
+    f0 = log(1 + in-degree of v)
+    f1 = log(1 + out-degree of v)
+    f2 = log(1 + (W'_v - W_v) / s_C)       rank flowing in from higher levels
+    f3 = log(1 + R1_v / s_C),  R1 = W'_C + c A_CC^T W'_C   (one series step)
+Target: t_v = log(R_v / s_C).  Prediction: R_0,v = s_C exp(y_v).
+
+Network: 4 -> 64 -> 64 -> 1, GELU (exact, with erf) after the two hidden
+layers.  Parameters in one flat vector, in this order: W1 [64 x 4] row-major,
+b1 [64], W2 [64 x 64] row-major, b2 [64], W3 [1 x 64], b3 [1]; 4545 values.
+Training minimises the mean squared error of y against t with Adam (Kingma
+and Ba, 2015: bias-corrected first and second moment estimates).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erf
+
+H = 64
+N_IN = 4
+SHAPES = [("W1", (H, N_IN)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (1, H)), ("b3", (1,))]
+N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
+
+
+def unpack(theta):
+    """Views of the flat parameter vector, in the documented order."""
+    theta = np.asarray(theta, dtype=np.float64)
+    out, o = {}, 0
+    for name, shape in SHAPES:
+        k = int(np.prod(shape))
+        out[name] = theta[o:o + k].reshape(shape)
+        o += k
+    return out
+
+
+def init_params(seed):
+    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in SHAPES:
+        fan_in = shape[1] if len(shape) == 2 else (N_IN if name == "b1" else H)
+        b = 1.0 / math.sqrt(fan_in)
+        parts.append(rng.uniform(-b, b, size=int(np.prod(shape))))
+    return np.concatenate(parts)
+
+
+def gelu(x):
+    """x * Phi(x) with the exact normal CDF."""
+    return 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
+
+
+def gelu_grad(x):
+    """d/dx [x Phi(x)] = Phi(x) + x phi(x)."""
+    return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+
+
+def forward(theta, X, keep=False):
+    """y [B] for features X [B, 4]; with keep, also the intermediate values."""
+    P = unpack(theta)
+    X = np.asarray(X, dtype=np.float64)
+    z1 = X @ P["W1"].T + P["b1"]
+    h1 = gelu(z1)
+    z2 = h1 @ P["W2"].T + P["b2"]
+    h2 = gelu(z2)
+    y = (h2 @ P["W3"].T)[:, 0] + P["b3"][0]
+    if keep:
+        return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2)
+    return y
+
+
+def loss_and_grad(theta, X, t):
+    """L = mean_i (y_i - t_i)^2 and dL/dtheta by the chain rule."""
+    P = unpack(theta)
+    y, c = forward(theta, X, keep=True)
+    B = len(y)
+    d = y - np.asarray(t, dtype=np.float64)
+    L = float(np.mean(d * d))
+    dy = 2.0 * d / B                       # [B]
+    gW3 = dy @ c["h2"]                     # [64]
+    gb3 = dy.sum()
+    dh2 = dy[:, None] * P["W3"][0][None, :]
+    dz2 = dh2 * gelu_grad(c["z2"])
+    gW2 = dz2.T @ c["h1"]
+    gb2 = dz2.sum(axis=0)
+    dh1 = dz2 @ P["W2"]
+    dz1 = dh1 * gelu_grad(c["z1"])
+    gW1 = dz1.T @ c["X"]
+    gb1 = dz1.sum(axis=0)
+    g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), [gb3]])
+    return L, g
+
+
+class Adam:
+    """Adam with bias correction; the state is two moment vectors and a step count."""
+
+    def __init__(self, n, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.m = np.zeros(n)
+        self.v = np.zeros(n)
+        self.t = 0
+        self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+
+    def step(self, theta, g):
+        self.t += 1
+        self.m = self.beta1 * self.m + (1.0 - self.beta1) * g
+        self.v = self.beta2 * self.v + (1.0 - self.beta2) * g * g
+        mhat = self.m / (1.0 - self.beta1 ** self.t)
+        vhat = self.v / (1.0 - self.beta2 ** self.t)
+        return theta - self.lr * mhat / (np.sqrt(vhat) + self.eps)
+
+
+def in_degree(n, row_ptr, col):
+    """In-degree without self-loops, duplicates counted."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    keep = src != col
+    return np.bincount(col[keep], minlength=n).astype(np.int64)
+
+
+def scc_features(Vs, Wp, W, local, nc, sub, c, indeg, outdeg):
+    """Features [len(Vs), 4] and the per-component scale s_C for the SCC
+    vertices Vs of one level (local: component index of each, sub: A^T
+    restricted to Vs, block diagonal)."""
+    size = np.bincount(local, minlength=nc).astype(np.float64)
+    s = np.bincount(local, weights=Wp, minlength=nc) / np.maximum(size, 1.0)
+    sv = s[local]
+    safe = np.where(sv > 0, sv, 1.0)
+    R1 = Wp + c * (sub @ Wp)
+    F = np.stack([np.log1p(indeg[Vs].astype(np.float64)), np.log1p(outdeg[Vs].astype(np.float64)),
+                  np.log1p((Wp - W[Vs]) / safe), np.log1p(R1 / safe)], axis=1)
+    return F, s, R1

@@ -122,9 +122,6 @@ def solve_opts(**kw):
     o = _lib.SolveOpts()
     _lib.load().pr_default_solve_opts(C.byref(o))
     for k, v in kw.items():
-        if k == "trace":
-            o.reserved[0] = 1 if v else 0
-            continue
         if k == "warm_start":
             v = v.handle if v is not None and not isinstance(v, int) else v
         setattr(o, k, v)

@@ -36,7 +36,8 @@ class BuildOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("stop", C.c_int32), ("precision", C.c_int32),
                 ("use_graph", C.c_int32), ("eps", C.c_double), ("tol", C.c_double),
-                ("max_iter", C.c_int64), ("warm_start", C.c_void_p), ("reserved", C.c_int32 * 8)]
+                ("max_iter", C.c_int64), ("warm_start", C.c_void_p), ("trace", C.c_int32),
+                ("kernel_timing", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class SolveStats(C.Structure):
@@ -44,17 +45,22 @@ class SolveStats(C.Structure):
                 ("n_iterated", C.c_int64), ("n_not_converged", C.c_int64), ("ws_accepted", C.c_int64),
                 ("ws_rejected", C.c_int64), ("cert_abs", C.c_double), ("r_sum", C.c_double),
                 ("cert_rel", C.c_double), ("time_ms", C.c_double), ("vert_iters", C.c_int64),
-                ("kernel_ms", C.c_double), ("reserved", C.c_int32 * 8)]
+                ("kernel_ms", C.c_double), ("kt_ms", C.c_double * 4), ("kt_count", C.c_int64 * 4),
+                ("gang_edge_iters", C.c_int64), ("gang_vert_iters", C.c_int64),
+                ("reserved", C.c_int32 * 8)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "kt_ms", "kt_count")}
+        d["kt_ms"] = list(self.kt_ms)
+        d["kt_count"] = list(self.kt_count)
+        return d
 
 
 class LevelsInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n", "m", "n_comp", "n_levels", "n_scc", "n_cac", "n_singleton", "v_scc", "v_cac",
         "v_singleton", "m_scc_internal", "m_cac_internal", "m_between", "n_items", "n_gangs",
-        "n_gang_scc")] + [(k, C.c_int32) for k in ("rows_per_wave", "small_cutoff", "team_edges", "grid_wgs")]
+        "n_gang_scc", "v_gang", "m_gang_internal", "m_gang_between", "n_phases", "n_hubs")] + [(k, C.c_int32) for k in ("rows_per_wave", "small_cutoff", "team_edges", "grid_wgs")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

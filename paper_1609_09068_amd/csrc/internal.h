@@ -141,6 +141,7 @@ struct Levels {
   int32_t* ghub_pieces = nullptr; // per hub: its piece positions in edge order
   double* gpiece_part = nullptr;  // [n_pieces] piece sums of the current term
   std::vector<int32_t> h_gang_nhub;  // hubs per gang (host)
+  std::vector<int32_t> h_gang_rank;  // component ranks of the componentwise gang SCCs (host)
   int64_t n_ghubs = 0, n_gpieces = 0;
   int32_t* gdone = nullptr;       // [n_gscc + 1] iterations when converged, -1 while running
   std::vector<uint32_t> h_int_ptr, h_full_ptr;
@@ -167,6 +168,7 @@ struct Levels {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   uint64_t graph_key = 0;
+  std::vector<hipEvent_t> kev;  // per-launch timing events (kernel_timing)
   ~Levels();
 };
 

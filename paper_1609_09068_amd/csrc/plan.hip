@@ -175,6 +175,7 @@ Levels::~Levels() {
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  for (hipEvent_t e : kev) (void)hipEventDestroy(e);
   for (void* p : ps)
     if (p) (void)hipFree(p);
 }

@@ -1,34 +1,42 @@
-// The PageRank step of Sec. 3.3 on the device: one persistent kernel that
-// works through the plan's items in topological order.
+// The PageRank step of Sec. 3.3 on the device.
 //
-// What one item computes (Sec. 3.3, loops ignored):
-//  * ITEM_VERTS   up to 256 consecutive vertices that are one-vertex
-//                 components or CAC vertices.  Every in-edge of such a vertex
-//                 comes from an earlier position (a higher level, or earlier
-//                 in the CAC's topological order), so
-//                     R_v = W_v + sum_{u -> v} x_u,    x_u = c R_u / outdeg(u)
-//                 computed once (eq. PR:levels plus the one-sweep CAC rule of
-//                 Sec. 3.3.1).
-//  * ITEM_SMALL   up to four SCCs, one wavefront each, with the series terms
-//                 kept in LDS: W'_C from the rank flowing in (eq. PR:levels),
-//                 then the power series P_0 = W'_C, P_{k+1} = c A_CC^T P_k,
-//                 R_C = sum_k P_k (Sec. 3.3.2) until the stop rule holds.
-//  * ITEM_TEAM    one member of a team of workgroups that runs the same
-//                 series on one larger SCC; members share the vector through
-//                 global memory and meet at a barrier once per term.
-// Dependencies between items are data driven: x starts at -1 ("not ready")
-// and every x_u is written exactly once, with an agent-scope store, after
-// R_u is final; readers poll with agent-scope loads.  Items are handed out
-// in plan order by an atomic counter, so every item an item waits for was
-// handed out earlier to a workgroup that is running; teams are contiguous
-// in the list and never larger than half the resident grid.
+// The plan (plan.hip) orders vertices level by level from the highest level
+// down, components within a level by class and size, CAC vertices in
+// topological order.  It splits the solve into phases:
+//
+//  * segment  one persistent kernel works through a run of items in plan
+//             order; workgroups pop items from an atomic counter.
+//      ITEM_VERTS   up to 256 consecutive one-vertex components or CAC
+//                   vertices.  Every in-edge of such a vertex comes from a
+//                   higher level or from earlier in its CAC's topological
+//                   order, so R_v = W_v + sum_{u -> v} x_u with
+//                   x_u = c R_u / outdeg(u) is exact in one pass (eq.
+//                   PR:levels, Sec. 3.3.1).
+//      ITEM_SMALL   up to four SCCs, one wavefront each, terms kept in LDS
+//                   and registers.
+//      ITEM_MEDIUM  one SCC per workgroup, rows staged in LDS when they fit.
+//             SCC items gather W'_C (eq. PR:levels), then run the power
+//             series P_0 = W'_C, P_{k+1} = c A_CC^T P_k, R_C = sum_k P_k
+//             (Sec. 3.3.2) until the stop rule holds.
+//  * gang     the SCCs of a level with many internal edges (and, for the
+//             plain method, the whole graph) are iterated by every
+//             workgroup, one launch per term; each launch also reads the
+//             per-workgroup partial norms of the previous term to decide
+//             the stop, in a fixed order.  Rows with very many in-edges are
+//             summed in pieces and combined by a small launch per term.
+//
+// Dependencies inside a segment are data driven: x starts at -1 ("not
+// ready") and every x_u is written once, with an agent-scope store, after
+// R_u is final; readers poll with agent-scope loads.  Items are popped in
+// plan order, so every item an item waits for went to a running workgroup.
 //
 // Precision: series terms y_k = c P_k / outdeg and their row sums are FP32
 // (PR_PREC_MIXED) or FP64; R, W', x, the norms and every sum across rows are
 // FP64.  All reductions use a fixed order (butterflies, fixed trees, and
-// fixed-point integer sums across workgroups), so a solve is bitwise
+// per-workgroup partials summed in workgroup order), so a solve is bitwise
 // reproducible.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -120,6 +128,14 @@ __device__ inline bool timed_out(const SolveParams& p, unsigned long long t0) {
     return true;
   }
   return false;
+}
+
+// Waiting for a value another workgroup publishes: sleep 256, 512, 1024,
+// then 2048 cycles between polls, so a wavefront that waits long costs the
+// memory system little.
+__device__ inline void backoff_sleep(int& n) {
+  for (int i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(4);
+  if (n < 8) n <<= 1;
 }
 
 // Cross-lane reductions with DPP (quad_perm xor 1 / xor 2, row half mirror,
@@ -269,8 +285,9 @@ __device__ inline double lane_partial_x_wait(const SolveParams& p, const int32_t
   double acc = 0.0;
   if (lane_partial_x<STRIDE>(p, src, lo, hi, &acc)) return acc;
   const unsigned long long t0 = wall_clock64();
+  int nap = 1;
   while (true) {
-    __builtin_amdgcn_s_sleep(2);
+    backoff_sleep(nap);
     if (lane_partial_x<STRIDE>(p, src, lo, hi, &acc)) return acc;
     if (timed_out(p, t0)) return 0.0;
   }
@@ -283,8 +300,9 @@ __device__ inline double wave_gather_x_wait(const SolveParams& p, const int32_t*
   bool ok = lane_partial_x<64>(p, src, lo + lane, hi, &part);
   if (!__all(ok)) {
     const unsigned long long t0 = wall_clock64();
+    int nap = 1;
     while (true) {
-      __builtin_amdgcn_s_sleep(2);
+      backoff_sleep(nap);
       ok = lane_partial_x<64>(p, src, lo + lane, hi, &part);
       if (__all(ok)) break;
       if (timed_out(p, t0)) {
@@ -349,30 +367,43 @@ __device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const 
       idx[j] = e < ce ? src[e] : -1;
     }
     if constexpr (WAIT_X) {
-      unsigned long long t0 = 0;
-      bool first = true;
-      while (true) {
-        double v[8];
-        bool ok = true;
+      double v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = idx[j] >= 0 ? ld_x(p.x, idx[j]) : 0.0;
+      for (int j = 0; j < 8; ++j) v[j] = idx[j] >= 0 ? ld_x(p.x, idx[j]) : 0.0;
+      bool ok = true;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          ok &= v[j] >= 0.0;
-          if (idx[j] >= 0) buf[lane + 64 * j] = (VT)v[j];
+      for (int j = 0; j < 8; ++j) ok &= v[j] >= 0.0;
+      if (!__all(ok)) {
+        // poll one missing source at a time (one address for the whole
+        // wavefront), then re-read only the sources still missing
+        const unsigned long long t0 = wall_clock64();
+        int nap = 1;
+        while (true) {
+          int want = -1;
+#pragma unroll
+          for (int j = 7; j >= 0; --j)
+            if (v[j] < 0.0) want = idx[j];
+          const unsigned long long m = __ballot(want >= 0);
+          if (!m) break;
+          const int a = __shfl(want, __ffsll(m) - 1, 64);
+          bool late = false;
+          while (ld_x(p.x, a) < 0.0) {
+            if (timed_out(p, t0)) {
+              late = true;
+              break;
+            }
+            backoff_sleep(nap);
+          }
+          if (late) break;
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (v[j] < 0.0) v[j] = ld_x(p.x, idx[j]);
         }
-        if (__all(ok)) {
-          if (!first && lane == 0) atomicAdd(&t->wst[S_T_WAIT], wall_clock64() - t0);
-          break;
-        }
-        if (first) {
-          t0 = wall_clock64();
-          first = false;
-        } else if (timed_out(p, t0)) {
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
+        if (lane == 0) atomicAdd(&t->wst[S_T_WAIT], wall_clock64() - t0);
       }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (idx[j] >= 0) buf[lane + 64 * j] = (VT)v[j];
     } else {
       VT v[8];
 #pragma unroll
@@ -428,8 +459,10 @@ __device__ void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* ti
   bool done = !act;
   unsigned long long t0 = 0;
   bool first = true;
+  int nap = 1;
   volatile double* vxl = xl;
   while (true) {
+    const unsigned long long before = __ballot(done);
     if (!done && !lng) {
       while (e < hi) {
         const int u = p.int_src[e];
@@ -472,7 +505,10 @@ __device__ void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* ti
       }
       break;
     }
-    __builtin_amdgcn_s_sleep(1);
+    // a chain inside the item advances one vertex per round: no pause
+    // while lanes keep finishing
+    if (__ballot(done) != before) nap = 1;
+    else backoff_sleep(nap);
   }
 }
 
@@ -1215,13 +1251,24 @@ __global__ __launch_bounds__(kThreads) void k_reduce2(const double* part, double
     out[0] = sa;
     out[1] = sb;
   }
+  // counter q = t % 16 over workgroups t/16, t/16 + 16, ...: independent
+  // loads in flight; integer sums and maxima do not depend on the order
+  __shared__ unsigned long long lacc[kThreads];
+  const int q = threadIdx.x % kWgStats;
+  unsigned long long acc = 0;
+  for (int g = threadIdx.x / kWgStats; g < G; g += kThreads / kWgStats) {
+    const unsigned long long v = wgstats[(size_t)g * kWgStats + q];
+    acc = q == S_ITERS_MAX ? (v > acc ? v : acc) : acc + v;
+  }
+  lacc[threadIdx.x] = acc;
+  __syncthreads();
   if (threadIdx.x < kWgStats) {
-    unsigned long long acc = 0;
-    for (int g = 0; g < G; ++g) {
-      const unsigned long long v = wgstats[(size_t)g * kWgStats + threadIdx.x];
-      acc = threadIdx.x == S_ITERS_MAX ? (v > acc ? v : acc) : acc + v;
+    unsigned long long a = 0;
+    for (int j = threadIdx.x; j < kThreads; j += kWgStats) {
+      const unsigned long long v = lacc[j];
+      a = threadIdx.x == S_ITERS_MAX ? (v > a ? v : a) : a + v;
     }
-    counters[threadIdx.x] = acc;
+    counters[threadIdx.x] = a;
   }
 }
 
@@ -1412,6 +1459,7 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   std::vector<Item> items;
   GangTables T;
   std::vector<Phase> phases;
+  std::vector<std::pair<int, int>> gang_ranges;
   int64_t seg_start = 0;
   int64_t r = 0;
   while (r < K) {
@@ -1440,6 +1488,7 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
       if ((int64_t)items.size() > seg_start) phases.push_back(Phase{0, (int32_t)seg_start, (int32_t)items.size()});
       seg_start = (int64_t)items.size();
       const int vb = lv.h_comp_vbeg[large.front()], ve = lv.h_comp_vbeg[large.back() + 1];
+      gang_ranges.push_back({vb, ve});
       phases.push_back(Phase{1, (int32_t)T.gangs.size(), 0});
       add_gang(lv.h_int_ptr, G, vb, ve, large, lv.h_comp_vbeg, T);
     }
@@ -1449,6 +1498,8 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   lv.n_items = (int64_t)items.size();
   lv.n_gangs = (int64_t)T.gangs.size();
   const int64_t n_gscc_cw = (int64_t)T.sccs.size();
+  lv.h_gang_rank.clear();
+  for (const GangScc& g : T.sccs) lv.h_gang_rank.push_back(g.rank);
   // the whole-graph gang of method PLAIN comes last
   if (!lv.h_full_ptr.empty()) add_gang(lv.h_full_ptr, G, 0, (int)lv.n, std::vector<int64_t>{-1}, lv.h_comp_vbeg, T);
   lv.n_gscc = (int64_t)T.sccs.size();
@@ -1518,6 +1569,17 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   I.n_items = lv.n_items;
   I.n_gangs = lv.n_gangs;
   I.n_gang_scc = n_gscc_cw;
+  I.v_gang = I.m_gang_internal = I.m_gang_between = 0;
+  for (const auto& gr : gang_ranges) {
+    uint32_t b[2];
+    PR_HIP_CHECK(hipMemcpy(&b[0], lv.bnd_ptr + gr.first, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    PR_HIP_CHECK(hipMemcpy(&b[1], lv.bnd_ptr + gr.second, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    I.v_gang += gr.second - gr.first;
+    I.m_gang_internal += lv.h_int_ptr[gr.second] - lv.h_int_ptr[gr.first];
+    I.m_gang_between += b[1] - b[0];
+  }
+  I.n_phases = (int64_t)phases.size();
+  I.n_hubs = lv.n_ghubs;
   I.rows_per_wave = lv.opts.rows_per_wave;
   I.small_cutoff = lv.opts.small_cutoff;
   I.team_edges = lv.opts.team_edges;
@@ -1561,6 +1623,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     set_error("plan lives on device %d but device %d is current", lv.device, dev);
     return PR_EINVAL;
   }
+  const auto host_t0 = std::chrono::steady_clock::now();
   pr_solve_stats local{};
   if (lv.n == 0) {
     if (st) *st = local;
@@ -1610,7 +1673,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.gpiece_part = lv.gpiece_part;
   p.n_gslots = lv.n_gslots;
   p.timeout = (unsigned long long)clock_khz * 1000ull * 30ull;  // 30 s
-  if (o.reserved[0] == 1) {  // timeline of the segment items (tests / profiling)
+  if (o.trace == 1) {  // timeline of the segment items (tests / profiling)
     if (!lv.trace) {
       hipError_t e = hipMalloc(&lv.trace, sizeof(unsigned long long) * 4 * std::max<int64_t>(lv.n_items, 1));
       if (e != hipSuccess) {
@@ -1648,13 +1711,32 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   PR_HIP_CHECK(hipEventCreate(&ev0));
   PR_HIP_CHECK(hipEventCreate(&ev1));
   const HubFn hk = pick_hubs(o.precision);
+  // optional per-launch timing: an event after every launch, so launch i
+  // spans events i and i+1 on the solve's stream
+  const bool timing = o.kernel_timing == 1 && !o.use_graph;
+  std::vector<int> fam;
+  auto mark = [&](int f) -> int32_t {
+    if (!timing) return PR_OK;
+    const size_t i = fam.size() + 1;
+    while (lv.kev.size() <= i) {
+      hipEvent_t e;
+      PR_HIP_CHECK(hipEventCreate(&e));
+      lv.kev.push_back(e);
+    }
+    PR_HIP_CHECK(hipEventRecord(lv.kev[i], s));
+    fam.push_back(f);
+    return PR_OK;
+  };
   auto launch_gang = [&](int gang) -> int32_t {
     const int nh = lv.h_gang_nhub[gang];
     for (int64_t k = 0; k <= kb + 1; ++k) {
       const int fin = k == kb + 1 ? 1 : 0;
       hipLaunchKernelGGL(gk, dim3(lv.ggrid), dim3(kThreads), 0, s, p, gang, (int)k, fin);
-      if (nh > 0 && !fin)
+      PR_TRY(mark(1));
+      if (nh > 0 && !fin) {
         hipLaunchKernelGGL(hk, dim3((nh + kWaves - 1) / kWaves), dim3(kThreads), 0, s, p, gang, (int)k);
+        PR_TRY(mark(2));
+      }
     }
     return PR_OK;
   };
@@ -1679,12 +1761,14 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
           q.seg_head = lv.seg_heads + pi;
           void* args[] = {&q};
           PR_HIP_CHECK(hipLaunchKernel((const void*)seg, dim3(lv.grid), dim3(kThreads), args, 0, s));
+          PR_TRY(mark(0));
         }
       }
     }
     k_reduce1<<<kRedBlocks, kThreads, 0, s>>>(R, lv.n, lv.lastnorm, plain ? 1 : lv.n_comp, lv.red + 8);
     k_reduce2<<<1, kThreads, 0, s>>>(lv.red + 8, lv.red, lv.wgstats, lv.sgrid, lv.counters);
     PR_HIP_CHECK(hipGetLastError());
+    PR_TRY(mark(3));
     return PR_OK;
   };
   int32_t rc = PR_OK;
@@ -1725,6 +1809,14 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     PR_HIP_CHECK(hipEventRecord(ev1, s));
   } else {
     PR_HIP_CHECK(hipEventRecord(ev0, s));
+    if (timing) {
+      if (lv.kev.empty()) {
+        hipEvent_t e;
+        PR_HIP_CHECK(hipEventCreate(&e));
+        lv.kev.push_back(e);
+      }
+      PR_HIP_CHECK(hipEventRecord(lv.kev[0], s));
+    }
     rc = launch_all(false);
     if (rc) return rc;
     PR_HIP_CHECK(hipEventRecord(ev1, s));
@@ -1752,9 +1844,23 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   local.r_sum = red[0];
   local.cert_abs = c / (1.0 - c) * red[1];
   local.cert_rel = red[0] > 0.0 ? local.cert_abs / red[0] : 0.0;
-  local.time_ms = ms;
+  local.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host_t0).count();
   local.kernel_ms = ms;
   local.vert_iters = (int64_t)cnt[S_VERT_ITERS] + (plain ? 0 : (lv.n - lv.info.v_scc));
+  if (timing && !plain && !lv.h_gang_rank.empty()) {
+    std::vector<int32_t> it(lv.n_comp);
+    PR_HIP_CHECK(hipMemcpy(it.data(), lv.iters, sizeof(int32_t) * lv.n_comp, hipMemcpyDeviceToHost));
+    for (int32_t r : lv.h_gang_rank) {
+      local.gang_edge_iters += (int64_t)it[r] * lv.h_comp_int_edges[r];
+      local.gang_vert_iters += (int64_t)it[r] * (lv.h_comp_vbeg[r + 1] - lv.h_comp_vbeg[r]);
+    }
+  }
+  for (size_t i = 0; i < fam.size(); ++i) {
+    float d = 0.f;
+    PR_HIP_CHECK(hipEventElapsedTime(&d, lv.kev[i], lv.kev[i + 1]));
+    local.kt_ms[fam[i]] += d;
+    local.kt_count[fam[i]] += 1;
+  }
   if (st) *st = local;
   return local.n_not_converged ? PR_NOT_CONVERGED : PR_OK;
 }
