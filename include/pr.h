@@ -230,7 +230,12 @@ int32_t pr_solve(pr_levels_t* lv, double c, const void* W_dev, void* R_dev,
  * kernels, the number
  * of gang launches and ticks in single-workgroup SCC iterations), 4 = the
  * item timeline of the last solve run with trace = 1 in its options
- * (uint64[n_items x 4]: workgroup, start tick, end tick, item kind).
+ * (uint64[n_items x 4]: workgroup | item kind << 32, tick when the item was
+ * taken, tick when its rank inflow was complete, tick when it finished),
+ * 5 = the plan's work items (int32[n_items x 4]: kind 0 vertex range
+ * [a, b), 1 SCCs of ranks [a, b) one per wavefront, 2 the SCC of rank a on
+ * one workgroup; c unused), 6 = first plan position of each component rank
+ * (int32[n_comp + 1]), 7 = component id of each rank (int32[n_comp]).
  */
 int32_t pr_levels_debug(const pr_levels_t* lv, int32_t what, void* host_out);
 

@@ -84,6 +84,15 @@ class Levels:
         elif what == "trace":
             out = np.zeros((self.info()["n_items"], 4), dtype=np.uint64)
             code = 4
+        elif what == "items":
+            out = np.zeros((self.info()["n_items"], 4), dtype=np.int32)
+            code = 5
+        elif what == "rank_vbeg":
+            out = np.zeros(self.info()["n_comp"] + 1, dtype=np.int32)
+            code = 6
+        elif what == "rank_comp":
+            out = np.zeros(self.info()["n_comp"], dtype=np.int32)
+            code = 7
         else:
             raise ValueError(what)
         _lib._check(lib.pr_levels_debug(self.handle, code, out.ctypes.data_as(C.c_void_p)))

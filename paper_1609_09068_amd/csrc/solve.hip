@@ -251,6 +251,9 @@ __device__ inline double block_max(double v, double* lds) {
 // whole wavefront; a group of LPR lanes hands over rows longer than
 // max(kLongLane, 8 LPR).
 constexpr uint32_t kLongLane = 32;
+// rows of an LDS-resident SCC with more sources than this are summed by a
+// whole wavefront
+constexpr uint32_t kHubLane = 64;
 
 // this lane's share (stride STRIDE from lo) of sum x[src[e]], e in [lo, hi);
 // returns false if a source is not final yet (the sum is then garbage)
@@ -341,6 +344,7 @@ struct WaveTile {
   double racc[64];
   uint32_t rlo[64], rhi[64];
   unsigned long long* wst;  // the workgroup's counters (time accounting)
+  unsigned long long* rdy;  // latest end of a readiness wait in the current item (trace)
 };
 
 template <int RPW, typename VT, bool WAIT_X>
@@ -401,6 +405,7 @@ __device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const 
         }
         if (lane == 0) atomicAdd(&t->wst[S_T_WAIT], wall_clock64() - t0);
       }
+      if (p.trace && lane == 0) atomicMax(t->rdy, wall_clock64());
 #pragma unroll
       for (int j = 0; j < 8; ++j)
         if (idx[j] >= 0) buf[lane + 64 * j] = (VT)v[j];
@@ -436,8 +441,12 @@ __device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const 
 // ------------------------------------------------------------------ items
 
 // One-vertex components and CAC vertices (Sec. 3.3 first bullet, Sec. 3.3.1).
-// Sources inside the same item are resolved through LDS (xl), so a chain of
-// CAC vertices advances at LDS speed; other sources come from the global x.
+// R_v = W_v + (rank from higher levels) + (rank from earlier vertices of
+// v's CAC).  The CAC in-edges split into sources in earlier items, waited for
+// once through the global x, and sources inside this item, whose values are
+// exchanged through LDS (xl): a chain inside the item then advances one
+// vertex per round at LDS latency.  Sums run in a fixed order: boundary,
+// earlier-item sources, in-item sources, each in edge order.
 __device__ void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* tile, double* xl) {
   const int lane = threadIdx.x & 63;
   const int v = vbeg + (int)threadIdx.x;
@@ -450,47 +459,87 @@ __device__ void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* ti
     acc += p.W[p.perm[v]];
     p.wprime[v] = acc;
   }
-  // in-edges inside the CAC, in topological order: sources may sit in this
-  // very item, so nothing here blocks; every round lets each lane (and
-  // each long row, wavefront-wide) use what is final so far
-  uint32_t e = act ? p.int_ptr[v] : 0u;
+  const uint32_t lo = act ? p.int_ptr[v] : 0u;
   const uint32_t hi = act ? p.int_ptr[v + 1] : 0u;
-  const bool lng = (hi - e) > kLongLane;
-  bool done = !act;
+  const bool lng = (hi - lo) > kLongLane;
+  auto inside = [&](int u) { return u >= vbeg && u < vend; };
+  // sources in earlier items: independent loads four at a time, then a wait
+  // for any that is not final yet
   unsigned long long t0 = 0;
   bool first = true;
   int nap = 1;
+  if (act && !lng) {
+    for (uint32_t e = lo; e < hi; e += 4) {
+      int u[4];
+      double xv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        u[j] = e + j < hi ? p.int_src[e + j] : -1;
+        xv[j] = (u[j] >= 0 && !inside(u[j])) ? ld_x(p.x, u[j]) : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (xv[j] < 0.0) {
+          const unsigned long long tw = wall_clock64();
+          int nw = 1;
+          while ((xv[j] = ld_x(p.x, u[j])) < 0.0) {
+            if (timed_out(p, tw)) {
+              xv[j] = 0.0;
+              break;
+            }
+            backoff_sleep(nw);
+          }
+        }
+        acc += xv[j];
+      }
+    }
+  }
+  // in-item sources through LDS; rows with many CAC in-edges are summed by
+  // the whole wavefront from the global x once every source is final
+  // per-vertex constants and the pending in-item source stay in registers,
+  // so a round that only waits touches nothing but LDS
+  const double cinv = act ? p.c * p.inv64[v] : 0.0;
+  const int orig = act ? p.perm[v] : 0;
+  uint32_t e = lo;
+  int pend = -1;
+  bool done = !act;
   volatile double* vxl = xl;
   while (true) {
     const unsigned long long before = __ballot(done);
     if (!done && !lng) {
-      while (e < hi) {
-        const int u = p.int_src[e];
-        const double xv = (u >= vbeg && u < vend) ? vxl[u - vbeg] : ld_x(p.x, u);
+      while (true) {
+        if (pend < 0) {
+          while (e < hi && !inside(p.int_src[e])) ++e;
+          if (e == hi) break;
+          pend = p.int_src[e] - vbeg;
+        }
+        const double xv = vxl[pend];
         if (xv < 0.0) break;
         acc += xv;
+        pend = -1;
         ++e;
       }
       if (e == hi) {
-        const double xv = p.c * acc * p.inv64[v];
+        const double xv = cinv * acc;
         vxl[v - vbeg] = xv;
         st_x(p.x, v, xv);
-        p.Rout[p.perm[v]] = acc;
+        p.Rout[orig] = acc;
         done = true;
       }
     }
     unsigned long long m = __ballot(!done && lng);
+    bool waiting_global = m != 0;
     while (m) {
       const int b = __ffsll(m) - 1;
       m &= m - 1;
-      const uint32_t blo = __shfl(e, b, 64), bhi = __shfl(hi, b, 64);
-      double s = 0.0;
-      if (wave_gather_x_try(p, p.int_src, blo, bhi, &s) && lane == b) {
-        acc += s;
-        const double xv = p.c * acc * p.inv64[v];
+      const uint32_t blo = __shfl(lo, b, 64), bhi = __shfl(hi, b, 64);
+      double sum = 0.0;
+      if (wave_gather_x_try(p, p.int_src, blo, bhi, &sum) && lane == b) {
+        acc += sum;
+        const double xv = cinv * acc;
         vxl[v - vbeg] = xv;
         st_x(p.x, v, xv);
-        p.Rout[p.perm[v]] = acc;
+        p.Rout[orig] = acc;
         done = true;
       }
     }
@@ -500,15 +549,21 @@ __device__ void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* ti
       first = false;
     } else if (timed_out(p, t0)) {
       if (!done) {
-        p.Rout[p.perm[v]] = acc;
+        p.Rout[orig] = acc;
         st_x(p.x, v, 0.0);
       }
       break;
     }
-    // a chain inside the item advances one vertex per round: no pause
-    // while lanes keep finishing
-    if (__ballot(done) != before) nap = 1;
-    else backoff_sleep(nap);
+    // while lanes keep finishing a chain advances at LDS speed: no pause;
+    // waits on other wavefronts of the item are short, waits on the global
+    // x of long rows back off
+    if (__ballot(done) != before) {
+      nap = 1;
+    } else if (waiting_global) {
+      backoff_sleep(nap);
+    } else {
+      __builtin_amdgcn_s_sleep(1);
+    }
   }
 }
 
@@ -622,20 +677,31 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned lon
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     while (k < p.max_iter) {
       ++k;
-      YT a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      // all gathers issued before any is used (one LDS wait); unused slots
+      // read the zero pad
+      YT g[16];
+      if (nq <= 8) {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        if (q < nq) {
-          const YT val = ya[(pk[q >> 2] >> (8u * (q & 3))) & 0xffu];
-          if ((q & 3) == 0) a0 += val;
-          else if ((q & 3) == 1) a1 += val;
-          else if ((q & 3) == 2) a2 += val;
-          else a3 += val;
+        for (int q = 0; q < 8; ++q) g[q] = ya[(pk[q >> 2] >> (8u * (q & 3))) & 0xffu];
+#pragma unroll
+        for (int q = 8; q < 16; ++q) g[q] = (YT)0;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) g[q] = ya[(pk[q >> 2] >> (8u * (q & 3))) & 0xffu];
+      }
+      YT sv = (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) +
+              (((g[8] + g[9]) + (g[10] + g[11])) + ((g[12] + g[13]) + (g[14] + g[15])));
+      if (extra) {
+        for (uint32_t e = lo + 16; e < hi; e += 8) {
+          uint32_t ix[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) ix[j] = e + j < hi ? lsrc[e + j] : (uint32_t)(kSmallMax - 1);
+          YT h[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) h[j] = ya[ix[j]];
+          sv += ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));
         }
       }
-      if (extra)
-        for (uint32_t e = lo + 16; e < hi; ++e) a0 += ya[lsrc[e]];
-      const YT sv = (a0 + a1) + (a2 + a3);
       if (act) {
         R0 += (double)sv;
         if constexpr (sizeof(YT) == 8) yb[lane] = cy * sv * inv64;
@@ -676,12 +742,13 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned lon
           YT s0 = 0, s1 = 0;
           if (staged) {
             const uint32_t lo = lptr[i], hi = lptr[i + 1];
-            uint32_t e = lo;
-            for (; e + 1 < hi; e += 2) {
-              s0 += ya[lsrc[e]];
-              s1 += ya[lsrc[e + 1]];
+            for (uint32_t e = lo; e < hi; e += 8) {
+              YT h[8];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) h[j] = e + j < hi ? ya[lsrc[e + j]] : (YT)0;
+              s0 += (h[0] + h[1]) + (h[2] + h[3]);
+              s1 += (h[4] + h[5]) + (h[6] + h[7]);
             }
-            if (e < hi) s0 += ya[lsrc[e]];
           } else {
             uint32_t e = rlo[j];
             for (; e + 1 < rhi[j]; e += 2) {
@@ -775,13 +842,14 @@ __device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned
   bool conv = true;
   const unsigned long long t_it = wall_clock64();
   // LDS layout when staged: R (double) | y0 | y1 | inv (float) | ptr (u32, nv+1) | src (u16)
-  const size_t need = (size_t)nv * (8 + 2 * sizeof(YT) + 4) + 4 * (size_t)(nv + 1) + 2 * (size_t)ne + 64;
+  const size_t need = (size_t)nv * (8 + 2 * sizeof(YT) + 4) + 2 * sizeof(YT) + 4 * (size_t)(nv + 1) +
+                      2 * (size_t)ne + 64;
   const bool staged = need <= raw_bytes && nv <= 65535;
   if (staged) {
     double* lR = reinterpret_cast<double*>(raw);
-    YT* l0 = reinterpret_cast<YT*>(lR + nv);
-    YT* l1 = l0 + nv;
-    float* linv = reinterpret_cast<float*>(l1 + nv);
+    YT* l0 = reinterpret_cast<YT*>(lR + nv);  // nv terms and a zero pad
+    YT* l1 = l0 + nv + 1;
+    float* linv = reinterpret_cast<float*>(l1 + nv + 1);
     uint32_t* lptr = reinterpret_cast<uint32_t*>(linv + nv);
     uint16_t* lsrc = reinterpret_cast<uint16_t*>(lptr + nv + 1);
     for (int q = threadIdx.x; q < nv; q += kThreads) {
@@ -790,6 +858,10 @@ __device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned
       linv[q] = p.inv32[vb + q];
     }
     for (int q = threadIdx.x; q <= nv; q += kThreads) lptr[q] = ptr[vb + q] - eb;
+    if (threadIdx.x == 0) {
+      l0[nv] = (YT)0;
+      l1[nv] = (YT)0;
+    }
     for (uint32_t q = threadIdx.x; q < ne; q += kThreads) lsrc[q] = (uint16_t)(src[eb + q] - vb);
     __syncthreads();
     YT* la = l0;
@@ -800,21 +872,48 @@ __device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned
         ++k;
         part = 0.0;
         double pm = 0.0;
-        for (int r = threadIdx.x; r < nv; r += kThreads) {
-          const uint32_t lo = lptr[r], hi = lptr[r + 1];
-          YT s0 = 0, s1 = 0;
-          uint32_t e = lo;
-          for (; e + 1 < hi; e += 2) {
-            s0 += la[lsrc[e]];
-            s1 += la[lsrc[e + 1]];
-          }
-          if (e < hi) s0 += la[lsrc[e]];
-          const YT s = s0 + s1;
+        auto finish = [&](int r, YT s) {
           lR[r] += (double)s;
           if constexpr (sizeof(YT) == 8) lb[r] = cy * s * p.inv64[vb + r];
           else lb[r] = cy * s * linv[r];
           part += (double)s;
           pm = fmax(pm, (double)s);
+        };
+        for (int rb = wave * 64; rb < nv; rb += kThreads) {
+          const int r = rb + lane;
+          const uint32_t lo = r < nv ? lptr[r] : 0u, hi = r < nv ? lptr[r + 1] : 0u;
+          // a row with more than kHubLane sources is summed by the whole
+          // wavefront below; the others by their lane, eight independent
+          // gathers per step (source ids, then values: one LDS wait each)
+          const bool hub = hi - lo > kHubLane;
+          if (r < nv && !hub) {
+            YT s = 0;
+            for (uint32_t e = lo; e < hi; e += 8) {
+              uint32_t ix[8];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) ix[j] = e + j < hi ? lsrc[e + j] : (uint32_t)nv;
+              YT g[8];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) g[j] = la[ix[j]];
+              s += ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
+            }
+            finish(r, s);
+          }
+          unsigned long long m = __ballot(r < nv && hub);
+          while (m) {
+            const int b = __ffsll(m) - 1;
+            m &= m - 1;
+            const uint32_t blo = __shfl(lo, b, 64), bhi = __shfl(hi, b, 64);
+            YT s = 0;
+            for (uint32_t e = blo + lane; e < bhi; e += 256) {
+              YT g[4];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) g[j] = e + 64 * j < bhi ? la[lsrc[e + 64 * j]] : (YT)0;
+              s += (g[0] + g[1]) + (g[2] + g[3]);
+            }
+            s = wave_sum(s);
+            if (lane == b) finish(r, s);
+          }
         }
         double norm, mx;
         block_sum_max(part, pm, red, (int)(k & 1), &norm, &mx);  // the barrier also publishes lb
@@ -888,7 +987,7 @@ __device__ inline void flush_stats(const SolveParams& p, unsigned long long* s_s
 // LDS of the segment kernel: four wavefront tiles followed by the small-SCC
 // term vectors; a single-workgroup SCC may reuse all of it once its weights
 // are gathered, and a vertex item keeps its local x values in the second part.
-constexpr size_t kSegLds = 40 * 1024;
+constexpr size_t kSegLds = 53 * 1024;  // three workgroups per CU (the VGPR limit too)
 static_assert(kWaves * sizeof(WaveTile) + kWaves * 2 * kSmallMax * sizeof(double) <= kSegLds, "segment LDS");
 
 // Persistent segment kernel.  Items are handed out in plan order by one
@@ -903,9 +1002,13 @@ __global__ __launch_bounds__(kThreads) void k_segment(SolveParams p) {
   __shared__ unsigned long long s_stats[kWgStats];
   WaveTile* tiles = reinterpret_cast<WaveTile*>(s_raw);
   unsigned char* second = s_raw + kWaves * sizeof(WaveTile);
+  __shared__ unsigned long long s_ready;
   const int wave = threadIdx.x >> 6;
   if (threadIdx.x < kWgStats) s_stats[threadIdx.x] = 0ull;
-  if ((threadIdx.x & 63) == 0) tiles[wave].wst = s_stats;
+  if ((threadIdx.x & 63) == 0) {
+    tiles[wave].wst = s_stats;
+    tiles[wave].rdy = &s_ready;
+  }
   __syncthreads();
   const unsigned long long t_k = wall_clock64();
   __shared__ int s_next;
@@ -917,8 +1020,9 @@ __global__ __launch_bounds__(kThreads) void k_segment(SolveParams p) {
     const Item it = p.items[i];
     const unsigned long long t_i = wall_clock64();
     if (p.trace && threadIdx.x == 0) {
-      p.trace[4 * (size_t)(p.item_base + i)] = blockIdx.x;
+      p.trace[4 * (size_t)(p.item_base + i)] = blockIdx.x | ((unsigned long long)it.kind << 32);
       p.trace[4 * (size_t)(p.item_base + i) + 1] = t_i;
+      s_ready = t_i;
     }
     int slot;
     if (it.kind == ITEM_VERTS) {
@@ -940,9 +1044,15 @@ __global__ __launch_bounds__(kThreads) void k_segment(SolveParams p) {
     if (threadIdx.x == 0) {
       const unsigned long long t_e = wall_clock64();
       s_stats[slot] += t_e - t_i;
-      if (p.trace) p.trace[4 * (size_t)(p.item_base + i) + 2] = t_e;
+      if (p.trace) {
+        p.trace[4 * (size_t)(p.item_base + i) + 2] = s_ready;
+        p.trace[4 * (size_t)(p.item_base + i) + 3] = t_e;
+      }
     }
-    if ((threadIdx.x & 63) == 0) tiles[wave].wst = s_stats;  // a staged SCC may have overwritten it
+    if ((threadIdx.x & 63) == 0) {  // a staged SCC may have overwritten them
+      tiles[wave].wst = s_stats;
+      tiles[wave].rdy = &s_ready;
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) s_stats[S_T_SEGMENT] += wall_clock64() - t_k;
@@ -1901,24 +2011,31 @@ extern "C" int32_t pr_levels_debug(const pr_levels_t* lh, int32_t what, void* ho
     if (n) PR_HIP_CHECK(hipMemcpy(host_out, lv.perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
     return PR_OK;
   }
-  if (what == 4) {  // item timeline of the last traced solve: n_items x {wg, start, end, kind}
+  if (what == 4) {  // item timeline of the last traced solve: n_items x {wg | kind << 32, start, ready, end}
     if (!lv.trace) {
       set_error("no traced solve yet");
       return PR_EINVAL;
     }
-    std::vector<unsigned long long> t(4 * (size_t)lv.n_items);
-    std::vector<Item> it(lv.n_items);
-    if (lv.n_items) {
-      PR_HIP_CHECK(hipMemcpy(t.data(), lv.trace, sizeof(unsigned long long) * t.size(), hipMemcpyDeviceToHost));
-      PR_HIP_CHECK(hipMemcpy(it.data(), lv.items, sizeof(Item) * it.size(), hipMemcpyDeviceToHost));
-    }
-    for (int64_t i = 0; i < lv.n_items; ++i) t[4 * i + 3] = (unsigned long long)it[i].kind;
-    memcpy(host_out, t.data(), sizeof(unsigned long long) * t.size());
+    if (lv.n_items)
+      PR_HIP_CHECK(hipMemcpy(host_out, lv.trace, sizeof(unsigned long long) * 4 * lv.n_items, hipMemcpyDeviceToHost));
     return PR_OK;
   }
   if (what == 3) {  // per-workgroup counters of the last solve: grid_wgs x 16 uint64
     PR_HIP_CHECK(hipMemcpy(host_out, lv.wgstats, sizeof(unsigned long long) * kWgStats * lv.sgrid,
                            hipMemcpyDeviceToHost));
+    return PR_OK;
+  }
+  if (what == 5) {  // the plan's items: n_items x {kind, a, b, c} (int32)
+    if (lv.n_items)
+      PR_HIP_CHECK(hipMemcpy(host_out, lv.items, sizeof(Item) * lv.n_items, hipMemcpyDeviceToHost));
+    return PR_OK;
+  }
+  if (what == 6) {  // per component rank: first plan position (int32[n_comp + 1])
+    memcpy(host_out, lv.h_comp_vbeg.data(), sizeof(int32_t) * (K + 1));
+    return PR_OK;
+  }
+  if (what == 7) {  // per component rank: the partition's component id (int32[n_comp])
+    if (K) memcpy(host_out, lv.h_comp_id_of_rank.data(), sizeof(int32_t) * K);
     return PR_OK;
   }
   set_error("unknown debug array %d", what);
