@@ -239,6 +239,65 @@ int32_t pr_solve(pr_levels_t* lv, double c, const void* W_dev, void* R_dev,
  */
 int32_t pr_levels_debug(const pr_levels_t* lv, int32_t what, void* host_out);
 
+/* ------------------------------------------------------ starting guess
+ *
+ * The paper starts each SCC's power series from P_0 = W'_C (Sec. 3.3.2) and
+ * names an earlier ranking as a possible initial rank (Sec. 5).  This part
+ * learns a start: a network 4 -> 64 -> 64 -> 1 (GELU after both hidden
+ * layers; BF16 operands on the matrix cores, FP32 accumulation) maps four
+ * features of an SCC vertex v,
+ *   f0 = log(1 + in-degree), f1 = log(1 + out-degree)   (loops ignored),
+ *   f2 = log(1 + (W'_v - W_v) / s_C),  f3 = log(1 + R1_v / s_C),
+ *   s_C = ||W'_C||_1 / |C|,  R1 = W'_C + c A_CC^T W'_C   (one series step),
+ * to y_v, and R_0,v = s_C exp(y_v).  With pr_solve_opts.warm_start set, each
+ * SCC forms r_0 = W'_C + c A_CC^T R_0 - R_0 (FP64) and keeps the guess when
+ * ||r_0||_1 < ||c A_CC^T W'_C||_1: its series then runs on r_0 and
+ * R_C = R_0 + sum_k (c A_CC^T)^k r_0, which is the same R_C (Def. 3.5).
+ * Otherwise it starts from W'_C as without a guess.
+ *
+ * Parameters: one flat float vector of 4545 values, in this order:
+ * W1 [64 x 4] row-major, b1 [64], W2 [64 x 64] row-major, b2 [64],
+ * W3 [64], b3 [1].  Training: Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the
+ * mean squared error over a batch; FP32 master weights, BF16 copies.
+ * All calls return PR_EHANDLE for a handle that is not a live pr_mlp_t and
+ * PR_EINVAL when the device current now is not the one the network was made
+ * on.  Device buffers are the caller's and are not kept past the call.
+ */
+#define PR_MLP_PARAMS 4545
+
+/* New network on the current device, weights uniform in
+ * (-1/sqrt(fan_in), 1/sqrt(fan_in)) from a counter-based stream of `seed`. */
+int32_t pr_mlp_create(uint64_t seed, pr_mlp_t** out);
+/* Replace the weights (host float[4545]); resets the Adam state.
+ * PR_EINVAL if a value is not finite. */
+int32_t pr_mlp_set_params(pr_mlp_t* mlp, const float* host_params);
+/* Copy the FP32 weights to host float[4545]. */
+int32_t pr_mlp_get_params(const pr_mlp_t* mlp, float* host_out);
+/* y_dev[i] = network(X_dev[4i .. 4i+3]) for i < n (device floats, row-major
+ * features); returns after the stream work completes. */
+int32_t pr_mlp_predict(const pr_mlp_t* mlp, int64_t n, const float* X_dev, float* y_dev, void* hip_stream);
+/* Gradient of the mean squared error (1/n) sum_i (y_i - t_i)^2 over the n
+ * rows (X_dev float[n x 4], t_dev float[n], device) without a step:
+ * grad_host float[4545] (nullable), *loss = the mean squared error. */
+int32_t pr_mlp_grad(pr_mlp_t* mlp, int64_t n, const float* X_dev, const float* t_dev, float* grad_host,
+                    double* loss, void* hip_stream);
+/* One Adam step with learning rate lr on the batch; *loss (nullable) = the
+ * batch's mean squared error before the step.  PR_EINVAL for n <= 0 or a
+ * learning rate that is not positive and finite. */
+int32_t pr_mlp_train_step(pr_mlp_t* mlp, int64_t n, const float* X_dev, const float* t_dev, float lr,
+                          double* loss, void* hip_stream);
+/* Weights and Adam state to / from a file ("PRMLP001", int32 4545, int64
+ * step, float[3 x 4545]: weights, first and second moments).  pr_mlp_load
+ * returns PR_EINVAL for a file that is not in this format. */
+int32_t pr_mlp_save(const pr_mlp_t* mlp, const char* path);
+int32_t pr_mlp_load(const char* path, pr_mlp_t** out);
+/* Features of every SCC vertex from the weights W' of the last pr_solve on
+ * this plan (training data): F_dev float[n x 4] (the features above,
+ * caller's vertex order), s_dev float[n] (s_C), mask_dev uint8[n] (1 for a
+ * vertex of an SCC, else 0 and zero features).  W_dev: the W of that solve. */
+int32_t pr_warm_features(const pr_levels_t* lv, double c, const void* W_dev, float* F_dev, float* s_dev,
+                         uint8_t* mask_dev, void* hip_stream);
+
 /* --------------------------------------------------------------- common */
 
 /* Release any handle; NULL, unknown and already-released handles are ignored. */

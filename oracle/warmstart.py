@@ -147,3 +147,46 @@ def scc_features(Vs, Wp, W, local, nc, sub, c, indeg, outdeg):
     F = np.stack([np.log1p(indeg[Vs].astype(np.float64)), np.log1p(outdeg[Vs].astype(np.float64)),
                   np.log1p((Wp - W[Vs]) / safe), np.log1p(R1 / safe)], axis=1)
     return F, s, R1
+
+
+GELU_LIPSCHITZ = 1.1289  # max over x of |d/dx x Phi(x)| (at x = +-sqrt(2))
+
+
+def forward_bf16_bound(theta, X, u=2.0 ** -8):
+    """First-order bound on |y_computed - y| when every matrix-product operand
+    (weights, features, hidden activations) is rounded to bfloat16 (unit
+    roundoff u) and products are summed exactly: per layer, rounding both
+    factors of each product adds at most 2u |W||h|, an input error e adds
+    |W| e, and GELU multiplies errors by at most GELU_LIPSCHITZ."""
+    P = unpack(theta)
+    Xs = np.asarray(X, dtype=np.float64)
+    _, c = forward(theta, Xs, keep=True)
+    X = np.abs(Xs)
+    aW1, aW2, aW3 = np.abs(P["W1"]), np.abs(P["W2"]), np.abs(P["W3"][0])
+    e1 = 2 * u * (X @ aW1.T)
+    eh1 = GELU_LIPSCHITZ * e1
+    h1 = np.abs(c["h1"])
+    e2 = 2 * u * (h1 @ aW2.T) + eh1 @ aW2.T
+    eh2 = GELU_LIPSCHITZ * e2
+    h2 = np.abs(c["h2"])
+    return 2 * u * (h2 @ aW3) + eh2 @ aW3
+
+
+def to_bf16(a):
+    """Round to bfloat16 (nearest even) through the float32 bit pattern."""
+    f = np.asarray(a, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(theta, X):
+    """The network with every matrix-product operand rounded to bfloat16 and
+    everything else (sums, biases, GELU) in float64: the arithmetic a
+    BF16-operand, wide-accumulator implementation performs, up to the order of
+    its sums."""
+    P = unpack(theta)
+    X = np.asarray(X, dtype=np.float64)
+    h1 = gelu(to_bf16(X) @ to_bf16(P["W1"]).T + P["b1"])
+    h2 = gelu(to_bf16(h1) @ to_bf16(P["W2"]).T + P["b2"])
+    return to_bf16(h2) @ to_bf16(P["W3"][0]) + P["b3"][0]

@@ -110,6 +110,105 @@ class Levels:
             pass
 
 
+class Mlp:
+    """Owner of a pr_mlp_t handle: the starting-guess network."""
+
+    N_PARAMS = 4545
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    @classmethod
+    def create(cls, seed=0):
+        h = C.c_void_p()
+        _lib._check(_lib.load().pr_mlp_create(C.c_uint64(seed), C.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def load_file(cls, path):
+        h = C.c_void_p()
+        _lib._check(_lib.load().pr_mlp_load(str(path).encode(), C.byref(h)))
+        return cls(h.value)
+
+    def save(self, path):
+        _lib._check(_lib.load().pr_mlp_save(self.handle, str(path).encode()))
+
+    def get_params(self):
+        out = np.zeros(self.N_PARAMS, dtype=np.float32)
+        _lib._check(_lib.load().pr_mlp_get_params(self.handle, _lib._ptr(out, C.c_float)))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        if theta.shape != (self.N_PARAMS,):
+            raise ValueError("expected 4545 parameters")
+        _lib._check(_lib.load().pr_mlp_set_params(self.handle, _lib._ptr(theta, C.c_float)))
+
+    def predict(self, X, stream=None):
+        """X: float32 device tensor [n, 4]; returns a float32 device tensor [n]."""
+        import torch
+
+        _need_f32_dev(X, 2)
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _lib._check(_lib.load().pr_mlp_predict(self.handle, X.shape[0], C.c_void_p(X.data_ptr()),
+                                               C.c_void_p(y.data_ptr()), C.c_void_p(_stream_ptr(stream))))
+        return y
+
+    def grad(self, X, t, stream=None):
+        """Gradient of the mean squared error on (X, t); returns (grad [4545], loss)."""
+        _need_f32_dev(X, 2)
+        _need_f32_dev(t, 1)
+        g = np.zeros(self.N_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        _lib._check(_lib.load().pr_mlp_grad(self.handle, X.shape[0], C.c_void_p(X.data_ptr()),
+                                            C.c_void_p(t.data_ptr()), _lib._ptr(g, C.c_float), C.byref(loss),
+                                            C.c_void_p(_stream_ptr(stream))))
+        return g, loss.value
+
+    def train_step(self, X, t, lr, stream=None):
+        _need_f32_dev(X, 2)
+        _need_f32_dev(t, 1)
+        loss = C.c_double()
+        _lib._check(_lib.load().pr_mlp_train_step(self.handle, X.shape[0], C.c_void_p(X.data_ptr()),
+                                                  C.c_void_p(t.data_ptr()), C.c_float(lr), C.byref(loss),
+                                                  C.c_void_p(_stream_ptr(stream))))
+        return loss.value
+
+    def free(self):
+        if self.handle:
+            _lib.load().pr_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _need_f32_dev(x, dim):
+    if not x.is_cuda or x.dtype.itemsize != 4 or not x.dtype.is_floating_point or x.dim() != dim \
+            or not x.is_contiguous():
+        raise TypeError(f"expected a contiguous float32 device tensor of dimension {dim}")
+    if dim == 2 and x.shape[1] != 4:
+        raise ValueError("features must have 4 columns")
+
+
+def warm_features(levels: "Levels", c, W, stream=None):
+    """Features, component scale and SCC mask of every vertex from the last solve
+    of `levels` with weights W (see pr_warm_features)."""
+    import torch
+
+    n = levels.n
+    F = torch.empty((n, 4), dtype=torch.float32, device=W.device)
+    S = torch.empty(n, dtype=torch.float32, device=W.device)
+    M = torch.empty(n, dtype=torch.uint8, device=W.device)
+    _lib._check(_lib.load().pr_warm_features(levels.handle, float(c), C.c_void_p(W.data_ptr()),
+                                             C.c_void_p(F.data_ptr()), C.c_void_p(S.data_ptr()),
+                                             C.c_void_p(M.data_ptr()), C.c_void_p(_stream_ptr(stream))))
+    return F, S, M
+
+
 def pr_partition(row_ptr, col) -> Partition:
     row_ptr, col = _lib._as_csr(row_ptr, col)
     n = len(row_ptr) - 1

@@ -50,10 +50,6 @@ bool registry_remove(void* h, HandleKind* k) {
 
 using namespace prlib;
 
-// pr_mlp is released through a function defined with the learned part.
-namespace prlib {
-void mlp_destroy(void* h);
-}
 
 extern "C" {
 

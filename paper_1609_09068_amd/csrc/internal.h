@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdint>
 #include <cstring>
@@ -10,6 +11,7 @@
 #include <vector>
 
 #include "../../include/pr.h"
+#include "mlp_dev.h"
 
 namespace prlib {
 
@@ -24,6 +26,12 @@ void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
                        __FILE__, __LINE__);                                         \
       return PR_EHIP;                                                               \
     }                                                                               \
+  } while (0)
+
+#define PR_TRY(x)                 \
+  do {                            \
+    int32_t rc_ = (x);            \
+    if (rc_ != PR_OK) return rc_; \
   } while (0)
 
 // ---------------------------------------------------------------- handles
@@ -171,6 +179,23 @@ struct Levels {
   std::vector<hipEvent_t> kev;  // per-launch timing events (kernel_timing)
   ~Levels();
 };
+
+// ------------------------------------------------------ starting guesses
+struct Mlp {
+  int device = 0;
+  float* master = nullptr;     // [kMlpParams] FP32 weights (flat, see mlp_dev.h)
+  float* mom1 = nullptr;       // Adam first moments
+  float* mom2 = nullptr;       // Adam second moments
+  float* grad = nullptr;       // last batch gradient
+  double* loss = nullptr;      // last batch sum of squared errors
+  MlpPacked* packed = nullptr; // BF16 fragments used by every kernel
+  float* gpart = nullptr;      // per-wavefront partial gradients
+  double* lpart = nullptr;
+  int64_t gpart_cap = 0;
+  int64_t step = 0;
+  ~Mlp();
+};
+void mlp_destroy(void* h);
 
 int32_t build_levels(const Partition& p, const int64_t* row_ptr, const int32_t* col,
                      const pr_build_opts& opts, hipStream_t stream, Levels& lv);

@@ -161,11 +161,6 @@ int32_t dalloc(T** p, size_t count) {
 
 }  // namespace
 
-#define PR_TRY(x)              \
-  do {                         \
-    int32_t rc_ = (x);         \
-    if (rc_ != PR_OK) return rc_; \
-  } while (0)
 
 Levels::~Levels() {
   void* ps[] = {perm, comp_vbeg, comp_rank_of_id, comp_id_of_rank, bnd_ptr, bnd_src, int_ptr, int_src,

@@ -1426,11 +1426,6 @@ GangFn pick_gang(int precision, int rpw) {
 
 }  // namespace
 
-#define PR_TRY(x)                 \
-  do {                            \
-    int32_t rc_ = (x);            \
-    if (rc_ != PR_OK) return rc_; \
-  } while (0)
 
 // launch sizes: a segment uses every workgroup slot the device keeps
 // resident; a gang launch up to eight workgroups per compute unit

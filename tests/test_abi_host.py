@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     assert "pr_partition" in names and "pr_solve" in names and "pr_free" in names
     for name in names:
         assert hasattr(lib, name), name
-    assert set(names) <= set(_lib.EXPORTS) | {n for n in names if n.startswith("pr_mlp")}
+    assert set(names) == set(_lib.EXPORTS)
 
 
 def test_partition_fig1_and_errors():

@@ -159,3 +159,23 @@ def test_small_config_warm_start():
     R, st = componentwise_solve(g.n, g.row_ptr, g.col, c, W, eps=1e-10, return_stats=True,
                                 warm=ws.init_params(0))
     assert np.abs(R - ref).sum() / ref.sum() < 1e-10
+
+
+def test_bf16_rounding():
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: nearest even keeps 1
+    assert ws.to_bf16(1.0 + 2.0 ** -8) == 1.0
+    assert ws.to_bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6
+    assert ws.to_bf16(-3.0) == -3.0
+    x = np.random.default_rng(2).normal(size=1000)
+    assert np.all(np.abs(ws.to_bf16(x) - x) <= 2.0 ** -8 * np.abs(x))
+
+
+def test_bf16_bound_covers_emulated_rounding():
+    rng = np.random.default_rng(7)
+    th = ws.init_params(9) * 3.0
+    X = np.column_stack([rng.uniform(0, 7, 500), rng.uniform(0, 7, 500), rng.uniform(0, 3, 500),
+                         rng.uniform(0, 4, 500)])
+    err = np.abs(ws.forward_bf16(th, X) - ws.forward(th, X))
+    bound = ws.forward_bf16_bound(th, X)
+    assert np.all(err <= bound)
+    assert err.max() > 0.0
