@@ -177,6 +177,8 @@ struct Levels {
   hipGraphExec_t graph_exec = nullptr;
   uint64_t graph_key = 0;
   std::vector<hipEvent_t> kev;  // per-launch timing events (kernel_timing)
+  double* warm_buf = nullptr;   // starting-guess scratch (allocated on first use)
+  int32_t* warm_gws = nullptr;  // [n_gscc] per gang SCC: guess kept / not / none
   ~Levels();
 };
 

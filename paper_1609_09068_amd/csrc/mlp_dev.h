@@ -104,16 +104,21 @@ __device__ inline float mlp_forward16(const MlpPacked& w, bf16x4 xb) {
 
 // Forward pass for up to 64 rows held one per lane (features f0..f3 of the
 // lane's row; inactive lanes pass anything).  Returns the lane's output.
+// The weights are read from memory (L1/L2) for each block rather than held
+// in registers, so a kernel that embeds this keeps its register budget.
 __device__ inline float mlp_forward64(const MlpPacked& w, float f0, float f1, float f2, float f3) {
   const int lane = threadIdx.x & 63;
   float out = 0.f;
-#pragma unroll
+#pragma unroll 1
   for (int b = 0; b < 4; ++b) {
+    uint64_t wa = (uint64_t)(uintptr_t)&w;
+    asm volatile("" : "+v"(wa));  // not loop-invariant: the loads stay inside the loop
+    const MlpPacked* wb = (const MlpPacked*)(uintptr_t)wa;
     const int srcl = 16 * b + (lane & 15);
     const float a0 = __shfl(f0, srcl, 64), a1 = __shfl(f1, srcl, 64);
     const float a2 = __shfl(f2, srcl, 64), a3 = __shfl(f3, srcl, 64);
     const bf16x4 xb = lane < 16 ? pack4(a0, a1, a2, a3) : pack4(0.f, 0.f, 0.f, 0.f);
-    const float y = mlp_forward16(w, xb);
+    const float y = mlp_forward16(*wb, xb);
     // row 16b + i came out on lane i
     const float yb = __shfl(y, lane & 15, 64);
     if ((lane >> 4) == b) out = yb;

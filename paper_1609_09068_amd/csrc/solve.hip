@@ -77,6 +77,20 @@ struct SolveParams {
   double* x;
   double* R;
   double* wprime;
+  // starting guess (null: start every SCC from W'_C)
+  const MlpPacked* mlp;
+  double* wr0;   // [n] R_0 of the guess
+  double* wx;    // [n] c R_0 / outdeg
+  double* wres;  // [n] r_0 = W' + c A^T R_0 - R_0
+  // starting guess of gang SCCs: per-workgroup partial norms of the first
+  // plain term, of r_0 and max |r_0| (slot layout of gpart), then per SCC
+  // the decision (1 kept, 0 not, -1 none), ||r_0||_1 and max |r_0|
+  double* gwp1;
+  double* gwr0;
+  double* gwm0;
+  int32_t* gws;
+  double* gwn;
+  double* gwm;
   void* y0;
   void* y1;
   const Item* items;
@@ -571,25 +585,110 @@ __device__ inline bool stop_now(const SolveParams& p, double norm, double mx, do
   return p.stop == PR_STOP_CERT_L1 ? (norm <= thresh) : (mx < p.tol);
 }
 
+// k: terms of the series; ws: -1 no starting guess, 0 guess rejected, 1
+// kept (a guess costs two more passes over the component's edges)
 __device__ inline void record_scc(const SolveParams& p, int rank, int64_t k, double last, bool conv, uint64_t ne,
-                                  uint64_t nv, unsigned long long* wst, bool lds_stats) {
+                                  uint64_t nv, unsigned long long* wst, bool lds_stats, int ws = -1) {
   p.iters[rank] = (int32_t)k;
   p.lastnorm[rank] = last;
+  const unsigned long long passes = (unsigned long long)k + (ws >= 0 ? 2ull : 0ull);
   if (lds_stats) {
-    atomicAdd(&wst[S_EDGE_ITERS], (unsigned long long)k * ne);
-    atomicAdd(&wst[S_VERT_ITERS], (unsigned long long)k * nv);
+    atomicAdd(&wst[S_EDGE_ITERS], passes * ne);
+    atomicAdd(&wst[S_VERT_ITERS], passes * nv);
     atomicMax(&wst[S_ITERS_MAX], (unsigned long long)k);
     atomicAdd(&wst[S_ITERS_SUM], (unsigned long long)k);
     atomicAdd(&wst[S_N_ITERATED], 1ull);
     if (!conv) atomicAdd(&wst[S_NOT_CONV], 1ull);
+    if (ws == 1) atomicAdd(&wst[S_WS_ACC], 1ull);
+    if (ws == 0) atomicAdd(&wst[S_WS_REJ], 1ull);
   } else {
-    wst[S_EDGE_ITERS] += (unsigned long long)k * ne;
-    wst[S_VERT_ITERS] += (unsigned long long)k * nv;
+    wst[S_EDGE_ITERS] += passes * ne;
+    wst[S_VERT_ITERS] += passes * nv;
     if ((unsigned long long)k > wst[S_ITERS_MAX]) wst[S_ITERS_MAX] = (unsigned long long)k;
     wst[S_ITERS_SUM] += (unsigned long long)k;
     wst[S_N_ITERATED] += 1ull;
     if (!conv) wst[S_NOT_CONV] += 1ull;
+    if (ws == 1) wst[S_WS_ACC] += 1ull;
+    if (ws == 0) wst[S_WS_REJ] += 1ull;
   }
+}
+
+// ---------------------------------------------------------- starting guess
+// For the SCC on rows [vbeg, vbeg + nv), run by a group of G threads (one
+// wavefront, G = 64, or the workgroup, G = kThreads) once its W' is final:
+// the network's guess R_0 from the four features, the residual
+// r_0 = W' + c A^T R_0 - R_0 in FP64 (into wr0 / wres), and the decision to
+// keep it: ||r_0||_1 < ||c A^T W'||_1, the first term of the plain start.
+// Every thread of the group returns the same decision, and with it
+// ||r_0||_1 and max |r_0|.
+struct WarmOut {
+  bool keep;
+  double n_r0, m_r0;
+};
+
+template <int G>
+__device__ WarmOut warm_preamble(const SolveParams& p, int vbeg, int nv, double wsum, double* red) {
+  const int tid = G == 64 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  auto gsum = [&](double v) { return G == 64 ? wave_sum(v) : block_sum(v, red); };
+  auto gmax = [&](double v) { return G == 64 ? wave_max(v) : block_max(v, red); };
+  auto gsync = [&]() {
+    if constexpr (G == 64) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    else __syncthreads();
+  };
+  WarmOut o{false, 0.0, 0.0};
+  gsync();  // every W' of the component is visible to the group
+  const double s = wsum / (double)nv;
+  if (!(s > 0.0)) return o;
+  double np1 = 0.0;
+  for (int base = 0; base < nv; base += G) {  // uniform trip count: the network needs whole wavefronts
+    const int i = base + tid;
+    const bool act = i < nv;
+    const int v = vbeg + i;
+    float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
+    double inv = 0.0;
+    if (act) {
+      const double wpv = p.wprime[v];
+      inv = p.inv64[v];
+      const uint32_t lo = p.int_ptr[v], hi = p.int_ptr[v + 1];
+      double acc = 0.0;
+      for (uint32_t e = lo; e < hi; ++e) {
+        const int u = p.int_src[e];
+        acc += p.wprime[u] * p.inv64[u];
+      }
+      const double p1 = p.c * acc;
+      np1 += fabs(p1);
+      const double indeg = (double)((p.bnd_ptr[v + 1] - p.bnd_ptr[v]) + (hi - lo));
+      f0 = (float)log1p(indeg);
+      f1 = (float)log1p(rint(1.0 / inv));
+      f2 = (float)log1p((wpv - p.W[p.perm[v]]) / s);
+      f3 = (float)log1p((wpv + p1) / s);
+    }
+    const float y = mlp_forward64(*p.mlp, f0, f1, f2, f3);
+    if (act) {
+      const double r0 = s * exp((double)y);
+      p.wr0[v] = r0;
+      p.wx[v] = p.c * r0 * inv;
+    }
+  }
+  np1 = gsum(np1);
+  gsync();
+  double nr0 = 0.0, mr0 = 0.0;
+  for (int i = tid; i < nv; i += G) {
+    const int v = vbeg + i;
+    double acc = 0.0;
+    for (uint32_t e = p.int_ptr[v]; e < p.int_ptr[v + 1]; ++e) acc += p.wx[p.int_src[e]];
+    const double r = p.wprime[v] + acc - p.wr0[v];
+    p.wres[v] = r;
+    nr0 += fabs(r);
+    mr0 = fmax(mr0, fabs(r));
+  }
+  nr0 = gsum(nr0);
+  mr0 = gmax(mr0);
+  gsync();
+  o.keep = nr0 < np1;  // false for a non-finite guess
+  o.n_r0 = nr0;
+  o.m_r0 = mr0;
+  return o;
 }
 
 // An SCC with at most 256 vertices, iterated by one wavefront.  After the
@@ -597,7 +696,7 @@ __device__ inline void record_scc(const SolveParams& p, int rank, int64_t k, dou
 // (one-byte local source ids, two-byte row offsets) when they fit, so every
 // term touches only LDS and registers (R stays in registers, four rows per
 // lane).
-template <typename YT>
+template <typename YT, bool WARM>
 __device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned long long* wst, WaveTile* tile) {
   const int lane = threadIdx.x & 63;
   const int vbeg = p.comp_vbeg[rank];
@@ -650,7 +749,29 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned lon
   int64_t k = 0;
   double last = wsum;
   bool conv = true;
-  if (staged && nv <= 64 && !(p.stop == PR_STOP_CERT_L1 && wsum == 0.0)) {
+  bool skip = p.stop == PR_STOP_CERT_L1 && wsum == 0.0;
+  int ws = -1;
+  if (WARM && !skip) {
+    const WarmOut w = warm_preamble<64>(p, vbeg, nv, wsum, nullptr);
+    ws = w.keep ? 1 : 0;
+    if (w.keep) {  // start from R_0 + r_0 with the term r_0
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = lane + 64 * j;
+        if (i < nv) {
+          const int v = vbeg + i;
+          const double r = p.wres[v];
+          Rj[j] = p.wr0[v] + r;
+          if constexpr (sizeof(YT) == 8) ya[i] = (YT)(p.c * r * p.inv64[v]);
+          else ya[i] = (YT)(p.c * r * (double)inv[j]);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      last = w.n_r0;
+      if (stop_now(p, w.n_r0, w.m_r0, thresh)) skip = true;  // the guess already meets the rule
+    }
+  }
+  if (staged && nv <= 64 && !skip) {
     // one row per lane; its first 16 sources packed in registers (entry 255
     // of the term buffers is a zero pad for lanes with fewer sources)
     conv = false;
@@ -707,7 +828,7 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned lon
         if constexpr (sizeof(YT) == 8) yb[lane] = cy * sv * inv64;
         else yb[lane] = cy * sv * inv[0];
       }
-      const double sd = act ? (double)sv : 0.0;
+      const double sd = act ? fabs((double)sv) : 0.0;
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       YT* t = ya;
       ya = yb;
@@ -729,7 +850,7 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned lon
       }
     }
     Rj[0] = R0;
-  } else if (!(p.stop == PR_STOP_CERT_L1 && wsum == 0.0)) {
+  } else if (!skip) {
     conv = false;
     while (k < p.max_iter) {
       ++k;
@@ -761,8 +882,8 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned lon
           Rj[j] += (double)s;
           if constexpr (sizeof(YT) == 8) yb[i] = cy * s * p.inv64[vbeg + i];
           else yb[i] = cy * s * inv[j];
-          part += (double)s;
-          pm = fmax(pm, (double)s);
+          part += fabs((double)s);
+          pm = fmax(pm, fabs((double)s));
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -787,14 +908,14 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned lon
       st_x(p.x, v, p.c * Rj[j] * p.inv64[v]);
     }
   }
-  if (lane == 0) record_scc(p, rank, k, last, conv, ne, (uint64_t)nv, wst, true);
+  if (lane == 0) record_scc(p, rank, k, last, conv, ne, (uint64_t)nv, wst, true, ws);
 }
 
 // One SCC iterated by one workgroup.  When the component fits, its rows
 // (two-byte local sources), 1/outdeg, R and both term vectors live in LDS
 // during the iteration; otherwise the vectors stay in global memory, touched
 // only by this workgroup.
-template <typename YT, int RPW>
+template <typename YT, int RPW, bool WARM>
 __device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned long long* wst, WaveTile* tiles,
                            unsigned char* raw, size_t raw_bytes) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -840,6 +961,24 @@ __device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned
   int64_t k = 0;
   double last = wsum;
   bool conv = true;
+  bool skip = p.stop == PR_STOP_CERT_L1 && wsum == 0.0;
+  int ws = -1;
+  if (WARM && !skip) {
+    const WarmOut w = warm_preamble<kThreads>(p, vb, nv, wsum, red);
+    ws = w.keep ? 1 : 0;
+    if (w.keep) {  // start from R_0 + r_0 with the term r_0
+      for (int i = threadIdx.x; i < nv; i += kThreads) {
+        const int v = vb + i;
+        const double r = p.wres[v];
+        p.R[v] = p.wr0[v] + r;
+        if constexpr (sizeof(YT) == 8) ya[v] = c * r * p.inv64[v];
+        else ya[v] = (YT)(c * r * (double)p.inv32[v]);
+      }
+      __syncthreads();
+      last = w.n_r0;
+      if (stop_now(p, w.n_r0, w.m_r0, thresh)) skip = true;  // the guess already meets the rule
+    }
+  }
   const unsigned long long t_it = wall_clock64();
   // LDS layout when staged: R (double) | y0 | y1 | inv (float) | ptr (u32, nv+1) | src (u16)
   const size_t need = (size_t)nv * (8 + 2 * sizeof(YT) + 4) + 2 * sizeof(YT) + 4 * (size_t)(nv + 1) +
@@ -866,7 +1005,7 @@ __device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned
     __syncthreads();
     YT* la = l0;
     YT* lb = l1;
-    if (!(p.stop == PR_STOP_CERT_L1 && wsum == 0.0)) {
+    if (!skip) {
       conv = false;
       while (k < p.max_iter) {
         ++k;
@@ -876,8 +1015,8 @@ __device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned
           lR[r] += (double)s;
           if constexpr (sizeof(YT) == 8) lb[r] = cy * s * p.inv64[vb + r];
           else lb[r] = cy * s * linv[r];
-          part += (double)s;
-          pm = fmax(pm, (double)s);
+          part += fabs((double)s);
+          pm = fmax(pm, fabs((double)s));
         };
         for (int rb = wave * 64; rb < nv; rb += kThreads) {
           const int r = rb + lane;
@@ -933,7 +1072,7 @@ __device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned
       st_x(p.x, vb + q, c * r * p.inv64[vb + q]);
     }
   } else {
-    if (!(p.stop == PR_STOP_CERT_L1 && wsum == 0.0)) {
+    if (!skip) {
       conv = false;
       while (k < p.max_iter) {
         ++k;
@@ -947,8 +1086,8 @@ __device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned
             p.R[v] += (double)s;
             if constexpr (sizeof(YT) == 8) yb[v] = cy * s * p.inv64[v];
             else yb[v] = cy * s * p.inv32[v];
-            part += (double)s;
-            pm = fmax(pm, (double)s);
+            part += fabs((double)s);
+            pm = fmax(pm, fabs((double)s));
           }
         }
         double norm, mx;
@@ -971,7 +1110,7 @@ __device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned
   }
   if (threadIdx.x == 0) {
     wst[S_T_MEDIUM_ITER] += wall_clock64() - t_it;
-    record_scc(p, rank, k, last, conv, ne, (uint64_t)nv, wst, false);
+    record_scc(p, rank, k, last, conv, ne, (uint64_t)nv, wst, false, ws);
   }
 }
 
@@ -995,7 +1134,7 @@ static_assert(kWaves * sizeof(WaveTile) + kWaves * 2 * kSmallMax * sizeof(double
 // whatever the number of resident workgroups: an item only waits for items
 // handed out before it, and those are held by running workgroups; the
 // lowest unfinished item has nothing left to wait for.
-template <typename YT, int RPW>
+template <typename YT, int RPW, bool WARM>
 __global__ __launch_bounds__(kThreads) void k_segment(SolveParams p) {
   __shared__ double s_red[16];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kSegLds];
@@ -1034,10 +1173,10 @@ __global__ __launch_bounds__(kThreads) void k_segment(SolveParams p) {
     } else if (it.kind == ITEM_SMALL) {
       const int r = it.a + wave;
       YT* ybuf = reinterpret_cast<YT*>(second) + (size_t)wave * 2 * kSmallMax;
-      if (r < it.b) run_small<YT>(p, r, ybuf, s_stats, &tiles[wave]);
+      if (r < it.b) run_small<YT, WARM>(p, r, ybuf, s_stats, &tiles[wave]);
       slot = S_T_SMALL;
     } else {
-      run_medium<YT, RPW>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
+      run_medium<YT, RPW, WARM>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
       slot = S_T_MEDIUM;
     }
     __syncthreads();
@@ -1122,8 +1261,12 @@ __device__ inline void gang_finalise(const SolveParams& p, const GangScc& sc, co
       p.lastnorm[0] = last;
     }
     const uint64_t ne = p.int_ptr[sc.vend] - p.int_ptr[sc.vbeg];
-    wst[S_EDGE_ITERS] += (unsigned long long)iters * ne;
-    wst[S_VERT_ITERS] += (unsigned long long)iters * (unsigned long long)(sc.vend - sc.vbeg);
+    const int ws = p.mlp ? p.gws[sc.gidx] : -1;
+    const unsigned long long passes = (unsigned long long)iters + (ws >= 0 ? 2ull : 0ull);
+    wst[S_EDGE_ITERS] += passes * ne;
+    wst[S_VERT_ITERS] += passes * (unsigned long long)(sc.vend - sc.vbeg);
+    if (ws == 1) wst[S_WS_ACC] += 1ull;
+    if (ws == 0) wst[S_WS_REJ] += 1ull;
     if ((unsigned long long)iters > wst[S_ITERS_MAX]) wst[S_ITERS_MAX] = (unsigned long long)iters;
     wst[S_ITERS_SUM] += (unsigned long long)iters;
     wst[S_N_ITERATED] += 1ull;
@@ -1196,6 +1339,7 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
           p.wprime[v] = wp;
           if constexpr (sizeof(YT) == 8) yw[v] = c * wp * p.inv64[v];
           else yw[v] = (YT)(c * wp * (double)p.inv32[v]);
+          if (p.mlp) p.wx[v] = c * wp * p.inv64[v];
           part += wp;
         }
       }
@@ -1211,10 +1355,18 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
       }
       const double thresh = p.eps * (1.0 - c) * wsum;
       bool stop;
-      if (k == 1) stop = (p.stop == PR_STOP_CERT_L1 && wsum == 0.0);
-      else stop = stop_now(p, tot, mx, thresh);
+      double last = k == 1 ? wsum : tot;
+      if (k == 1) {
+        stop = (p.stop == PR_STOP_CERT_L1 && wsum == 0.0);
+        if (!stop && p.mlp && p.gws[si] == 1) {  // kept guess: term 0 is r_0
+          last = p.gwn[si];
+          stop = stop_now(p, p.gwn[si], p.gwm[si], thresh);
+        }
+      } else {
+        stop = stop_now(p, tot, mx, thresh);
+      }
       if (stop || final_launch) {
-        gang_finalise(p, sc, g, k - 1, k == 1 ? wsum : tot, stop, s_stats);
+        gang_finalise(p, sc, g, k - 1, last, stop, s_stats);
         continue;
       }
       const YT cy = (YT)c;
@@ -1236,8 +1388,8 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
           p.R[v] += (double)sv;
           if constexpr (sizeof(YT) == 8) yw[v] = cy * sv * p.inv64[v];
           else yw[v] = cy * sv * p.inv32[v];
-          part += (double)sv;
-          pm = fmax(pm, (double)sv);
+          part += fabs((double)sv);
+          pm = fmax(pm, fabs((double)sv));
         }
         ra = rb;
       }
@@ -1301,8 +1453,119 @@ __global__ __launch_bounds__(kThreads) void k_gang_hubs(SolveParams p, int gang,
   p.R[v] += (double)s;
   if constexpr (sizeof(YT) == 8) yw[v] = (YT)p.c * s * p.inv64[v];
   else yw[v] = (YT)p.c * s * p.inv32[v];
-  p.gpart[slot] = (double)s;
-  p.gpmx[slot] = (double)s;
+  p.gpart[slot] = fabs((double)s);
+  p.gpmx[slot] = fabs((double)s);
+}
+
+// Starting guess for the SCCs of a gang (Sec. 3.3.2 series started from a
+// predicted R_0, see warm_preamble): three launches between term 0 and
+// term 1.  step 0: the first plain term p_1 = c A^T W' (from wx = c W' /
+// outdeg), the features, the network and R_0 (wres = c R_0 / outdeg);
+// step 1: r_0 = W' + c A^T R_0 - R_0 (into wx); step 2: every workgroup
+// combines the partial norms in slot order and, if ||r_0||_1 < ||p_1||_1,
+// replaces R by R_0 + r_0 and term 0 by r_0.
+template <typename YT, int RPW>
+__global__ __launch_bounds__(kThreads) void k_gang_warm(SolveParams p, int gang, int step) {
+  __shared__ double s_red[4];
+  __shared__ WaveTile s_tile[kWaves];
+  __shared__ unsigned long long s_stats[kWgStats];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < kWgStats) s_stats[threadIdx.x] = 0ull;
+  if (lane == 0) s_tile[wave].wst = s_stats;
+  __syncthreads();
+  const GangDesc gd = p.gangs[gang];
+  const GangCtx g = gang_ctx(p, gd);
+  const double c = p.c;
+  for (int si = g.s_lo; si < g.s_hi; ++si) {
+    const GangScc sc = p.gscc[si];
+    const int a = sc.vbeg > g.r0 ? sc.vbeg : g.r0, z = sc.vend < g.r1 ? sc.vend : g.r1;
+    const uint32_t* ptr = p.int_ptr;
+    const int64_t tot_w = (int64_t)(ptr[z] - ptr[a]) + (z - a);
+    auto find_row = [&](int64_t target) {
+      int lo = a, hi = z;
+      while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        if ((int64_t)(ptr[mid] - ptr[a]) + (mid - a) < target) lo = mid + 1;
+        else hi = mid;
+      }
+      return lo;
+    };
+    const int w0 = wave == 0 ? a : find_row(tot_w * wave / kWaves);
+    const int w1 = wave == kWaves - 1 ? z : find_row(tot_w * (wave + 1) / kWaves);
+    const size_t slot = (size_t)sc.pbase + (blockIdx.x - sc.wg_first);
+    if (step == 0) {
+      double tot, mx;
+      gang_total(p, sc, 0, s_red, &tot, &mx);  // ||W'_C||_1 from term 0's partials
+      const double sC = tot / (double)(sc.vend - sc.vbeg);
+      double np1 = 0.0;
+      for (int ra = w0; ra < w1; ra += 64) {
+        const int nr = w1 - ra < 64 ? w1 - ra : 64;
+        const double p1 = wave_tile_gather<RPW, double, false>(p, ptr, p.int_src, p.wx, ra, nr, &s_tile[wave]);
+        const int v = ra + lane;
+        const bool act = lane < nr && sC > 0.0;
+        float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
+        if (act) {
+          const double wpv = p.wprime[v];
+          np1 += fabs(p1);
+          const double indeg = (double)((p.bnd_ptr[v + 1] - p.bnd_ptr[v]) + (ptr[v + 1] - ptr[v]));
+          f0 = (float)log1p(indeg);
+          f1 = (float)log1p(rint(1.0 / p.inv64[v]));
+          f2 = (float)log1p((wpv - p.W[p.perm[v]]) / sC);
+          f3 = (float)log1p((wpv + p1) / sC);
+        }
+        const float y = mlp_forward64(*p.mlp, f0, f1, f2, f3);
+        if (lane < nr) {
+          const double r0 = act ? sC * exp((double)y) : 0.0;
+          p.wr0[v] = r0;
+          p.wres[v] = c * r0 * p.inv64[v];
+        }
+      }
+      np1 = block_sum(np1, s_red);
+      if (threadIdx.x == 0) p.gwp1[slot] = np1;
+    } else if (step == 1) {
+      double nr0 = 0.0, mr0 = 0.0;
+      for (int ra = w0; ra < w1; ra += 64) {
+        const int nr = w1 - ra < 64 ? w1 - ra : 64;
+        const double acc = wave_tile_gather<RPW, double, false>(p, ptr, p.int_src, p.wres, ra, nr, &s_tile[wave]);
+        if (lane < nr) {
+          const int v = ra + lane;
+          const double r = p.wprime[v] + acc - p.wr0[v];
+          p.wx[v] = r;
+          nr0 += fabs(r);
+          mr0 = fmax(mr0, fabs(r));
+        }
+      }
+      nr0 = block_sum(nr0, s_red);
+      mr0 = block_max(mr0, s_red);
+      if (threadIdx.x == 0) {
+        p.gwr0[slot] = nr0;
+        p.gwm0[slot] = mr0;
+      }
+    } else {
+      double s1 = 0.0, s2 = 0.0, m2 = 0.0;
+      for (int j = threadIdx.x; j < sc.nslot; j += kThreads) {
+        s1 += p.gwp1[sc.pbase + j];
+        s2 += p.gwr0[sc.pbase + j];
+        m2 = fmax(m2, p.gwm0[sc.pbase + j]);
+      }
+      const double np1 = block_sum(s1, s_red), nr0 = block_sum(s2, s_red), mr0 = block_max(m2, s_red);
+      const bool keep = nr0 < np1;  // false for a non-finite guess
+      if (keep) {
+        YT* y0 = (YT*)p.y0;
+        for (int v = a + (int)threadIdx.x; v < z; v += kThreads) {
+          const double r = p.wx[v];
+          p.R[v] = p.wr0[v] + r;
+          if constexpr (sizeof(YT) == 8) y0[v] = c * r * p.inv64[v];
+          else y0[v] = (YT)(c * r * (double)p.inv32[v]);
+        }
+      }
+      if (blockIdx.x == sc.wg_first && threadIdx.x == 0) {
+        p.gws[si] = keep ? 1 : 0;
+        p.gwn[si] = nr0;
+        p.gwm[si] = mr0;
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------ setup kernels
@@ -1326,6 +1589,18 @@ __global__ void k_init(SolveParams p, int64_t K, int64_t n_gscc, int64_t n_stats
   }
   for (int64_t i = tid; i < n_stats; i += stride) p.wgstats[i] = 0ull;
   for (int64_t i = tid; i < n_heads; i += stride) seg_heads[i] = 0u;
+  if (p.mlp) {
+    for (int64_t i = tid; i < n_gscc; i += stride) {
+      p.gws[i] = -1;
+      p.gwn[i] = 0.0;
+      p.gwm[i] = 0.0;
+    }
+    for (int64_t i = tid; i < p.n_gslots; i += stride) {
+      p.gwp1[i] = 0.0;
+      p.gwr0[i] = 0.0;
+      p.gwm0[i] = 0.0;
+    }
+  }
 }
 
 __global__ void k_zero_counters(unsigned long long* c) {
@@ -1396,12 +1671,20 @@ using SegFn = void (*)(SolveParams);
 using GangFn = void (*)(SolveParams, int, int, int);
 
 template <typename YT>
-SegFn seg_kernel(int rpw) {
+SegFn seg_kernel(int rpw, bool warm) {
+  if (warm) {
+    switch (rpw) {
+      case 64: return k_segment<YT, 64, true>;
+      case 16: return k_segment<YT, 16, true>;
+      case 4: return k_segment<YT, 4, true>;
+      default: return k_segment<YT, 1, true>;
+    }
+  }
   switch (rpw) {
-    case 64: return k_segment<YT, 64>;
-    case 16: return k_segment<YT, 16>;
-    case 4: return k_segment<YT, 4>;
-    default: return k_segment<YT, 1>;
+    case 64: return k_segment<YT, 64, false>;
+    case 16: return k_segment<YT, 16, false>;
+    case 4: return k_segment<YT, 4, false>;
+    default: return k_segment<YT, 1, false>;
   }
 }
 template <typename YT>
@@ -1417,8 +1700,21 @@ using HubFn = void (*)(SolveParams, int, int);
 HubFn pick_hubs(int precision) {
   return precision == PR_PREC_FP64 ? (HubFn)k_gang_hubs<double> : (HubFn)k_gang_hubs<float>;
 }
-SegFn pick_segment(int precision, int rpw) {
-  return precision == PR_PREC_FP64 ? seg_kernel<double>(rpw) : seg_kernel<float>(rpw);
+using WarmGangFn = void (*)(SolveParams, int, int);
+template <typename YT>
+WarmGangFn gang_warm_kernel(int rpw) {
+  switch (rpw) {
+    case 64: return k_gang_warm<YT, 64>;
+    case 16: return k_gang_warm<YT, 16>;
+    case 4: return k_gang_warm<YT, 4>;
+    default: return k_gang_warm<YT, 1>;
+  }
+}
+WarmGangFn pick_gang_warm(int precision, int rpw) {
+  return precision == PR_PREC_FP64 ? gang_warm_kernel<double>(rpw) : gang_warm_kernel<float>(rpw);
+}
+SegFn pick_segment(int precision, int rpw, bool warm = false) {
+  return precision == PR_PREC_FP64 ? seg_kernel<double>(rpw, warm) : seg_kernel<float>(rpw, warm);
 }
 GangFn pick_gang(int precision, int rpw) {
   return precision == PR_PREC_FP64 ? gang_kernel<double>(rpw) : gang_kernel<float>(rpw);
@@ -1616,9 +1912,12 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   lv.phases = phases;
   // device copies
   void* old[] = {lv.items, lv.gangs, lv.gsccs, lv.gbounds, lv.gpart, lv.gpmx, lv.gwsum, lv.gdone, lv.wgstats,
-                 lv.trace, lv.seg_heads, lv.ghubs, lv.gpieces, lv.gpiece_ptr, lv.gpiece_part, lv.ghub_pieces};
+                 lv.trace, lv.seg_heads, lv.ghubs, lv.gpieces, lv.gpiece_ptr, lv.gpiece_part, lv.ghub_pieces,
+                 lv.warm_buf, lv.warm_gws};
   for (void* q : old)
     if (q) (void)hipFree(q);
+  lv.warm_buf = nullptr;  // sized by the schedule: allocated again on first use
+  lv.warm_gws = nullptr;
   lv.items = nullptr;
   lv.gangs = nullptr;
   lv.gsccs = nullptr;
@@ -1778,6 +2077,27 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.gpiece_part = lv.gpiece_part;
   p.n_gslots = lv.n_gslots;
   p.timeout = (unsigned long long)clock_khz * 1000ull * 30ull;  // 30 s
+  if (o.warm_start && !plain) {
+    const Mlp* m = reinterpret_cast<const Mlp*>(o.warm_start);
+    if (m->device != lv.device) {
+      set_error("the warm-start network lives on device %d, the plan on device %d", m->device, lv.device);
+      return PR_EINVAL;
+    }
+    if (!lv.warm_buf) {
+      PR_TRY(dalloc(&lv.warm_buf, 3 * (size_t)lv.n + 3 * (size_t)lv.n_gslots + 2 * (size_t)lv.n_gscc));
+      PR_TRY(dalloc(&lv.warm_gws, std::max<int64_t>(lv.n_gscc, 1)));
+    }
+    p.mlp = m->packed;
+    p.wr0 = lv.warm_buf;
+    p.wx = lv.warm_buf + lv.n;
+    p.wres = lv.warm_buf + 2 * lv.n;
+    p.gwp1 = lv.warm_buf + 3 * lv.n;
+    p.gwr0 = p.gwp1 + lv.n_gslots;
+    p.gwm0 = p.gwr0 + lv.n_gslots;
+    p.gwn = p.gwm0 + lv.n_gslots;
+    p.gwm = p.gwn + lv.n_gscc;
+    p.gws = lv.warm_gws;
+  }
   if (o.trace == 1) {  // timeline of the segment items (tests / profiling)
     if (!lv.trace) {
       hipError_t e = hipMalloc(&lv.trace, sizeof(unsigned long long) * 4 * std::max<int64_t>(lv.n_items, 1));
@@ -1810,7 +2130,16 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   double sumW = 0.0;
   for (int i = 0; i < kRedBlocks; ++i) sumW += wparts[2 * i];
   const int64_t kb = term_bound(o, c, sumW);
-  const SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave);
+  const SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave, p.mlp != nullptr);
+  // the variant with the starting guess needs more registers: size its grid
+  // to what stays resident
+  unsigned seg_grid = (unsigned)lv.grid;
+  if (p.mlp) {
+    int occ = 0, cus = 0;
+    PR_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)seg, kThreads, 0));
+    PR_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, lv.device));
+    seg_grid = (unsigned)std::max(1, std::min(lv.grid, std::max(occ, 1) * cus));
+  }
   const GangFn gk = pick_gang(o.precision, lv.opts.rows_per_wave);
   hipEvent_t ev0, ev1;
   PR_HIP_CHECK(hipEventCreate(&ev0));
@@ -1832,6 +2161,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     fam.push_back(f);
     return PR_OK;
   };
+  const WarmGangFn wk = pick_gang_warm(o.precision, lv.opts.rows_per_wave);
   auto launch_gang = [&](int gang) -> int32_t {
     const int nh = lv.h_gang_nhub[gang];
     for (int64_t k = 0; k <= kb + 1; ++k) {
@@ -1841,6 +2171,12 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
       if (nh > 0 && !fin) {
         hipLaunchKernelGGL(hk, dim3((nh + kWaves - 1) / kWaves), dim3(kThreads), 0, s, p, gang, (int)k);
         PR_TRY(mark(2));
+      }
+      if (k == 0 && p.mlp) {  // the starting guess of the gang's SCCs
+        for (int step = 0; step < 3; ++step) {
+          hipLaunchKernelGGL(wk, dim3(lv.ggrid), dim3(kThreads), 0, s, p, gang, step);
+          PR_TRY(mark(1));
+        }
       }
     }
     return PR_OK;
@@ -1865,7 +2201,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
           q.item_base = ph.a;
           q.seg_head = lv.seg_heads + pi;
           void* args[] = {&q};
-          PR_HIP_CHECK(hipLaunchKernel((const void*)seg, dim3(lv.grid), dim3(kThreads), args, 0, s));
+          PR_HIP_CHECK(hipLaunchKernel((const void*)seg, dim3(seg_grid), dim3(kThreads), args, 0, s));
           PR_TRY(mark(0));
         }
       }
@@ -1887,6 +2223,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     key = mix64(key, (uint64_t)o.max_iter);
     key = mix64(key, (uint64_t)kb);
     key = mix64(key, (uint64_t)(o.stop * 16 + o.precision * 4 + o.method));
+    key = mix64(key, (uint64_t)(uintptr_t)p.mlp);
     if (!lv.graph_exec || lv.graph_key != key) {
       if (lv.graph_exec) (void)hipGraphExecDestroy(lv.graph_exec);
       if (lv.graph) (void)hipGraphDestroy(lv.graph);
