@@ -1,10 +1,12 @@
 """Benchmark: componentwise PageRank vs plain power series on one MI355X.
 
 One step = one pr_solve of the componentwise method (Sec. 3.3: boundary
-mass, one-vertex components, CAC sweeps, SCC power series, output) on the
-web-like graph of 1M vertices / 10M edges, with the plan resident on the
-device.  The plain whole-graph power series (Sec. 4.2, method 1) is timed the
-same way as the comparator.  Both stop on the 1-norm certificate at 1e-6.
+mass, one-vertex components, CAC sweeps, SCC power series started from the
+learned guess where it passes the residual test, output) on the web-like
+graph of 1M vertices / 10M edges, with the plan resident on the device.  The
+same solve from the plain start and the plain whole-graph power series
+(Sec. 4.2, method 1) are timed the same way beside it.  All stop on the
+1-norm certificate at 1e-6.
 
 Prints ONE JSON line.  --gpus N > 1 is refused (single-GPU build).
 """
@@ -183,6 +185,8 @@ def main():
                     help="also run a plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "hbm_traffic_c2_web_1m.json"),
                     help="committed counter summary that supplies roofline.traffic")
+    ap.add_argument("--no-warm", action="store_true", help="no starting guess in the headline step")
+    ap.add_argument("--warm-net", default=os.path.join(ROOT, "paper_1609_09068_amd", "data", "warm_web.prmlp"))
     ap.add_argument("--only", choices=["componentwise", "plain"],
                     help="run one method only (counter runs: one kernel family per method)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
@@ -247,20 +251,33 @@ def main():
     if args.only:
         # counter runs: a few solves of one method, then the calibration copy
         meth = 0 if args.only == "componentwise" else 1
+        net = None
+        if meth == 0 and not args.no_warm and os.path.exists(args.warm_net):
+            net = pr.Mlp.load_file(args.warm_net)
         for _ in range(args.warmup + args.steps):
-            run(meth, R, 1)
+            run(meth, R, 1, **(dict(warm_start=net) if net is not None else {}))
         if args.calib_copy_mb:
             calib_copy(torch, args.calib_copy_mb)
         log(f"{args.only}: {args.warmup + args.steps} solves done")
         return
+    net = None
+    if not args.no_warm:
+        if not os.path.exists(args.warm_net):
+            raise SystemExit(f"bench.py: trained network {args.warm_net} missing (use --no-warm)")
+        net = pr.Mlp.load_file(args.warm_net)
+    wopt = dict(warm_start=net) if net is not None else {}
+    Rn = torch.empty_like(W)
     for _ in range(args.warmup):
-        run(0, R, 1)
+        run(0, R, 1, **wopt)
+        run(0, Rn, 1)
         run(1, Rp, 1)
     # the same solve without per-launch events: shows what the events cost
-    t_ne, _ = run(0, R, 2, kernel_timing=0)
+    t_ne, _ = run(0, R, 2, kernel_timing=0, **wopt)
     log(f"warmup done; componentwise without launch events {t_ne / 2 * 1e3:.3f} ms")
-    t_cw, st_cw = run(0, R, args.steps)
-    log(f"componentwise: {t_cw / args.steps * 1e3:.3f} ms/step")
+    t_cw, st_cw = run(0, R, args.steps, **wopt)
+    log(f"componentwise{' + starting guess' if net else ''}: {t_cw / args.steps * 1e3:.3f} ms/step")
+    t_cn, st_cn = run(0, Rn, args.steps)
+    log(f"componentwise, plain start: {t_cn / args.steps * 1e3:.3f} ms/step")
     t_pl, st_pl = run(1, Rp, args.steps)
     log(f"plain: {t_pl / args.steps * 1e3:.3f} ms/step")
 
@@ -301,6 +318,7 @@ def main():
         Rc = R.cpu().numpy()
         Rpl = Rp.cpu().numpy()
         acc = {"componentwise": float(np.abs(Rc - ref).sum() / ref.sum()),
+               "componentwise_plain_start": float(np.abs(Rn.cpu().numpy() - ref).sum() / ref.sum()),
                "plain": float(np.abs(Rpl - ref).sum() / ref.sum()),
                "cert_componentwise": s["cert_rel"], "cert_plain": sp["cert_rel"],
                "reference": f"oracle plain power series, FP64, eps 1e-12 ({kref} terms)"}
@@ -343,7 +361,8 @@ def main():
         "dtype": "f32+f64" if args.precision == 0 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: web-like graph n={g.n} m={g.m}, c={args.c}, "
-                               f"1-norm certificate eps={args.eps}, W=1, solve with the plan resident",
+                               f"1-norm certificate eps={args.eps}, W=1, componentwise solve"
+                               f"{' with the learned starting guess' if net is not None else ''}, plan resident",
                    "n": g.n, "m": g.m, "levels": info["n_levels"], "components": info["n_comp"],
                    "scc": info["n_scc"], "scc_vertices": info["v_scc"], "m_scc_internal": info["m_scc_internal"],
                    "m_between": info["m_between"], "m_cac_internal": info["m_cac_internal"],
@@ -351,6 +370,7 @@ def main():
                    "small_cutoff": info["small_cutoff"], "team_edges": info["team_edges"],
                    "grid_wgs": info["grid_wgs"], "hipgraph": bool(args.graph)},
         "time_to_1e-6_ms": {"componentwise": round(ms_cw, 4), "plain": round(ms_pl, 4),
+                            "componentwise_plain_start": round(t_cn / args.steps * 1e3, 4),
                             "componentwise_device": round(mcw["kernel_ms"], 4),
                             "plain_device": round(mpl["kernel_ms"], 4),
                             "componentwise_no_launch_events": round(t_ne / 2 * 1e3, 4)},
@@ -358,7 +378,12 @@ def main():
         "plain_gedge_iter_s": round(sp["edge_iters"] / (ms_pl * 1e-3) / 1e9, 4),
         "plain_equivalent_gedge_iter_s": round(sp["edge_iters"] / (ms_cw * 1e-3) / 1e9, 4),
         "iterations": {"componentwise_max": s["iters_max"], "plain": sp["iters_max"],
-                       "edge_iters_cw": s["edge_iters"], "edge_iters_plain": sp["edge_iters"]},
+                       "componentwise_terms_sum": s["iters_sum"], "plain_start_terms_sum": st_cn[-1]["iters_sum"],
+                       "edge_iters_cw": s["edge_iters"], "edge_iters_cw_plain_start": st_cn[-1]["edge_iters"],
+                       "edge_iters_plain": sp["edge_iters"]},
+        "starting_guess": None if net is None else {
+            "network": os.path.relpath(args.warm_net, ROOT), "kept": s["ws_accepted"], "fell_back": s["ws_rejected"],
+            "fallback_rate": round(s["ws_rejected"] / max(s["ws_accepted"] + s["ws_rejected"], 1), 4)},
         "rel_l1_vs_fp64_oracle": acc,
         "partition_ms": round(t_part * 1e3, 2),
         "build_ms": round(t_build * 1e3, 2),
