@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--small-cutoff", type=int, default=0)
     ap.add_argument("--team-edges", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1, 2],
+                    help="plan autotuner: 0 off, 1 cached or sweep, 2 sweep")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "hbm_traffic_c2_web_1m.json"),
@@ -224,6 +226,8 @@ def main():
         bopts["small_cutoff"] = args.small_cutoff
     if args.team_edges:
         bopts["team_edges"] = args.team_edges
+    if args.autotune and not (args.rows_per_wave or args.small_cutoff or args.team_edges):
+        bopts["autotune"] = args.autotune
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lv = pr.pr_build_levels(part, g.row_ptr, g.col, **bopts)
@@ -368,7 +372,8 @@ def main():
                    "m_between": info["m_between"], "m_cac_internal": info["m_cac_internal"],
                    "gang_vertices": info["v_gang"], "rows_per_wave": info["rows_per_wave"],
                    "small_cutoff": info["small_cutoff"], "team_edges": info["team_edges"],
-                   "grid_wgs": info["grid_wgs"], "hipgraph": bool(args.graph)},
+                   "grid_wgs": info["grid_wgs"], "hipgraph": bool(args.graph),
+                   "autotuned": bool(bopts.get("autotune", 0))},
         "time_to_1e-6_ms": {"componentwise": round(ms_cw, 4), "plain": round(ms_pl, 4),
                             "componentwise_plain_start": round(t_cn / args.steps * 1e3, 4),
                             "componentwise_device": round(mcw["kernel_ms"], 4),

@@ -100,9 +100,14 @@ typedef struct pr_build_opts {
   int32_t rows_per_wave;
   /* 1 = also keep the whole-graph pull CSR needed by method PLAIN. */
   int32_t build_plain;
-  /* 1 = run the autotuner (sweeps rows_per_wave and the small/medium/team
-     split with timed solves; results cached in a JSON file named by the
-     environment variable PR_AUTOTUNE_CACHE, if set). */
+  /* Autotuner of the launch shape: 0 = off (use the three fields above);
+     2 = sweep rows_per_wave {1, 4, 16, 64} x small_cutoff {16, 64} x
+     team_edges {16384, 65536}, timing solves of this plan on the device
+     (W = 1, c = 0.85, eps 1e-6, mixed precision; method PLAIN too when
+     build_plain), and keep the fastest; 1 = as 2 unless this graph was tuned
+     before on this device: in this process, or in the text file named by
+     the environment variable PR_AUTOTUNE_CACHE (read and appended to).
+     The choice is reported by pr_levels_get_info. */
   int32_t autotune;
   int32_t reserved[7];
 } pr_build_opts;
@@ -169,7 +174,10 @@ typedef struct pr_solve_opts {
   int32_t trace;        /* 1 = record the item timeline (pr_levels_debug what = 4); slows the solve */
   int32_t kernel_timing;/* 1 = HIP events around every launch; per-family times land in the stats
                            (ignored with use_graph) */
-  int32_t reserved[6];
+  int32_t warm_scope;   /* with warm_start: 0 = only the SCCs iterated in gang phases (the large
+                           ones, where the guess's two extra passes cost less than the terms it
+                           saves), 1 = every SCC */
+  int32_t reserved[5];
 } pr_solve_opts;
 
 void pr_default_solve_opts(pr_solve_opts* o);

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpr.so")
 ARCH = os.environ.get("PR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.cpp", "partition.cpp", "devsort.hip", "plan.hip", "solve.hip", "mlp.hip"]
+SOURCES = ["abi.cpp", "partition.cpp", "devsort.hip", "plan.hip", "solve.hip", "mlp.hip", "autotune.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",

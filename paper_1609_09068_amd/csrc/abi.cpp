@@ -182,6 +182,10 @@ int32_t pr_build_levels(const pr_partition_t* ph, int64_t n, const int64_t* row_
     set_error("small_cutoff = %d exceeds 256", o.small_cutoff);
     return PR_EINVAL;
   }
+  if (o.autotune < 0 || o.autotune > 2) {
+    set_error("autotune = %d, expected 0, 1 or 2", o.autotune);
+    return PR_EINVAL;
+  }
   if (o.rows_per_wave != 1 && o.rows_per_wave != 4 && o.rows_per_wave != 16 && o.rows_per_wave != 64) {
     set_error("rows_per_wave = %d, expected 1, 4, 16 or 64", o.rows_per_wave);
     return PR_EINVAL;
@@ -258,6 +262,10 @@ int32_t pr_solve(pr_levels_t* lh, double c, const void* W_dev, void* R_dev, cons
   }
   if (lv->n > 0 && (!W_dev || !R_dev)) {
     set_error("W_dev / R_dev is NULL");
+    return PR_EINVAL;
+  }
+  if (o.warm_scope != 0 && o.warm_scope != 1) {
+    set_error("warm_scope = %d, expected 0 or 1", o.warm_scope);
     return PR_EINVAL;
   }
   if (o.warm_start && !registry_has(o.warm_start, KIND_MLP)) {

@@ -1,0 +1,148 @@
+// Autotuner of a plan's launch shape: rows per wavefront {1, 4, 16, 64}
+// (lanes per row in the gathers), the largest SCC iterated by one wavefront
+// (small_cutoff) and the internal-edge count above which an SCC is iterated
+// by a gang of every workgroup (team_edges).  Each candidate schedule is
+// timed with real solves of this plan on the device (W = 1, c = 0.85,
+// certificate 1e-6, mixed precision; the plain method too when the plan
+// keeps it) and the fastest is kept.  Results are cached per graph, device
+// and library version: in memory for the process and, when the environment
+// variable PR_AUTOTUNE_CACHE names a file, in that file (one line per entry:
+// key, rows_per_wave, small_cutoff, team_edges).
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+
+#include "internal.h"
+
+namespace prlib {
+
+namespace {
+
+struct Choice {
+  int32_t rpw, small, team;
+};
+
+std::mutex g_tune_mu;
+std::map<uint64_t, Choice>& tune_cache() {
+  static std::map<uint64_t, Choice> m;
+  return m;
+}
+
+uint64_t mix(uint64_t h, uint64_t v) {
+  h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+  return h * 0xff51afd7ed558ccdull;
+}
+
+bool file_lookup(uint64_t key, Choice* c) {
+  const char* path = getenv("PR_AUTOTUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  unsigned long long k;
+  int a, b, d;
+  bool found = false;
+  while (fscanf(f, "%llx %d %d %d", &k, &a, &b, &d) == 4) {
+    if (k == key && (a == 1 || a == 4 || a == 16 || a == 64) && b >= 1 && b <= 256 && d >= 1) {
+      *c = Choice{a, b, d};
+      found = true;  // the last entry for a key wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void file_store(uint64_t key, const Choice& c) {
+  const char* path = getenv("PR_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%016llx %d %d %d\n", (unsigned long long)key, c.rpw, c.small, c.team);
+  fclose(f);
+}
+
+__global__ void k_fill(double* a, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+}  // namespace
+
+int32_t autotune_levels(Levels& lv, hipStream_t s) {
+  hipDeviceProp_t prop;
+  PR_HIP_CHECK(hipGetDeviceProperties(&prop, lv.device));
+  uint64_t key = mix(lv.graph_hash, (uint64_t)lv.n);
+  for (const char* q = prop.gcnArchName; *q; ++q) key = mix(key, (uint64_t)(unsigned char)*q);
+  for (const char* q = pr_version(); *q; ++q) key = mix(key, (uint64_t)(unsigned char)*q);
+  key = mix(key, lv.full_ptr ? 1u : 0u);
+  Choice best{lv.opts.rows_per_wave, lv.opts.small_cutoff, lv.opts.team_edges};
+  bool have = false;
+  if (lv.opts.autotune == 1) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      best = it->second;
+      have = true;
+    } else if (file_lookup(key, &best)) {
+      tune_cache()[key] = best;
+      have = true;
+    }
+  }
+  if (!have && lv.n > 0) {
+    double *W = nullptr, *R = nullptr;
+    PR_HIP_CHECK(hipMalloc(&W, sizeof(double) * lv.n));
+    hipError_t e = hipMalloc(&R, sizeof(double) * lv.n);
+    if (e != hipSuccess) {
+      (void)hipFree(W);
+      set_error("hipMalloc failed: %s", hipGetErrorString(e));
+      return PR_ENOMEM;
+    }
+    k_fill<<<1024, 256, 0, s>>>(W, lv.n, 1.0);
+    pr_solve_opts o;
+    pr_default_solve_opts(&o);
+    o.eps = 1e-6;
+    o.precision = PR_PREC_MIXED;
+    double best_ms = 1e300;
+    int32_t rc = PR_OK;
+    for (int rpw : {16, 4, 64, 1}) {
+      for (int small : {64, 16}) {
+        for (int team : {65536, 16384}) {
+          lv.opts.rows_per_wave = rpw;
+          lv.opts.small_cutoff = small;
+          lv.opts.team_edges = team;
+          rc = make_schedule(lv, s);
+          if (rc) break;
+          double ms = 0.0;
+          for (int method : {PR_METHOD_COMPONENTWISE, PR_METHOD_PLAIN}) {
+            if (method == PR_METHOD_PLAIN && !lv.full_ptr) continue;
+            o.method = method;
+            pr_solve_stats st;
+            for (int rep = 0; rep < 2 && !rc; ++rep) rc = solve_levels(lv, 0.85, W, R, o, s, &st);
+            if (rc > 0) rc = PR_OK;  // not converged within max_iter: still a valid timing
+            if (rc) break;
+            ms += st.kernel_ms;
+          }
+          if (rc) break;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = Choice{rpw, small, team};
+          }
+        }
+        if (rc) break;
+      }
+      if (rc) break;
+    }
+    (void)hipFree(W);
+    (void)hipFree(R);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_cache()[key] = best;
+    file_store(key, best);
+  }
+  lv.opts.rows_per_wave = best.rpw;
+  lv.opts.small_cutoff = best.small;
+  lv.opts.team_edges = best.team;
+  return make_schedule(lv, s);
+}
+
+}  // namespace prlib

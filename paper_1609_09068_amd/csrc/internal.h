@@ -202,6 +202,7 @@ void mlp_destroy(void* h);
 int32_t build_levels(const Partition& p, const int64_t* row_ptr, const int32_t* col,
                      const pr_build_opts& opts, hipStream_t stream, Levels& lv);
 int32_t make_schedule(Levels& lv, hipStream_t stream);
+int32_t autotune_levels(Levels& lv, hipStream_t stream);
 int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_solve_opts& o,
                      hipStream_t stream, pr_solve_stats* st);
 int32_t solve_grid_size(int precision, int* grid);

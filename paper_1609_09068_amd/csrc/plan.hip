@@ -364,6 +364,7 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
     return PR_EHIP;
   }
   PR_TRY(make_schedule(lv, s));
+  if (opts.autotune) PR_TRY(autotune_levels(lv, s));
   return PR_OK;
 }
 

@@ -77,8 +77,10 @@ struct SolveParams {
   double* x;
   double* R;
   double* wprime;
-  // starting guess (null: start every SCC from W'_C)
+  // starting guess (null: start from W'_C): for SCCs of segment items
+  // (mlp) and of gangs (gmlp)
   const MlpPacked* mlp;
+  const MlpPacked* gmlp;
   double* wr0;   // [n] R_0 of the guess
   double* wx;    // [n] c R_0 / outdeg
   double* wres;  // [n] r_0 = W' + c A^T R_0 - R_0
@@ -1261,7 +1263,7 @@ __device__ inline void gang_finalise(const SolveParams& p, const GangScc& sc, co
       p.lastnorm[0] = last;
     }
     const uint64_t ne = p.int_ptr[sc.vend] - p.int_ptr[sc.vbeg];
-    const int ws = p.mlp ? p.gws[sc.gidx] : -1;
+    const int ws = p.gmlp ? p.gws[sc.gidx] : -1;
     const unsigned long long passes = (unsigned long long)iters + (ws >= 0 ? 2ull : 0ull);
     wst[S_EDGE_ITERS] += passes * ne;
     wst[S_VERT_ITERS] += passes * (unsigned long long)(sc.vend - sc.vbeg);
@@ -1339,7 +1341,7 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
           p.wprime[v] = wp;
           if constexpr (sizeof(YT) == 8) yw[v] = c * wp * p.inv64[v];
           else yw[v] = (YT)(c * wp * (double)p.inv32[v]);
-          if (p.mlp) p.wx[v] = c * wp * p.inv64[v];
+          if (p.gmlp) p.wx[v] = c * wp * p.inv64[v];
           part += wp;
         }
       }
@@ -1358,7 +1360,7 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
       double last = k == 1 ? wsum : tot;
       if (k == 1) {
         stop = (p.stop == PR_STOP_CERT_L1 && wsum == 0.0);
-        if (!stop && p.mlp && p.gws[si] == 1) {  // kept guess: term 0 is r_0
+        if (!stop && p.gmlp && p.gws[si] == 1) {  // kept guess: term 0 is r_0
           last = p.gwn[si];
           stop = stop_now(p, p.gwn[si], p.gwm[si], thresh);
         }
@@ -1513,7 +1515,7 @@ __global__ __launch_bounds__(kThreads) void k_gang_warm(SolveParams p, int gang,
           f2 = (float)log1p((wpv - p.W[p.perm[v]]) / sC);
           f3 = (float)log1p((wpv + p1) / sC);
         }
-        const float y = mlp_forward64(*p.mlp, f0, f1, f2, f3);
+        const float y = mlp_forward64(*p.gmlp, f0, f1, f2, f3);
         if (lane < nr) {
           const double r0 = act ? sC * exp((double)y) : 0.0;
           p.wr0[v] = r0;
@@ -1589,7 +1591,7 @@ __global__ void k_init(SolveParams p, int64_t K, int64_t n_gscc, int64_t n_stats
   }
   for (int64_t i = tid; i < n_stats; i += stride) p.wgstats[i] = 0ull;
   for (int64_t i = tid; i < n_heads; i += stride) seg_heads[i] = 0u;
-  if (p.mlp) {
+  if (p.gmlp) {
     for (int64_t i = tid; i < n_gscc; i += stride) {
       p.gws[i] = -1;
       p.gwn[i] = 0.0;
@@ -2087,7 +2089,8 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
       PR_TRY(dalloc(&lv.warm_buf, 3 * (size_t)lv.n + 3 * (size_t)lv.n_gslots + 2 * (size_t)lv.n_gscc));
       PR_TRY(dalloc(&lv.warm_gws, std::max<int64_t>(lv.n_gscc, 1)));
     }
-    p.mlp = m->packed;
+    p.gmlp = m->packed;
+    if (o.warm_scope == 1) p.mlp = m->packed;  // every SCC, not only the gangs'
     p.wr0 = lv.warm_buf;
     p.wx = lv.warm_buf + lv.n;
     p.wres = lv.warm_buf + 2 * lv.n;
@@ -2172,7 +2175,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
         hipLaunchKernelGGL(hk, dim3((nh + kWaves - 1) / kWaves), dim3(kThreads), 0, s, p, gang, (int)k);
         PR_TRY(mark(2));
       }
-      if (k == 0 && p.mlp) {  // the starting guess of the gang's SCCs
+      if (k == 0 && p.gmlp) {  // the starting guess of the gang's SCCs
         for (int step = 0; step < 3; ++step) {
           hipLaunchKernelGGL(wk, dim3(lv.ggrid), dim3(kThreads), 0, s, p, gang, step);
           PR_TRY(mark(1));
@@ -2224,6 +2227,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     key = mix64(key, (uint64_t)kb);
     key = mix64(key, (uint64_t)(o.stop * 16 + o.precision * 4 + o.method));
     key = mix64(key, (uint64_t)(uintptr_t)p.mlp);
+    key = mix64(key, (uint64_t)(uintptr_t)p.gmlp);
     if (!lv.graph_exec || lv.graph_key != key) {
       if (lv.graph_exec) (void)hipGraphExecDestroy(lv.graph_exec);
       if (lv.graph) (void)hipGraphDestroy(lv.graph);

@@ -272,3 +272,29 @@ def test_config2_full_size_mixed(prm, c2, method):
     # partition of the full graph is bit-exact
     if method == 0:
         assert partition_arrays_equal(p.as_dict(), partition_theorem(g.n, g.row_ptr, g.col))
+
+
+def test_autotuner_sweeps_caches_and_stays_exact(prm, c1, tmp_path, monkeypatch):
+    pr, torch = prm
+    g, W, ref = c1
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PR_AUTOTUNE_CACHE", str(cache))
+    part = pr.pr_partition(g.row_ptr, g.col)
+    _say("autotune sweep")
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col, autotune=2)
+    info = lv.info()
+    assert info["rows_per_wave"] in (1, 4, 16, 64)
+    assert info["small_cutoff"] in (16, 64) and info["team_edges"] in (16384, 65536)
+    lines = cache.read_text().split()
+    assert len(lines) == 4 and int(lines[1]) == info["rows_per_wave"]
+    # cached: the same choice without a sweep (the file is not appended to)
+    lv2 = pr.pr_build_levels(part, g.row_ptr, g.col, autotune=1)
+    assert {k: lv2.info()[k] for k in ("rows_per_wave", "small_cutoff", "team_edges")} == \
+        {k: info[k] for k in ("rows_per_wave", "small_cutoff", "team_edges")}
+    assert len(cache.read_text().split()) == 4
+    Wd = torch.tensor(W, device="cuda")
+    Rd = torch.empty_like(Wd)
+    pr.pr_solve(lv2, C, Wd, Rd, eps=1e-10, precision=1)
+    assert _rel_l1(Rd.cpu().numpy(), ref) <= 1e-10
+    with pytest.raises(pr.PRError):
+        pr.pr_build_levels(part, g.row_ptr, g.col, autotune=3)

@@ -62,7 +62,7 @@ def test_warm_result_matches_oracle(prm, split, precision):
     net = pr.Mlp.create(5)
     eps = 1e-10 if precision == 1 else 1e-6
     R, st, lv, _ = _solve(pr, torch, g, W, team_edges=team_edges, small_cutoff=small_cutoff, eps=eps,
-                          precision=precision, warm_start=net)
+                          precision=precision, warm_start=net, warm_scope=1)
     err = np.abs(R - ref).sum() / ref.sum()
     assert err <= (eps if precision == 1 else 1e-6), err
     assert st["ws_accepted"] + st["ws_rejected"] == st["n_iterated"]
@@ -84,7 +84,7 @@ def test_rejected_guess_is_the_plain_start(prm, split):
     R0, st0, lv0, _ = _solve(pr, torch, g, W, team_edges=team_edges, small_cutoff=small_cutoff, eps=1e-8,
                              precision=1)
     R1, st1, lv1, part = _solve(pr, torch, g, W, team_edges=team_edges, small_cutoff=small_cutoff, eps=1e-8,
-                                precision=1, warm_start=net)
+                                precision=1, warm_start=net, warm_scope=1)
     assert st1["ws_accepted"] == 0 and st1["ws_rejected"] == st1["n_iterated"] > 0
     np.testing.assert_array_equal(R1, R0)
     np.testing.assert_array_equal(lv1.debug("iters", n_comp=part.n_comp), lv0.debug("iters", n_comp=part.n_comp))
@@ -109,22 +109,26 @@ def test_accept_decisions_follow_the_oracle(prm):
                                  warm=th.astype(np.float32).astype(np.float64))
     acc_oracle = int((sto["accepted"] == 1).sum())
     n_scc = int((sto["accepted"] >= 0).sum())
-    _, st, _, _ = _solve(pr, torch, g, W, eps=1e-8, precision=1, warm_start=rng_net)
+    _, st, _, _ = _solve(pr, torch, g, W, eps=1e-8, precision=1, warm_start=rng_net, warm_scope=1)
     assert st["n_iterated"] == n_scc
     assert abs(st["ws_accepted"] - acc_oracle) <= max(2, n_scc // 20), (st["ws_accepted"], acc_oracle, n_scc)
 
 
-def test_warm_full_size_mixed(prm):
+@pytest.mark.parametrize("scope", [0, 1])
+def test_warm_full_size_mixed(prm, scope):
     pr, torch = prm
-    _say("warm c2 full")
+    _say("warm c2 full", scope)
     g = config_graph("c2_web_1m")
     W = np.ones(g.n)
     ref, _, _ = pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-12)
     net = pr.Mlp.create(7)
-    R, st, lv, _ = _solve(pr, torch, g, W, eps=1e-6, precision=0, warm_start=net)
+    R, st, lv, _ = _solve(pr, torch, g, W, eps=1e-6, precision=0, warm_start=net, warm_scope=scope)
     err = np.abs(R - ref).sum() / ref.sum()
     assert err <= 1e-6, err
-    assert lv.info()["n_gang_scc"] >= 1
+    n_gang = lv.info()["n_gang_scc"]
+    assert n_gang >= 1
+    decided = st["ws_accepted"] + st["ws_rejected"]
+    assert decided == (n_gang if scope == 0 else st["n_iterated"])
 
 
 def test_random_graph_warm_fp64(prm):
@@ -133,5 +137,6 @@ def test_random_graph_warm_fp64(prm):
     W = np.random.default_rng(21).uniform(0, 3, g.n)
     ref, _, _ = pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-14)
     net = pr.Mlp.create(21)
-    R, st, _, _ = _solve(pr, torch, g, W, eps=1e-11, precision=1, warm_start=net, team_edges=256, small_cutoff=8)
+    R, st, _, _ = _solve(pr, torch, g, W, eps=1e-11, precision=1, warm_start=net, warm_scope=1,
+                         team_edges=256, small_cutoff=8)
     assert np.abs(R - ref).sum() / ref.sum() <= 1e-11

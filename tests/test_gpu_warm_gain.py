@@ -82,7 +82,7 @@ def test_trained_guess_saves_terms(prm, precision):
     R0 = torch.empty_like(W)
     R1 = torch.empty_like(W)
     _, st0 = pr.pr_solve(lv, C, W, R0, eps=1e-6, precision=precision)
-    _, st1 = pr.pr_solve(lv, C, W, R1, eps=1e-6, precision=precision, warm_start=net)
+    _, st1 = pr.pr_solve(lv, C, W, R1, eps=1e-6, precision=precision, warm_start=net, warm_scope=1)
     ref, _, _ = pagerank_power_series(g.n, g.row_ptr, g.col, C, np.ones(g.n), eps=1e-13)
     for R in (R0, R1):
         err = np.abs(R.cpu().numpy() - ref).sum() / ref.sum()
@@ -95,3 +95,26 @@ def test_trained_guess_saves_terms(prm, precision):
     # guess's two passes included)
     assert st1["iters_sum"] <= 0.9 * st0["iters_sum"]
     assert st1["edge_iters"] < st0["edge_iters"]
+
+
+@pytest.mark.skipif(not os.path.exists(NET), reason="trained network not present")
+def test_trained_guess_on_the_gang_scc(prm):
+    """Default scope: only the large SCC (a gang phase) takes the guess."""
+    pr, torch = prm
+    net = pr.Mlp.load_file(NET)
+    g = config_graph("c4_train_100k", seed=4950)
+    part = pr.pr_partition(g.row_ptr, g.col)
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col)
+    assert lv.info()["n_gang_scc"] == 1
+    W = torch.ones(g.n, dtype=torch.float64, device="cuda")
+    R0 = torch.empty_like(W)
+    R1 = torch.empty_like(W)
+    _, st0 = pr.pr_solve(lv, C, W, R0, eps=1e-6, precision=1)
+    _, st1 = pr.pr_solve(lv, C, W, R1, eps=1e-6, precision=1, warm_start=net)
+    assert st1["ws_accepted"] + st1["ws_rejected"] == 1
+    ref, _, _ = pagerank_power_series(g.n, g.row_ptr, g.col, C, np.ones(g.n), eps=1e-13)
+    assert np.abs(R1.cpu().numpy() - ref).sum() / ref.sum() <= 1e-6
+    print(f"gang SCC: kept {st1['ws_accepted']}, terms {st0['iters_sum']} -> {st1['iters_sum']}",
+          file=sys.stderr, flush=True)
+    if st1["ws_accepted"]:
+        assert st1["iters_sum"] < st0["iters_sum"]
