@@ -1,11 +1,11 @@
 """Benchmark: componentwise PageRank vs plain power series on one MI355X.
 
-One step = one pr_solve of the componentwise method (Sec. 3.3: boundary
+One step = one pr_solve of the componentwise method (Sec. 4.3: boundary
 mass, one-vertex components, CAC sweeps, SCC power series started from the
 learned guess where it passes the residual test, output) on the web-like
 graph of 1M vertices / 10M edges, with the plan resident on the device.  The
 same solve from the plain start and the plain whole-graph power series
-(Sec. 4.2, method 1) are timed the same way beside it.  All stop on the
+(Sec. 5.2, method 1) are timed the same way beside it.  All stop on the
 1-norm certificate at 1e-6.
 
 Prints ONE JSON line.  --gpus N > 1 is refused (single-GPU build).
@@ -87,15 +87,30 @@ def load_traffic(path, kernel):
     return k["hbm_bytes_per_launch"]
 
 
-def source_hash():
+def _strip_comments(src):
+    """C/C++ source without comments and blank runs: what the compiler sees."""
+    import re
+
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return re.sub(r"\s+", " ", src).strip()
+
+
+def source_hash(read=None):
+    """Hash of the library's sources with comments removed: a counter summary
+    stays valid across comment-only edits and is void after any code change."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1609_09068_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + f.read())
+            if read is None:
+                with open(os.path.join(csrc, name)) as f:
+                    text = f.read()
+            else:
+                text = read(name)
+            h.update(name.encode() + _strip_comments(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,11 +1,11 @@
 """Seeded graph generators.
 
 The paper measures on the Google 2002 web graph and on a Barabasi-Albert graph
-(Sec. 4.1).  Neither is available here, so these generators plant the shape
+(Sec. 5.1).  Neither is available here, so these generators plant the shape
 that matters for the componentwise method instead: a block of strongly
 connected vertices (a giant SCC for the web-like recipe), many small SCCs, many
 acyclic tree/chain regions that become CACs, dangling vertices, heavy-tailed
-out-degrees and a DAG of blocks several tens of levels deep (Sec. 4.1 and the
+out-degrees and a DAG of blocks several tens of levels deep (Sec. 5.1 and the
 statistics quoted for the web graph there).
 
 A graph is returned as CSR over out-edges: ``row_ptr`` int64[n+1] and

@@ -5,11 +5,11 @@
  * PageRank algorithm" (arXiv 1609.09068).  The library computes the
  * non-normalised PageRank R^(3) of Def. 3.5, i.e. the solution of
  *
- *        (I - c A^T) R = W                                          (Sec. 3.3)
+ *        (I - c A^T) R = W                                          (Sec. 4.3)
  *
  * where A is the adjacency matrix of the input graph with every non-zero row
  * scaled to sum to one (Def. 3.4).  Self-loops are ignored everywhere, as in
- * the experiments (Sec. 4.2); a repeated edge counts with its multiplicity
+ * the experiments (Sec. 5.2); a repeated edge counts with its multiplicity
  * in A and in the out-degree.
  *
  * Conventions for every entry point
@@ -53,9 +53,9 @@ typedef struct pr_mlp_s pr_mlp_t;
 /* ------------------------------------------------------------- partition */
 
 /*
- * pr_partition -- SCC/CAC partition of Sec. 3.1 (Theorem 3.1), on the host.
+ * pr_partition -- SCC/CAC partition of Sec. 4.1 (Theorem 3.1), on the host.
  *
- * Runs the modified Tarjan depth-first search of Sec. 3.1 (iterative, so a
+ * Runs the modified Tarjan depth-first search of Sec. 4.1 (iterative, so a
  * path of 10^7 vertices is fine): strongly connected components are found as
  * in Tarjan's algorithm, levels are propagated during the search, and a
  * one-vertex component that points to CACs one level below it (and to no SCC
@@ -64,7 +64,7 @@ typedef struct pr_mlp_s pr_mlp_t;
  * Result (read with pr_partition_get) is the unique partition of
  * Theorem 3.1 in canonical form:
  *   comp[v]        component id, numbered in order of first appearance while
- *                  scanning v = 0..n-1 (Sec. 3.1, numbering pass)
+ *                  scanning v = 0..n-1 (Sec. 4.1, numbering pass)
  *   comp_level[k]  0-based level (Def. 3.3): a component with no edge to
  *                  another component has level 0
  *   comp_type[k]   1 = SCC of two or more vertices, 0 = CAC (one-vertex
@@ -115,11 +115,11 @@ typedef struct pr_build_opts {
 void pr_default_build_opts(pr_build_opts* o);
 
 /*
- * pr_build_levels -- the intermediate step of Sec. 3.2, on the device.
+ * pr_build_levels -- the intermediate step of Sec. 4.2, on the device.
  *
  * Copies the CSR to the device and builds, with HIP kernels, the solve
  * plan: components sorted by level (descending), type and size (descending),
- * ties by id (Sec. 3.2); vertices renumbered level-major and component-major
+ * ties by id (Sec. 4.2); vertices renumbered level-major and component-major
  * (topological order inside CACs); edges split into the pull CSR of edges
  * between components (used once, eq. PR:levels) and of edges inside
  * components; 1/outdeg; the work list of the persistent solve kernel.
@@ -153,11 +153,11 @@ int32_t pr_levels_get_info(const pr_levels_t* lv, pr_levels_info* info);
 
 /* ------------------------------------------------------------- the solve */
 
-#define PR_METHOD_COMPONENTWISE 0 /* level by level, Sec. 3.3 */
-#define PR_METHOD_PLAIN 1         /* whole-graph power series, Sec. 3.3.2 / Sec. 4.2 method 1 */
+#define PR_METHOD_COMPONENTWISE 0 /* level by level, Sec. 4.3 */
+#define PR_METHOD_PLAIN 1         /* whole-graph power series, Sec. 4.3.2 / Sec. 5.2 method 1 */
 
 #define PR_STOP_CERT_L1 0      /* per component: ||P_k||_1 <= eps (1-c) ||W'_C||_1 */
-#define PR_STOP_PAPER_MAXABS 1 /* per component: max(P_k) < tol (listing of Sec. 3.3.2) */
+#define PR_STOP_PAPER_MAXABS 1 /* per component: max(P_k) < tol (listing of Sec. 4.3.2) */
 
 #define PR_PREC_MIXED 0 /* series terms and SpMV in FP32; R, sums, norms, boundary mass in FP64 */
 #define PR_PREC_FP64 1  /* everything in FP64 */
@@ -170,7 +170,7 @@ typedef struct pr_solve_opts {
   double eps;        /* PR_STOP_CERT_L1 target (relative 1-norm error bound); default 1e-6 */
   double tol;        /* PR_STOP_PAPER_MAXABS threshold; default 1e-9 */
   int64_t max_iter;  /* per-component iteration cap; default 100000 */
-  pr_mlp_t* warm_start;/* NULL = start every SCC from P_0 = W' (Sec. 3.3.2) */
+  pr_mlp_t* warm_start;/* NULL = start every SCC from P_0 = W' (Sec. 4.3.2) */
   int32_t trace;        /* 1 = record the item timeline (pr_levels_debug what = 4); slows the solve */
   int32_t kernel_timing;/* 1 = HIP events around every launch; per-family times land in the stats
                            (ignored with use_graph) */
@@ -211,13 +211,13 @@ typedef struct pr_solve_stats {
  * W_dev: n doubles (device), the weight vector in the caller's vertex order,
  *        non-negative and finite.
  * R_dev: n doubles (device), written with R in the caller's vertex order.
- * COMPONENTWISE follows Sec. 3.3: levels from the highest down, each vertex's
+ * COMPONENTWISE follows Sec. 4.3: levels from the highest down, each vertex's
  * weight raised by the rank flowing in from higher levels (eq. PR:levels),
  * one-vertex components copied, CACs solved exactly in topological order
- * (Sec. 3.3.1), SCCs by the power series (Sec. 3.3.2) with the chosen stop
+ * (Sec. 4.3.1), SCCs by the power series (Sec. 4.3.2) with the chosen stop
  * rule.  PLAIN runs the power series on the whole graph with the same rule.
  * With PR_STOP_CERT_L1 the relative 1-norm error of R is below eps in exact
- * arithmetic (Sec. 3.4); stats->cert_rel reports the bound for this run.
+ * arithmetic (Sec. 4.4); stats->cert_rel reports the bound for this run.
  * The call returns after the stream work has completed.
  * Errors: PR_EINVAL (c outside (0,1), eps <= 0, tol <= 0, W negative or not
  * finite, method PLAIN without build_plain), PR_EHIP.
@@ -249,8 +249,8 @@ int32_t pr_levels_debug(const pr_levels_t* lv, int32_t what, void* host_out);
 
 /* ------------------------------------------------------ starting guess
  *
- * The paper starts each SCC's power series from P_0 = W'_C (Sec. 3.3.2) and
- * names an earlier ranking as a possible initial rank (Sec. 5).  This part
+ * The paper starts each SCC's power series from P_0 = W'_C (Sec. 4.3.2) and
+ * names an earlier ranking as a possible initial rank (Sec. 7).  This part
  * learns a start: a network 4 -> 64 -> 64 -> 1 (GELU after both hidden
  * layers; BF16 operands on the matrix cores, FP32 accumulation) maps four
  * features of an SCC vertex v,

@@ -9,12 +9,12 @@ code with the HIP library: no kernels, headers, helpers or tables.
 Modules
 -------
 pagerank      Def. 3.4 / 3.5 (dense solve, eigenvector route), the power
-              series of Sec. 3.3.2 with both stop rules.
-partition     the SCC/CAC partition of Sec. 3.1: the merge process of
+              series of Sec. 4.3.2 with both stop rules.
+partition     the SCC/CAC partition of Sec. 4.1: the merge process of
               Theorem 3.1 (primary) and the modified Tarjan DFS (second,
               independent route), canonical component numbering.
-componentwise the level-by-level solve of Sec. 3.3 (eq. PR:levels, the CAC
-              sweep of Sec. 3.3.1, the power series per SCC).
+componentwise the level-by-level solve of Sec. 4.3 (eq. PR:levels, the CAC
+              sweep of Sec. 4.3.1, the power series per SCC).
 warmstart     per-vertex features and the 4-64-64-1 GELU network used for the
               learned starting guess (forward, backward, Adam) in float64.
 """

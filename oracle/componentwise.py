@@ -1,20 +1,20 @@
-"""Serial componentwise PageRank (Sec. 3.3).
+"""Serial componentwise PageRank (Sec. 4.3).
 
 Test infrastructure only (see the package docstring).
 
-Levels are solved from the highest down to 0 (Sec. 3.3, steps 1-4).  Before a
+Levels are solved from the highest down to 0 (Sec. 4.3, steps 1-4).  Before a
 level is solved its weights are raised by the rank flowing in from every
 higher level (Corollary 3.2 and eq. PR:levels):
 
     W'_v = W_v + c * sum_{u -> v, level(u) > level(v)} R_u / outdeg(u)
 
-Then, per component of the level (Sec. 3.3, the four-way method choice with
+Then, per component of the level (Sec. 4.3, the four-way method choice with
 loops ignored):
   * a one-vertex component has R_v = W'_v,
   * a CAC of two or more vertices is solved exactly by the in-degree
-    countdown sweep of Sec. 3.3.1 (a vertex enters the queue once all of its
+    countdown sweep of Sec. 4.3.1 (a vertex enters the queue once all of its
     in-edges inside the CAC have been used),
-  * an SCC is solved by the power series of Sec. 3.3.2 restricted to the
+  * an SCC is solved by the power series of Sec. 4.3.2 restricted to the
     component, started from P_0 = W'_C.
 The SCCs of one level are iterated together as one block-diagonal product
 (there are no edges between different components of a level), but each keeps
@@ -109,7 +109,7 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
 
 
 def _cac_sweep(Vc, Wp, comp, c, deg, nbr_ptr, nbr, R):
-    """Sec. 3.3.1 with loops ignored: v.degree = in-degree inside v's CAC,
+    """Sec. 4.3.1 with loops ignored: v.degree = in-degree inside v's CAC,
     v.rank = W'_v; a vertex is dequeued only after all its in-edges inside the
     CAC have delivered rank, and then pushes c*rank/outdeg along each out-edge
     inside the CAC.  Every vertex and edge is used once."""
@@ -144,7 +144,7 @@ def _cac_sweep(Vc, Wp, comp, c, deg, nbr_ptr, nbr, R):
 
 
 def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter, feat=None):
-    """Power series of Sec. 3.3.2 on each SCC of one level.
+    """Power series of Sec. 4.3.2 on each SCC of one level.
 
     With a starting guess (feat), a component whose guess passes the residual
     test starts from p = r_0 and R = R_0 + r_0 with no term counted yet; one

@@ -4,8 +4,8 @@ Test infrastructure only (see the package docstring).
 
 Conventions (Def. 3.4): A is the adjacency matrix with every non-zero row
 scaled to sum to one.  Self-loops are ignored, as in the experiments of
-Sec. 4.2; a repeated edge counts with its multiplicity (the paper assumes
-simple graphs, Sec. 2, so this only matters for inputs that are not).
+Sec. 5.2; a repeated edge counts with its multiplicity (the paper assumes
+simple graphs, Sec. 3, so this only matters for inputs that are not).
 Dangling vertices have a zero row.
 """
 from __future__ import annotations
@@ -50,7 +50,7 @@ def transition_T_csr(n, row_ptr, col):
 
 
 def pagerank_dense(n, row_ptr, col, c, W):
-    """R^(3) as the solution of (I - c A^T) R = W (Sec. 3.3, third method;
+    """R^(3) as the solution of (I - c A^T) R = W (Sec. 4.3, third method;
     equivalent to Def. 3.5).  LAPACK via numpy; for small n only."""
     A = transition_dense(n, row_ptr, col)
     return np.linalg.solve(np.eye(n) - c * A.T, np.asarray(W, dtype=np.float64))
@@ -111,16 +111,16 @@ def pagerank_random_walks(n, row_ptr, col, c, W, walks_per_unit, seed):
 
 def pagerank_power_series(n, row_ptr, col, c, W, *, stop="cert", eps=1e-6, tol=None,
                           max_iter=1_000_000, AT=None):
-    """The power series of Sec. 3.3.2 on the whole graph (the paper's baseline,
-    "method 1" of Sec. 4.2):  P_0 = W,  P_{k+1} = c A^T P_k,  R = sum_k P_k.
+    """The power series of Sec. 4.3.2 on the whole graph (the paper's baseline,
+    "method 1" of Sec. 5.2):  P_0 = W,  P_{k+1} = c A^T P_k,  R = sum_k P_k.
 
     Stop rules (one term P_k is added per iteration, k >= 1):
       "cert":  stop after the first k with ||P_k||_1 <= eps (1-c) ||W||_1.
-               Because ||c A^T x||_1 <= c ||x||_1 (Sec. 3.4), the neglected tail
+               Because ||c A^T x||_1 <= c ||x||_1 (Sec. 4.4), the neglected tail
                is at most c/(1-c) ||P_k||_1 <= c eps ||W||_1 <= c eps ||R*||_1,
                a relative 1-norm error below eps.
       "paper": stop after the first k with max(P_k) < tol (the listing of
-               Sec. 3.3.2; an absolute max-norm rule).
+               Sec. 4.3.2; an absolute max-norm rule).
     Returns (R, iterations, ||P_K||_1).
     """
     if AT is None:

@@ -1,4 +1,4 @@
-"""The SCC/CAC partition of Sec. 3.1.
+"""The SCC/CAC partition of Sec. 4.1.
 
 Test infrastructure only (see the package docstring).
 
@@ -8,22 +8,22 @@ Two independent routes compute the same partition:
   strongly connected components from scipy, then the merge process of
   Theorem 3.1 applied bottom-up over the DAG of SCCs.
 * ``partition_dfs`` (small graphs): the modified Tarjan depth-first search of
-  Sec. 3.1 (Discover / Explore / Finish with a merge-find forest), written
+  Sec. 4.1 (Discover / Explore / Finish with a merge-find forest), written
   from the description of those three steps.
 
 Both return the canonical form used everywhere in this project:
 
   comp[v]        component id; ids are given in order of first appearance
                  while scanning v = 0, 1, ..., n-1 (the numbering pass at the
-                 end of Sec. 3.1, with its counter initialised once)
+                 end of Sec. 4.1, with its counter initialised once)
   comp_level[k]  0-based level: components with no edge to another component
                  have level 0 (Def. 3.3 and Fig. 1)
   comp_type[k]   1 for an SCC of two or more vertices, 0 for a CAC (a
-                 one-vertex component counts as a CAC, Sec. 2 after Def. 3.3)
+                 one-vertex component counts as a CAC, Sec. 3 after Def. 3.3)
   comp_size[k]   number of vertices
   n_levels       1 + the largest level (0 for the empty graph)
 
-Self-loops are ignored in the component finding (Sec. 3.1).
+Self-loops are ignored in the component finding (Sec. 4.1).
 """
 from __future__ import annotations
 
@@ -198,7 +198,7 @@ def partition_theorem(n, row_ptr, col):
 
 
 class _MergeFind:
-    """Merge-find forest with union by depth (the .depth value of Sec. 3.1)."""
+    """Merge-find forest with union by depth (the .depth value of Sec. 4.1)."""
 
     def __init__(self, n):
         self.parent = list(range(n))
@@ -224,7 +224,7 @@ class _MergeFind:
 
 
 def partition_dfs(n, row_ptr, col):
-    """Modified Tarjan depth-first search of Sec. 3.1, iterative.
+    """Modified Tarjan depth-first search of Sec. 4.1, iterative.
 
     Discover sets index and lowlink to a running counter and the level to 1
     (levels are 1-based inside the search and shifted to 0-based at the end).

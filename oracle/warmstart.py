@@ -2,14 +2,14 @@
 
 Test infrastructure only (see the package docstring).
 
-The paper starts every SCC's series from P_0 = W'_C (Sec. 3.3.2) and notes
-that a previous ranking could serve as the initial rank (Sec. 5).  Here a
+The paper starts every SCC's series from P_0 = W'_C (Sec. 4.3.2) and notes
+that a previous ranking could serve as the initial rank (Sec. 7).  Here a
 small network predicts, per SCC vertex, the logarithm of its rank relative to
 the component's mean weight, from four local quantities.  The prediction R_0
 is only a starting point: the series is then run on the residual
     r_0 = W'_C + c A_CC^T R_0 - R_0,     R = R_0 + sum_k (c A_CC^T)^k r_0,
 which converges to the same R_C = (I - c A_CC^T)^{-1} W'_C (Def. 3.5,
-Sec. 3.3) whatever R_0 is.  The guess is kept for a component only when
+Sec. 4.3) whatever R_0 is.  The guess is kept for a component only when
 ||r_0||_1 < ||c A_CC^T W'_C||_1, the norm of the first term the plain start
 would add; otherwise the component falls back to the plain series.
 

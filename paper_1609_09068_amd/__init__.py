@@ -1,7 +1,7 @@
 """Componentwise PageRank on MI355X (gfx950).
 
-The SCC/CAC partition of Sec. 3.1 runs on the host (C++); the intermediate
-step (Sec. 3.2) and the level-by-level PageRank step (Sec. 3.3) run in HIP
+The SCC/CAC partition of Sec. 4.1 runs on the host (C++); the intermediate
+step (Sec. 4.2) and the level-by-level PageRank step (Sec. 4.3) run in HIP
 kernels.  Everything is reached through the C ABI of libpr.so (include/pr.h);
 this module only marshals arguments.  torch tensors provide device buffers
 and the stream.

@@ -1,6 +1,6 @@
-// Host SCC/CAC partition: the modified Tarjan depth-first search of Sec. 3.1.
+// Host SCC/CAC partition: the modified Tarjan depth-first search of Sec. 4.1.
 //
-// Per vertex the search keeps (Sec. 3.1): a discovery index, a lowlink, a
+// Per vertex the search keeps (Sec. 4.1): a discovery index, a lowlink, a
 // level, a merge-find parent and depth (union by depth), and a state that
 // says whether the vertex is still on the Tarjan stack or already placed in
 // an SCC or a CAC.  The three steps per vertex are
@@ -15,11 +15,11 @@
 //             an SCC of two or more vertices on that level (Theorem 3.1);
 //             a merge lowers the head's level by one.
 // The search is iterative (explicit frame stack), as in the paper's
-// implementation (Sec. 4), so long paths cannot overflow the call stack.
+// implementation (Sec. 5), so long paths cannot overflow the call stack.
 // Levels are 1-based during the search and exported 0-based (Def. 3.3 and
 // Fig. 1 put components without outgoing edges on level 0).
 // Component ids: one pass over v = 0..n-1 numbering the merge-find roots in
-// order of first appearance (Sec. 3.1, numbering pass).
+// order of first appearance (Sec. 4.1, numbering pass).
 #include <algorithm>
 #include <cstring>
 #include <new>

@@ -1,13 +1,13 @@
-// The intermediate step of Sec. 3.2 on the device: component order, vertex
+// The intermediate step of Sec. 4.2 on the device: component order, vertex
 // renumbering, split of the edges into "between components" and "inside a
 // component" pull CSRs, 1/outdeg, and the work list of the solve kernel.
 //
-// Component order (Sec. 3.2): level descending, then kind (SCC, CAC with two
+// Component order (Sec. 4.2): level descending, then kind (SCC, CAC with two
 // or more vertices, one-vertex component), then size descending, ties by
 // component id.  Vertices are laid out component by component in that
 // order; inside a component they follow the reverse of the order in which
 // the depth-first search closed their SCCs, which is a topological order of
-// the CAC's edges (Sec. 3.3.1 needs every in-edge of a vertex used before
+// the CAC's edges (Sec. 4.3.1 needs every in-edge of a vertex used before
 // the vertex itself).  Because levels are laid out from the highest down,
 // every edge between components points from a lower position to a higher
 // one, and inside a pull row the sources from other components (all at

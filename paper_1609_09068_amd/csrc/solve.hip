@@ -1,4 +1,4 @@
-// The PageRank step of Sec. 3.3 on the device.
+// The PageRank step of Sec. 4.3 on the device.
 //
 // The plan (plan.hip) orders vertices level by level from the highest level
 // down, components within a level by class and size, CAC vertices in
@@ -11,13 +11,13 @@
 //                   higher level or from earlier in its CAC's topological
 //                   order, so R_v = W_v + sum_{u -> v} x_u with
 //                   x_u = c R_u / outdeg(u) is exact in one pass (eq.
-//                   PR:levels, Sec. 3.3.1).
+//                   PR:levels, Sec. 4.3.1).
 //      ITEM_SMALL   up to four SCCs, one wavefront each, terms kept in LDS
 //                   and registers.
 //      ITEM_MEDIUM  one SCC per workgroup, rows staged in LDS when they fit.
 //             SCC items gather W'_C (eq. PR:levels), then run the power
 //             series P_0 = W'_C, P_{k+1} = c A_CC^T P_k, R_C = sum_k P_k
-//             (Sec. 3.3.2) until the stop rule holds.
+//             (Sec. 4.3.2) until the stop rule holds.
 //  * gang     the SCCs of a level with many internal edges (and, for the
 //             plain method, the whole graph) are iterated by every
 //             workgroup, one launch per term; each launch also reads the
@@ -456,7 +456,7 @@ __device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const 
 
 // ------------------------------------------------------------------ items
 
-// One-vertex components and CAC vertices (Sec. 3.3 first bullet, Sec. 3.3.1).
+// One-vertex components and CAC vertices (Sec. 4.3 first bullet, Sec. 4.3.1).
 // R_v = W_v + (rank from higher levels) + (rank from earlier vertices of
 // v's CAC).  The CAC in-edges split into sources in earlier items, waited for
 // once through the global x, and sources inside this item, whose values are
@@ -1459,7 +1459,7 @@ __global__ __launch_bounds__(kThreads) void k_gang_hubs(SolveParams p, int gang,
   p.gpmx[slot] = fabs((double)s);
 }
 
-// Starting guess for the SCCs of a gang (Sec. 3.3.2 series started from a
+// Starting guess for the SCCs of a gang (Sec. 4.3.2 series started from a
 // predicted R_0, see warm_preamble): three launches between term 0 and
 // term 1.  step 0: the first plain term p_1 = c A^T W' (from wx = c W' /
 // outdeg), the features, the network and R_0 (wres = c R_0 / outdeg);
@@ -2005,7 +2005,7 @@ static uint64_t mix64(uint64_t h, uint64_t x) {
 }
 
 // number of series terms after which every SCC has met the stop rule in
-// exact arithmetic: ||P_k||_1 <= c^k ||W'_C||_1 (Sec. 3.4), plus slack for
+// exact arithmetic: ||P_k||_1 <= c^k ||W'_C||_1 (Sec. 4.4), plus slack for
 // rounding; the paper rule uses max(P_k) <= ||P_k||_1 and ||W'_C||_1 <= sumW/(1-c)
 static int64_t term_bound(const pr_solve_opts& o, double c, double sumW) {
   double k;

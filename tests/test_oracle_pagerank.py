@@ -1,4 +1,4 @@
-"""Pins for the oracle's PageRank routes (Defs. 3.4-3.6, Sec. 3.3, Sec. 3.4)."""
+"""Pins for the oracle's PageRank routes (Defs. 3.4-3.6, Sec. 4.3, Sec. 4.4)."""
 import itertools
 import math
 
@@ -82,7 +82,7 @@ def test_bidirected_star():
 
 
 def test_singletons_keep_their_weight():
-    # Sec. 3.3: a component of isolated vertices has R = W (loops ignored)
+    # Sec. 4.3: a component of isolated vertices has R = W (loops ignored)
     rp = np.array([0, 1, 1, 2], dtype=np.int64)
     col = np.array([0, 2], dtype=np.int32)  # vertex 0 has a loop, 2 a loop
     W = np.array([0.3, 2.0, 5.0])
@@ -157,7 +157,7 @@ def test_brute_force_paths_on_dags(seed):
 # ---------------------------------------------------------- stop rules
 
 def test_paper_mode_iterations_on_a_cycle():
-    """Sec. 4.2: a bottom-level SCC needs about log(tol)/log(c) iterations;
+    """Sec. 5.2: a bottom-level SCC needs about log(tol)/log(c) iterations;
     on a cycle P_k = c^k exactly, so the listing's rule stops after 128."""
     m = 10
     g = _g(m, [(i, (i + 1) % m) for i in range(m)])
@@ -188,7 +188,7 @@ def test_certificate_bounds_relative_error(eps):
     for R in (Rp, Rc):
         err = np.sum(np.abs(R - ref)) / np.sum(ref)
         assert err <= eps
-        assert np.all(R <= ref * (1 + 1e-12))  # monotone from below (Sec. 3.4)
+        assert np.all(R <= ref * (1 + 1e-12))  # monotone from below (Sec. 4.4)
 
 
 def test_linearity_in_w():

@@ -1,4 +1,4 @@
-"""Pins for the oracle's SCC/CAC partition (Sec. 3.1, Theorem 3.1)."""
+"""Pins for the oracle's SCC/CAC partition (Sec. 4.1, Theorem 3.1)."""
 import json
 import os
 
