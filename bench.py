@@ -181,6 +181,42 @@ def calib_copy(torch, mib):
     log(f"calibration copy: {mib} MiB read + {mib} MiB write")
 
 
+def residual_bound(g, c, R, AT=None):
+    from oracle.pagerank import residual_bound as rb
+
+    return rb(g.n, g.row_ptr, g.col, c, np.ones(g.n), R, AT)
+
+
+def run_study(args, pr, torch, g, lv, info, W, R, t_part, t_build):
+    rows = []
+    AT = None
+    for c in (0.85, 0.99):
+        for prec in (0, 1):
+            for meth in (0, 1):
+                name = ("componentwise" if meth == 0 else "plain") + ("/mixed" if prec == 0 else "/fp64")
+                st = None
+                ms = []
+                for rep in range(1 + max(args.steps, 1)):
+                    rc, st = pr.pr_solve(lv, c, W, R, method=meth, precision=prec, eps=args.eps, kernel_timing=1)
+                    if rep:
+                        ms.append(st["kernel_ms"])
+                bound, AT = residual_bound(g, c, R.cpu().numpy(), AT)
+                t = float(np.median(ms))
+                kt = st["kt_ms"]
+                fam = 1 if meth == 1 else int(np.argmax(kt))
+                b = family_bytes(fam, info, st, prec, meth == 1)
+                row = {"c": c, "path": name, "ms": round(t, 3), "gedge_iter_s": round(st["edge_iters"] / t / 1e6, 3),
+                       "terms_max": st["iters_max"], "edge_iters": st["edge_iters"],
+                       "rel_l1_bound_vs_oracle_residual": bound, "cert_rel": st["cert_rel"],
+                       "dominant_kernel": FAMILIES[fam],
+                       "dominant_kernel_alg_gbs": round(b / (kt[fam] * 1e-3) / 1e9, 1) if kt[fam] > 0 else None}
+                log(json.dumps(row))
+                rows.append(row)
+    print(json.dumps({"study": "precision", "config": args.config, "n": g.n, "m": g.m, "eps": args.eps,
+                      "partition_ms": round(t_part * 1e3, 1), "build_ms": round(t_build * 1e3, 1),
+                      "rows": rows, "device": torch.cuda.get_device_name(0)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +228,13 @@ def main():
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy check against the oracle")
+    ap.add_argument("--check", choices=["auto", "reference", "residual"], default="auto",
+                    help="accuracy against the oracle: its FP64 series at eps 1e-12 (reference), or the bound "
+                         "||W - (I - cA^T)R||_1 / ((1-c)||R||_1) from one FP64 product (residual); auto picks the "
+                         "reference up to 20M edges")
+    ap.add_argument("--study", action="store_true",
+                    help="precision study: c in {0.85, 0.99} x {mixed, fp64} x {componentwise, plain}; prints one "
+                         "JSON line of its own instead of the benchmark line")
     ap.add_argument("--graph", type=int, default=0, help="replay a captured hipGraph")
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--small-cutoff", type=int, default=0)
@@ -227,7 +270,7 @@ def main():
     dev_name = torch.cuda.get_device_name(0)
     log("device", dev_name)
     t0 = time.perf_counter()
-    g = config_graph(args.config)
+    g = config_graph(args.config, log=log)
     log(f"graph {args.config}: n={g.n} m={g.m} gen {time.perf_counter() - t0:.1f}s")
 
     t0 = time.perf_counter()
@@ -254,6 +297,9 @@ def main():
     W = torch.ones(g.n, dtype=torch.float64, device="cuda")
     R = torch.empty_like(W)
     Rp = torch.empty_like(W)
+    if args.study:
+        run_study(args, pr, torch, g, lv, info, W, R, t_part, t_build)
+        return
     common = dict(eps=args.eps, precision=args.precision, use_graph=args.graph,
                   kernel_timing=0 if args.graph else 1)
 
@@ -328,7 +374,8 @@ def main():
                     for i in range(4)}}
 
     acc = None
-    if not args.no_check:
+    check = args.check if args.check != "auto" else ("reference" if g.m <= 20_000_000 else "residual")
+    if not args.no_check and check == "reference":
         from oracle.pagerank import pagerank_power_series
 
         t0 = time.perf_counter()
@@ -341,6 +388,13 @@ def main():
                "plain": float(np.abs(Rpl - ref).sum() / ref.sum()),
                "cert_componentwise": s["cert_rel"], "cert_plain": sp["cert_rel"],
                "reference": f"oracle plain power series, FP64, eps 1e-12 ({kref} terms)"}
+    elif not args.no_check:
+        b1, AT = residual_bound(g, args.c, R.cpu().numpy())
+        b2, _ = residual_bound(g, args.c, Rn.cpu().numpy(), AT)
+        b3, _ = residual_bound(g, args.c, Rp.cpu().numpy(), AT)
+        acc = {"componentwise": b1, "componentwise_plain_start": b2, "plain": b3,
+               "cert_componentwise": s["cert_rel"], "cert_plain": sp["cert_rel"],
+               "reference": "bound from the oracle's FP64 residual ||W - (I - cA^T)R||_1 / ((1-c)||R||_1)"}
 
     cpu = None
     if not args.no_cpu:

@@ -258,13 +258,15 @@ def web_like(n: int, m: int, seed: int, *, giant_frac: float = 0.4, cac_frac: fl
              n_levels: int = 60, scc_median: float = 12.0, scc_sigma: float = 1.0,
              cac_median: float = 8.0, cac_sigma: float = 1.0, intra_frac: float = 0.75,
              scc_tail_max: int | None = None, level_width: str = "uniform",
-             p_next_level: float = 0.5) -> Graph:
+             p_next_level: float = 0.5, log=None) -> Graph:
     """Web-like graph built from planted blocks placed on ``n_levels`` planned
     levels.  Edges between blocks only go from a higher planned level to a
     lower one, so the planted SCC blocks are exactly the SCCs and the tree and
     chain blocks are acyclic.  Out-degrees follow a truncated Zipf law scaled
     to ~m edges; edge targets are drawn proportionally to a per-vertex Zipf
-    "fitness", so in-degrees are heavy-tailed as well."""
+    "fitness", so in-degrees are heavy-tailed as well.  ``log`` (optional)
+    receives a line as each phase ends."""
+    say = log or (lambda *_: None)
     rng = np.random.default_rng(seed)
     n_giant = int(round(giant_frac * n))
     n_cac = int(round(cac_frac * n))
@@ -313,6 +315,7 @@ def web_like(n: int, m: int, seed: int, *, giant_frac: float = 0.4, cac_frac: fl
     np.maximum.at(lev_hi, vlvl, np.arange(n) + 1)
 
     is_scc = vkind <= 1
+    say(f"generator: {nb} blocks on {nl} levels planned")
     # --- intra edges -------------------------------------------------------
     # SCC blocks: one random Hamiltonian cycle each
     scc_v = np.nonzero(is_scc)[0]
@@ -336,6 +339,7 @@ def web_like(n: int, m: int, seed: int, *, giant_frac: float = 0.4, cac_frac: fl
     cac_dst = np.concatenate([tree_v, chain_v])
     children = np.bincount(cac_src, minlength=n)
 
+    say("generator: block-internal edges drawn")
     # --- degrees -----------------------------------------------------------
     leaf = (~is_scc) & (children == 0)
     n_dang = int(round(dangling_frac * n))
@@ -378,7 +382,9 @@ def web_like(n: int, m: int, seed: int, *, giant_frac: float = 0.4, cac_frac: fl
     src = np.concatenate([cyc_src, cac_src, es, isrc])
     dst = np.concatenate([cyc_dst, cac_dst, ed, idst])
     key = src * n + dst
+    say(f"generator: {len(key)} candidate edges drawn")
     _, first = np.unique(key, return_index=True)
+    say("generator: duplicates removed")
     structural = first < n_struct
     excess = len(first) - m
     if excess > 0:

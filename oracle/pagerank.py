@@ -147,3 +147,15 @@ def pagerank_power_series(n, row_ptr, col, c, W, *, stop="cert", eps=1e-6, tol=N
         else:
             raise ValueError(stop)
     return R, k, last
+
+
+def residual_bound(n, row_ptr, col, c, W, R, AT=None):
+    """Certificate of any candidate R (Sec. 4.4): the residual r = W - (I - c A^T) R
+    satisfies R* - R = (I - c A^T)^{-1} r, and the column sums of c A^T are at
+    most c, so ||R* - R||_1 <= ||r||_1 / (1 - c).  Returns that bound divided
+    by ||R||_1 (a relative 1-norm error bound) and A^T for reuse."""
+    if AT is None:
+        AT = transition_T_csr(n, row_ptr, col)
+    R = np.asarray(R, dtype=np.float64)
+    r = np.asarray(W, dtype=np.float64) - R + c * (AT @ R)
+    return float(np.abs(r).sum() / ((1.0 - c) * np.abs(R).sum())), AT

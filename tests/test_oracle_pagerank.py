@@ -223,3 +223,22 @@ def test_planted_transpose_mistake_is_caught():
     wrong = np.linalg.solve(np.eye(k) - C * A, np.ones(k))
     expect = np.array([(1 - C ** (j + 1)) / (1 - C) for j in range(k)])
     assert not np.allclose(wrong, expect, rtol=1e-6)
+
+
+def test_residual_bound_covers_the_error():
+    from graphgen import random_digraph
+    from oracle.pagerank import pagerank_dense, residual_bound
+
+    g = random_digraph(300, 1500, seed=17)
+    c = 0.85
+    W = np.random.default_rng(17).uniform(0, 2, g.n)
+    exact = pagerank_dense(g.n, g.row_ptr, g.col, c, W)
+    rng = np.random.default_rng(3)
+    for scale in (1e-3, 1e-6, 0.3):
+        R = exact * (1 + scale * rng.normal(size=g.n))
+        bound, _ = residual_bound(g.n, g.row_ptr, g.col, c, W, R)
+        err = np.abs(R - exact).sum() / np.abs(R).sum()
+        assert err <= bound
+        assert bound < 50 * err  # and it is not vacuous on these perturbations
+    bound, _ = residual_bound(g.n, g.row_ptr, g.col, c, W, exact)
+    assert bound < 1e-13
