@@ -243,8 +243,9 @@ def main():
                     help="plan autotuner: 0 off, 1 cached or sweep, 2 sweep")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "hbm_traffic_c2_web_1m.json"),
-                    help="committed counter summary that supplies roofline.traffic")
+    ap.add_argument("--traffic", default=None,
+                    help="committed counter summary that supplies roofline.traffic "
+                         "(default: profiles/hbm_traffic_<config>.json)")
     ap.add_argument("--no-warm", action="store_true", help="no starting guess in the headline step")
     ap.add_argument("--warm-net", default=os.path.join(ROOT, "paper_1609_09068_amd", "data", "warm_web.prmlp"))
     ap.add_argument("--only", choices=["componentwise", "plain"],
@@ -257,6 +258,8 @@ def main():
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.calib_copy_mb or 1024,
                       args.summarize_pmc[2], args.only or "componentwise")
         return
+    if args.traffic is None:
+        args.traffic = os.path.join(ROOT, "profiles", f"hbm_traffic_{args.config}.json")
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)

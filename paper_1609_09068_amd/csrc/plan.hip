@@ -5,10 +5,12 @@
 // Component order (Sec. 4.2): level descending, then kind (SCC, CAC with two
 // or more vertices, one-vertex component), then size descending, ties by
 // component id.  Vertices are laid out component by component in that
-// order; inside a component they follow the reverse of the order in which
-// the depth-first search closed their SCCs, which is a topological order of
-// the CAC's edges (Sec. 4.3.1 needs every in-edge of a vertex used before
-// the vertex itself).  Because levels are laid out from the highest down,
+// order.  Inside a CAC they follow the reverse of the order in which the
+// depth-first search closed their SCCs, which is a topological order of the
+// CAC's edges (Sec. 4.3.1 needs every in-edge of a vertex used before the
+// vertex itself).  Inside an SCC, where any order is valid, they are sorted
+// by out-degree, highest first, so the most-gathered terms share cache
+// lines.  Because levels are laid out from the highest down,
 // every edge between components points from a lower position to a higher
 // one, and inside a pull row the sources from other components (all at
 // higher levels) come before the sources of the vertex's own component.
@@ -54,6 +56,23 @@ __global__ void k_topo_list(const int32_t* emit_pos, int64_t n, uint32_t* list) 
   int64_t v = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (v >= n) return;
   list[n - 1 - emit_pos[v]] = (uint32_t)v;
+}
+
+// secondary vertex key: inside an SCC, out-degree descending (the vertices
+// gathered most often end up next to each other, so their terms share cache
+// lines); every other vertex keeps its topological position (key 0)
+constexpr uint32_t kDegKeyMax = (1u << 20) - 1;
+__global__ void k_vertex_degkey(const uint32_t* list, int64_t n, const int64_t* row_ptr, const int32_t* comp,
+                                const uint8_t* ctype, uint32_t* key) {
+  int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t v = list[i];
+  if (!ctype[comp[v]]) {
+    key[i] = 0u;
+    return;
+  }
+  const int64_t d = row_ptr[v + 1] - row_ptr[v];
+  key[i] = kDegKeyMax - (uint32_t)(d < (int64_t)kDegKeyMax ? d : (int64_t)kDegKeyMax);
 }
 
 __global__ void k_vertex_key(const uint32_t* list, int64_t n, const int32_t* comp, const int32_t* rank_of_id,
@@ -240,6 +259,8 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
   PR_TRY(dalloc(&lv.perm, n));
   if (n) {
     k_topo_list<<<nblk(n), kB, 0, s>>>(d_emit, n, vlist);
+    k_vertex_degkey<<<nblk(n), kB, 0, s>>>(vlist, n, d_rp, d_comp, d_ctype, vkey);
+    PR_TRY(radix_sort_pairs(vkey, vlist, n, 20, s));
     k_vertex_key<<<nblk(n), kB, 0, s>>>(vlist, n, d_comp, lv.comp_rank_of_id, vkey);
     PR_TRY(radix_sort_pairs(vkey, vlist, n, bit_length((uint64_t)std::max<int64_t>(K - 1, 0)), s));
     k_perm_inverse<<<nblk(n), kB, 0, s>>>(vlist, n, lv.perm, iperm);
