@@ -65,7 +65,8 @@ uint64_t hash_csr(int64_t n, const int64_t* row_ptr, const int32_t* col);
 // One work item of a persistent segment kernel.
 struct Item {
   int32_t kind;  // ITEM_*
-  int32_t a, b, c;
+  int32_t a, b;  // ITEM_VERTS: positions [a, b); SMALL: ranks [a, b); MEDIUM: rank a
+  int32_t c;     // ITEM_VERTS: longest chain of CAC edges inside the item (vertices)
 };
 enum : int32_t { ITEM_VERTS = 0, ITEM_SMALL = 1, ITEM_MEDIUM = 2 };
 

@@ -407,8 +407,9 @@ __device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const 
           if (!m) break;
           const int a = __shfl(want, __ffsll(m) - 1, 64);
           bool late = false;
+          unsigned polls = 0;
           while (ld_x(p.x, a) < 0.0) {
-            if (timed_out(p, t0)) {
+            if ((++polls & 15u) == 0u && timed_out(p, t0)) {
               late = true;
               break;
             }
@@ -457,20 +458,48 @@ __device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const 
 // ------------------------------------------------------------------ items
 
 // One-vertex components and CAC vertices (Sec. 4.3 first bullet, Sec. 4.3.1).
-// R_v = W_v + (rank from higher levels) + (rank from earlier vertices of
-// v's CAC).  The CAC in-edges split into sources in earlier items, waited for
-// once through the global x, and sources inside this item, whose values are
-// exchanged through LDS (xl): a chain inside the item then advances one
-// vertex per round at LDS latency.  Sums run in a fixed order: boundary,
-// earlier-item sources, in-item sources, each in edge order.
-__device__ void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* tile, double* xl) {
+// R_v = W_v + (rank from higher levels) + sum over v's CAC in-edges u -> v of
+// c R_u / outdeg(u).  The item's 256 vertices are in topological order.
+//  1. Rank from higher levels (boundary rows) and from CAC sources in earlier
+//     items, waited for through the published x: acc_v.
+//  2. Sources inside the item, through LDS (final R and a state per vertex),
+//     one of two ways chosen by the plan from the item's longest in-item
+//     chain (so the arithmetic depends only on the graph):
+//     a. Short chains: each wavefront on its own, no barrier: a vertex whose
+//        in-item sources are all final adds them in edge order.
+//     b. Long chains: synchronous rounds of the whole workgroup: a
+//        vertex with exactly one in-item source t keeps the affine form
+//        R_v = a_v + b_v R_t (a = acc, b = c / outdeg(t)) and jumps: if t is
+//        final, R_v = a_v + b_v R_t; if t has one source too,
+//        (a_v, b_v, t) <- (a_v + b_v a_t, b_v b_t, t's source), so a chain of
+//        length L resolves in about log2 L rounds (pointer jumping).  A vertex
+//        with several in-item sources waits until all are final and adds
+//        them in edge order.
+// Each vertex publishes x_v = c R_v / outdeg(v) as soon as R_v is final.
+// Every sum has a fixed order (the schedule depends only on the graph).
+constexpr int kCacDeep = 16;  // items with longer in-item chains use pointer jumping
+
+__device__ void run_verts(const SolveParams& p, int vbeg, int vend, int chain, WaveTile* tile, double* lds) {
   const int lane = threadIdx.x & 63;
-  const int v = vbeg + (int)threadIdx.x;
+  const int i = (int)threadIdx.x;
+  const int v = vbeg + i;
   const bool act = v < vend;
   const int ra = vbeg + (int)(threadIdx.x & ~63u);
   const int nr = vend - ra < 64 ? vend - ra : 64;
-  if (nr <= 0) return;
-  double acc = wave_tile_gather<64, double, true>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile);
+  double* sX = lds;                 // x = c R / outdeg of final vertices, -1 before
+  double* sR = lds + kThreads;      // (long chains) R of final vertices
+  double* sA = lds + 2 * kThreads;  // (long chains) affine form R_v = a + b R_t
+  double* sB = lds + 3 * kThreads;
+  int32_t* sT = reinterpret_cast<int32_t*>(lds + 4 * kThreads);
+  int32_t* sS = sT + kThreads;  // (long chains) 0 final, 1 one in-item source, 2 several
+  auto ld_lx = [&](int k) { return __hip_atomic_load(sX + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+  auto st_lx = [&](int k, double val) {
+    __hip_atomic_store(sX + k, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  sX[i] = -1.0;  // the LDS still holds the previous item's values
+  __syncthreads();
+  double acc = 0.0;
+  if (nr > 0) acc = wave_tile_gather<64, double, true>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile);
   if (act) {
     acc += p.W[p.perm[v]];
     p.wprime[v] = acc;
@@ -479,11 +508,21 @@ __device__ void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* ti
   const uint32_t hi = act ? p.int_ptr[v + 1] : 0u;
   const bool lng = (hi - lo) > kLongLane;
   auto inside = [&](int u) { return u >= vbeg && u < vend; };
-  // sources in earlier items: independent loads four at a time, then a wait
-  // for any that is not final yet
-  unsigned long long t0 = 0;
-  bool first = true;
-  int nap = 1;
+  auto wait_x = [&](int u) {
+    double xv = ld_x(p.x, u);
+    if (xv < 0.0) {
+      const unsigned long long tw = wall_clock64();
+      int nw = 1;
+      unsigned polls = 0;
+      while ((xv = ld_x(p.x, u)) < 0.0) {
+        if ((++polls & 15u) == 0u && timed_out(p, tw)) return 0.0;
+        backoff_sleep(nw);
+      }
+    }
+    return xv;
+  };
+  // 1. CAC sources in earlier items (rows with few sources): four
+  // independent loads at a time, then a wait for any not final yet
   if (act && !lng) {
     for (uint32_t e = lo; e < hi; e += 4) {
       int u[4];
@@ -495,90 +534,160 @@ __device__ void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* ti
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (xv[j] < 0.0) {
-          const unsigned long long tw = wall_clock64();
-          int nw = 1;
-          while ((xv[j] = ld_x(p.x, u[j])) < 0.0) {
-            if (timed_out(p, tw)) {
-              xv[j] = 0.0;
-              break;
-            }
-            backoff_sleep(nw);
-          }
-        }
+        if (xv[j] < 0.0) xv[j] = wait_x(u[j]);
         acc += xv[j];
       }
     }
   }
-  // in-item sources through LDS; rows with many CAC in-edges are summed by
-  // the whole wavefront from the global x once every source is final
-  // per-vertex constants and the pending in-item source stay in registers,
-  // so a round that only waits touches nothing but LDS
   const double cinv = act ? p.c * p.inv64[v] : 0.0;
   const int orig = act ? p.perm[v] : 0;
-  uint32_t e = lo;
-  int pend = -1;
   bool done = !act;
-  volatile double* vxl = xl;
-  while (true) {
-    const unsigned long long before = __ballot(done);
-    if (!done && !lng) {
-      while (true) {
-        if (pend < 0) {
-          while (e < hi && !inside(p.int_src[e])) ++e;
-          if (e == hi) break;
-          pend = p.int_src[e] - vbeg;
+  auto publish = [&](double r) {
+    const double xv = cinv * r;
+    st_lx(i, xv);
+    st_x(p.x, v, xv);
+    p.Rout[orig] = r;
+    done = true;
+    return xv;
+  };
+  if (chain <= kCacDeep) {
+    // 2a. short chains: each wavefront on its own, no barrier.  A lane walks
+    // its in-item sources in edge order, adding x of each final one and
+    // stopping at the first that is not; the pending source stays in a
+    // register, so a waiting round touches only LDS.  Rows with many CAC
+    // sources are summed by the whole wavefront from the global x once every
+    // source (inside the item or not) is final.
+    uint32_t e = lo;
+    int pend = -1;
+    unsigned rounds = 0;
+    const unsigned long long t0 = wall_clock64();
+    while (true) {
+      const unsigned long long before = __ballot(done);
+      if (!done && !lng) {
+        while (true) {
+          if (pend < 0) {
+            while (e < hi && !inside(p.int_src[e])) ++e;
+            if (e == hi) break;
+            pend = p.int_src[e] - vbeg;
+          }
+          const double xv = ld_lx(pend);
+          if (xv < 0.0) break;
+          acc += xv;
+          pend = -1;
+          ++e;
         }
-        const double xv = vxl[pend];
-        if (xv < 0.0) break;
-        acc += xv;
-        pend = -1;
-        ++e;
+        if (e == hi) publish(acc);
       }
-      if (e == hi) {
-        const double xv = cinv * acc;
-        vxl[v - vbeg] = xv;
-        st_x(p.x, v, xv);
-        p.Rout[orig] = acc;
-        done = true;
+      unsigned long long m = __ballot(!done && lng);
+      while (m) {
+        const int b = __ffsll(m) - 1;
+        m &= m - 1;
+        const uint32_t blo = __shfl(lo, b, 64), bhi = __shfl(hi, b, 64);
+        double sum = 0.0;
+        if (wave_gather_x_try(p, p.int_src, blo, bhi, &sum) && lane == b) publish(acc + sum);
+      }
+      if (__all(done)) break;
+      if ((++rounds & 255u) == 0u && timed_out(p, t0)) {
+        if (!done) {
+          st_x(p.x, v, 0.0);
+          p.Rout[orig] = acc;
+        }
+        break;
+      }
+      if (__ballot(done) == before) __builtin_amdgcn_s_sleep(1);
+    }
+    return;
+  }
+  // 2b. long chains: synchronous pointer jumping (whole workgroup).  Rows
+  // with many CAC sources first wait wavefront-wide for their sources in
+  // earlier items.
+  unsigned long long m = __ballot(act && lng);
+  while (m) {
+    const int b = __ffsll(m) - 1;
+    m &= m - 1;
+    const uint32_t blo = __shfl(lo, b, 64), bhi = __shfl(hi, b, 64);
+    double part = 0.0;
+    for (uint32_t e = blo + lane; e < bhi; e += 64) {
+      const int u = p.int_src[e];
+      if (!inside(u)) part += wait_x(u);
+    }
+    part = wave_sum(part);
+    if (lane == b) acc += part;
+  }
+  int npred = 0, single = -1;
+  for (uint32_t e = lo; e < hi; ++e) {
+    const int u = p.int_src[e];
+    if (inside(u)) {
+      ++npred;
+      single = u - vbeg;
+    }
+  }
+  double R = acc;
+  if (act && npred == 0) publish(acc);
+  int state = done ? 0 : (npred == 1 ? 1 : 2);
+  double a = acc, b = 0.0;
+  int t = -1;
+  if (state == 1) {
+    b = p.c * p.inv64[vbeg + single];
+    t = single;
+  }
+  sR[i] = R;
+  sA[i] = a;
+  sB[i] = b;
+  sT[i] = t;
+  sS[i] = state;
+  __syncthreads();
+  const unsigned long long t0 = wall_clock64();
+  for (unsigned round = 0;; ++round) {
+    int ns = state, nt = t;
+    double na = a, nb = b, nR = R;
+    if (state == 1) {
+      const int st = sS[t];
+      if (st == 0) {
+        nR = a + b * sR[t];
+        ns = 0;
+      } else if (st == 1) {
+        na = a + b * sA[t];
+        nb = b * sB[t];
+        nt = sT[t];
+      }
+    } else if (state == 2) {
+      bool ready = true;
+      for (uint32_t e = lo; e < hi && ready; ++e) {
+        const int u = p.int_src[e];
+        if (inside(u) && sS[u - vbeg] != 0) ready = false;
+      }
+      if (ready) {
+        double sum = acc;
+        for (uint32_t e = lo; e < hi; ++e) {
+          const int u = p.int_src[e];
+          if (inside(u)) sum += sX[u - vbeg];
+        }
+        nR = sum;
+        ns = 0;
       }
     }
-    unsigned long long m = __ballot(!done && lng);
-    bool waiting_global = m != 0;
-    while (m) {
-      const int b = __ffsll(m) - 1;
-      m &= m - 1;
-      const uint32_t blo = __shfl(lo, b, 64), bhi = __shfl(hi, b, 64);
-      double sum = 0.0;
-      if (wave_gather_x_try(p, p.int_src, blo, bhi, &sum) && lane == b) {
-        acc += sum;
-        const double xv = cinv * acc;
-        vxl[v - vbeg] = xv;
-        st_x(p.x, v, xv);
-        p.Rout[orig] = acc;
-        done = true;
-      }
-    }
-    if (__all(done)) break;
-    if (first) {
-      t0 = wall_clock64();
-      first = false;
-    } else if (timed_out(p, t0)) {
-      if (!done) {
-        p.Rout[orig] = acc;
-        st_x(p.x, v, 0.0);
+    const bool pending = __syncthreads_or(ns != 0);  // every read of this round is done
+    if (ns == 0 && state != 0) publish(nR);
+    state = ns;
+    t = nt;
+    a = na;
+    b = nb;
+    R = nR;
+    sR[i] = R;
+    sA[i] = a;
+    sB[i] = b;
+    sT[i] = t;
+    sS[i] = state;
+    __syncthreads();
+    if (!pending) break;
+    // bounded: a malformed plan cannot hold the workgroup (uniform test)
+    if ((round & 255u) == 255u && __syncthreads_or(threadIdx.x == 0 && timed_out(p, t0))) {
+      if (state != 0) {
+        st_x(p.x, v, cinv * R);
+        p.Rout[orig] = R;
       }
       break;
-    }
-    // while lanes keep finishing a chain advances at LDS speed: no pause;
-    // waits on other wavefronts of the item are short, waits on the global
-    // x of long rows back off
-    if (__ballot(done) != before) {
-      nap = 1;
-    } else if (waiting_global) {
-      backoff_sleep(nap);
-    } else {
-      __builtin_amdgcn_s_sleep(1);
     }
   }
 }
@@ -1130,6 +1239,8 @@ __device__ inline void flush_stats(const SolveParams& p, unsigned long long* s_s
 // are gathered, and a vertex item keeps its local x values in the second part.
 constexpr size_t kSegLds = 53 * 1024;  // three workgroups per CU (the VGPR limit too)
 static_assert(kWaves * sizeof(WaveTile) + kWaves * 2 * kSmallMax * sizeof(double) <= kSegLds, "segment LDS");
+static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + 2 * kThreads * sizeof(int32_t) <= kSegLds,
+              "vertex item LDS");
 
 // Persistent segment kernel.  Items are handed out in plan order by one
 // atomic counter per segment (one atomic per item).  This cannot deadlock,
@@ -1167,10 +1278,7 @@ __global__ __launch_bounds__(kThreads) void k_segment(SolveParams p) {
     }
     int slot;
     if (it.kind == ITEM_VERTS) {
-      double* xl = reinterpret_cast<double*>(second);
-      xl[threadIdx.x] = -1.0;
-      __syncthreads();
-      run_verts(p, it.a, it.b, &tiles[wave], xl);
+      run_verts(p, it.a, it.b, it.c, &tiles[wave], reinterpret_cast<double*>(second));
       slot = S_T_VERTS;
     } else if (it.kind == ITEM_SMALL) {
       const int r = it.a + wave;
@@ -1854,6 +1962,31 @@ static void add_gang(const std::vector<uint32_t>& ptr, int G, int vb, int ve, co
   }
   T.gangs.push_back(gd);
 }
+// Longest chain of CAC edges inside each vertex item (the item's vertices
+// are in topological order, so one pass in order gives each vertex's depth).
+__global__ __launch_bounds__(64) void k_item_depth(Item* items, int64_t n_items, const uint32_t* int_ptr,
+                                                    const int32_t* int_src) {
+  __shared__ int32_t depth[kThreads];
+  for (int64_t q = blockIdx.x; q < n_items; q += gridDim.x) {
+    const Item it = items[q];
+    if (it.kind != ITEM_VERTS) continue;
+    if (threadIdx.x == 0) {
+      int32_t best = 0;
+      for (int v = it.a; v < it.b; ++v) {
+        int32_t d = 1;
+        for (uint32_t e = int_ptr[v]; e < int_ptr[v + 1]; ++e) {
+          const int u = int_src[e];
+          if (u >= it.a && u < v) d = max(d, depth[u - it.a] + 1);
+        }
+        depth[v - it.a] = d;
+        best = max(best, d);
+      }
+      items[q].c = best;
+    }
+    __syncthreads();
+  }
+}
+
 int32_t make_schedule(Levels& lv, hipStream_t s) {
   PR_TRY(grid_for(lv.opts.rows_per_wave, &lv.grid, &lv.ggrid));
   lv.sgrid = std::max(lv.grid, lv.ggrid);
@@ -1944,6 +2077,11 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
     return PR_OK;
   };
   PR_TRY(upload(&lv.items, items));
+  if (!items.empty()) {
+    k_item_depth<<<(unsigned)std::min<size_t>(items.size(), 4096), 64, 0, s>>>(lv.items, (int64_t)items.size(),
+                                                                              lv.int_ptr, lv.int_src);
+    PR_HIP_CHECK(hipGetLastError());
+  }
   PR_TRY(upload(&lv.gangs, T.gangs));
   PR_TRY(upload(&lv.gsccs, T.sccs));
   PR_TRY(upload(&lv.gbounds, T.bounds));

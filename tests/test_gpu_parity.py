@@ -298,3 +298,53 @@ def test_autotuner_sweeps_caches_and_stays_exact(prm, c1, tmp_path, monkeypatch)
     assert _rel_l1(Rd.cpu().numpy(), ref) <= 1e-10
     with pytest.raises(pr.PRError):
         pr.pr_build_levels(part, g.row_ptr, g.col, autotune=3)
+
+
+@pytest.mark.parametrize("L", [255, 256, 1000, 3000])
+def test_long_chain_closed_form(prm, L):
+    """A chain v1 -> ... -> vL is one CAC spanning several items: with W = 1,
+    R_j = (1 - c^j) / (1 - c) (a closed form of the sum over the single path)."""
+    pr, torch = prm
+    _say("chain", L)
+    g = csr_from_edges(L, np.arange(L - 1), np.arange(1, L))
+    part = pr.pr_partition(g.row_ptr, g.col)
+    assert part.n_comp == 1 and part.comp_type[0] == 0
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col)
+    Wd = torch.ones(L, dtype=torch.float64, device="cuda")
+    Rd = torch.empty_like(Wd)
+    pr.pr_solve(lv, C, Wd, Rd, precision=1)
+    exact = (1.0 - C ** (np.arange(L) + 1.0)) / (1.0 - C)
+    np.testing.assert_allclose(Rd.cpu().numpy(), exact, rtol=1e-13)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_random_dag_cacs(prm, seed):
+    """Acyclic graphs: every component is a CAC or a single vertex; many
+    vertices have several CAC sources (junctions), chains cross items and
+    wavefronts.  Exact up to rounding against the oracle's sweep."""
+    pr, torch = prm
+    _say("dag", seed)
+    rng = np.random.default_rng(seed)
+    n = 4000
+    # edges i -> j with j > i: mostly short hops (deep chains), some long ones
+    src = rng.integers(0, n - 1, 9000)
+    hop = np.where(rng.random(9000) < 0.8, 1 + rng.integers(0, 3, 9000), 1 + rng.integers(0, 2000, 9000))
+    dst = np.minimum(src + hop, n - 1)
+    keep = dst > src
+    perm = rng.permutation(n)  # vertex ids not in topological order
+    g = csr_from_edges(n, perm[src[keep]], perm[dst[keep]])
+    W = rng.uniform(0.1, 2.0, n)
+    part = pr.pr_partition(g.row_ptr, g.col)
+    assert (part.comp_type == 0).all()
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col)
+    Wd = torch.tensor(W, device="cuda")
+    Rd = torch.empty_like(Wd)
+    pr.pr_solve(lv, C, Wd, Rd, precision=1)
+    from oracle.componentwise import componentwise_solve
+
+    ref = componentwise_solve(g.n, g.row_ptr, g.col, C, W)
+    np.testing.assert_allclose(Rd.cpu().numpy(), ref, rtol=1e-12)
+    # bitwise reproducible
+    Rd2 = torch.empty_like(Wd)
+    pr.pr_solve(lv, C, Wd, Rd2, precision=1)
+    assert np.array_equal(Rd.cpu().numpy(), Rd2.cpu().numpy())
