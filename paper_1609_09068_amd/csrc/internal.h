@@ -131,6 +131,7 @@ struct Levels {
   float* inv_deg32 = nullptr;     // [n] 1/outdeg (0 for dangling)
   double* inv_deg64 = nullptr;    // [n]
   Item* items = nullptr;          // [n_items]
+  uint32_t* vpath = nullptr;      // [n] vertex items: path order of the CAC sweep (see k_item_paths)
   int64_t n_items = 0;
   int32_t grid = 0;               // workgroups of a segment kernel launch
   int32_t ggrid = 0;              // workgroups of a gang kernel launch

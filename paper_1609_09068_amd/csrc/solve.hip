@@ -96,6 +96,7 @@ struct SolveParams {
   void* y0;
   void* y1;
   const Item* items;
+  const uint32_t* vpath;
   const int32_t* comp_vbeg;
   int32_t* iters;
   double* lastnorm;
@@ -459,45 +460,61 @@ __device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const 
 
 // One-vertex components and CAC vertices (Sec. 4.3 first bullet, Sec. 4.3.1).
 // R_v = W_v + (rank from higher levels) + sum over v's CAC in-edges u -> v of
-// c R_u / outdeg(u).  The item's 256 vertices are in topological order.
-//  1. Rank from higher levels (boundary rows) and from CAC sources in earlier
-//     items, waited for through the published x: acc_v.
-//  2. Sources inside the item, through LDS (final R and a state per vertex),
-//     one of two ways chosen by the plan from the item's longest in-item
-//     chain (so the arithmetic depends only on the graph):
-//     a. Short chains: each wavefront on its own, no barrier: a vertex whose
-//        in-item sources are all final adds them in edge order.
-//     b. Long chains: synchronous rounds of the whole workgroup: a
-//        vertex with exactly one in-item source t keeps the affine form
-//        R_v = a_v + b_v R_t (a = acc, b = c / outdeg(t)) and jumps: if t is
-//        final, R_v = a_v + b_v R_t; if t has one source too,
-//        (a_v, b_v, t) <- (a_v + b_v a_t, b_v b_t, t's source), so a chain of
-//        length L resolves in about log2 L rounds (pointer jumping).  A vertex
-//        with several in-item sources waits until all are final and adds
-//        them in edge order.
-// Each vertex publishes x_v = c R_v / outdeg(v) as soon as R_v is final.
+// c R_u / outdeg(u).  The item's (up to 256) vertices are in topological order.
+//  1. One thread per vertex: rank from higher levels (boundary rows) and from
+//     CAC sources in earlier items, waited for through the published x, gives
+//     acc_v; the sources inside the item are noted (up to four, in edge order).
+//  2. The plan covers the item by vertex-disjoint paths (k_item_paths).  One
+//     lane walks each path in order with the x of the previous vertex in a
+//     register: R_v = acc_v + the x of v's in-item sources in edge order,
+//     where a source on another path is read from LDS once that lane has
+//     published it (x < 0 means not yet; the lane then retries in the next
+//     round).  A chain inside the item costs one fused multiply-add chain in
+//     one lane instead of one round of LDS traffic per vertex.
+// x_v = c R_v / outdeg(v) is published the moment R_v is final when a later
+// item needs it (a CAC edge into a later item), else when the item ends.
 // Every sum has a fixed order (the schedule depends only on the graph).
-constexpr int kCacDeep = 16;  // items with longer in-item chains use pointer jumping
-
-__device__ void run_verts(const SolveParams& p, int vbeg, int vend, int chain, WaveTile* tile, double* lds) {
+__device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* tile, double* lds) {
   const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const int i = (int)threadIdx.x;
   const int v = vbeg + i;
+  const int nvi = vend - vbeg;
   const bool act = v < vend;
   const int ra = vbeg + (int)(threadIdx.x & ~63u);
   const int nr = vend - ra < 64 ? vend - ra : 64;
-  double* sX = lds;                 // x = c R / outdeg of final vertices, -1 before
-  double* sR = lds + kThreads;      // (long chains) R of final vertices
-  double* sA = lds + 2 * kThreads;  // (long chains) affine form R_v = a + b R_t
-  double* sB = lds + 3 * kThreads;
-  int32_t* sT = reinterpret_cast<int32_t*>(lds + 4 * kThreads);
-  int32_t* sS = sT + kThreads;  // (long chains) 0 final, 1 one in-item source, 2 several
+  double* sX = lds;                 // by vertex: x when final, -1 before
+  double* sR = lds + kThreads;      // by vertex: R
+  double* sA = lds + 2 * kThreads;  // by path position: acc
+  double* sC = lds + 3 * kThreads;  // by path position: c / outdeg
+  uint32_t* sP = reinterpret_cast<uint32_t*>(lds + 4 * kThreads);  // by position: in-item sources (bytes)
+  uint32_t* sI = sP + kThreads;  // by position: vertex | source count << 8 (7: more than four)
+  int32_t* sQ = reinterpret_cast<int32_t*>(sI + kThreads);  // by vertex: path position
+  int32_t* sPB = sQ + kThreads;                              // path k: positions [sPB[k], sPB[k+1])
+  int32_t* sWc = sPB + kThreads + 1;                         // path starts per wavefront
   auto ld_lx = [&](int k) { return __hip_atomic_load(sX + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
   auto st_lx = [&](int k, double val) {
     __hip_atomic_store(sX + k, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
+  // path order: position i holds vertex pw & 255; bit 8 starts a path
+  const uint32_t pw = act ? p.vpath[v] : 0u;
+  const bool early = pw & 0x10000u;  // v has a CAC edge into a later item
+  const bool pstart = act && (pw & 0x100u);
+  if (act) sQ[pw & 0xffu] = i | (pstart ? 0x10000 : 0);
   sX[i] = -1.0;  // the LDS still holds the previous item's values
+  const unsigned long long sm = __ballot(pstart);
+  if (lane == 0) sWc[wave] = (int32_t)__popcll(sm);
   __syncthreads();
+  {
+    int pid = (int)__popcll(sm & ((1ull << lane) - 1ull)), npath = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      if (w < wave) pid += sWc[w];
+      npath += sWc[w];
+    }
+    if (pstart) sPB[pid] = i;
+    if (i == 0) sPB[npath] = nvi;  // visible after the barrier below
+  }
   double acc = 0.0;
   if (nr > 0) acc = wave_tile_gather<64, double, true>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile);
   if (act) {
@@ -521,8 +538,10 @@ __device__ void run_verts(const SolveParams& p, int vbeg, int vend, int chain, W
     }
     return xv;
   };
-  // 1. CAC sources in earlier items (rows with few sources): four
-  // independent loads at a time, then a wait for any not final yet
+  // 1. CAC sources in earlier items: four independent loads at a time, then
+  // a wait for any not final yet; in-item sources are noted
+  uint32_t pk = 0u;
+  uint32_t np = 0u;
   if (act && !lng) {
     for (uint32_t e = lo; e < hi; e += 4) {
       int u[4];
@@ -534,77 +553,22 @@ __device__ void run_verts(const SolveParams& p, int vbeg, int vend, int chain, W
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (xv[j] < 0.0) xv[j] = wait_x(u[j]);
-        acc += xv[j];
+        if (u[j] >= 0 && inside(u[j])) {
+          if (np < 4u) pk |= (uint32_t)(u[j] - vbeg) << (8u * np);
+          ++np;
+        } else {
+          if (xv[j] < 0.0) xv[j] = wait_x(u[j]);
+          acc += xv[j];
+        }
       }
     }
   }
-  const double cinv = act ? p.c * p.inv64[v] : 0.0;
-  const int orig = act ? p.perm[v] : 0;
-  bool done = !act;
-  auto publish = [&](double r) {
-    const double xv = cinv * r;
-    st_lx(i, xv);
-    st_x(p.x, v, xv);
-    p.Rout[orig] = r;
-    done = true;
-    return xv;
-  };
-  if (chain <= kCacDeep) {
-    // 2a. short chains: each wavefront on its own, no barrier.  A lane walks
-    // its in-item sources in edge order, adding x of each final one and
-    // stopping at the first that is not; the pending source stays in a
-    // register, so a waiting round touches only LDS.  Rows with many CAC
-    // sources are summed by the whole wavefront from the global x once every
-    // source (inside the item or not) is final.
-    uint32_t e = lo;
-    int pend = -1;
-    unsigned rounds = 0;
-    const unsigned long long t0 = wall_clock64();
-    while (true) {
-      const unsigned long long before = __ballot(done);
-      if (!done && !lng) {
-        while (true) {
-          if (pend < 0) {
-            while (e < hi && !inside(p.int_src[e])) ++e;
-            if (e == hi) break;
-            pend = p.int_src[e] - vbeg;
-          }
-          const double xv = ld_lx(pend);
-          if (xv < 0.0) break;
-          acc += xv;
-          pend = -1;
-          ++e;
-        }
-        if (e == hi) publish(acc);
-      }
-      unsigned long long m = __ballot(!done && lng);
-      while (m) {
-        const int b = __ffsll(m) - 1;
-        m &= m - 1;
-        const uint32_t blo = __shfl(lo, b, 64), bhi = __shfl(hi, b, 64);
-        double sum = 0.0;
-        if (wave_gather_x_try(p, p.int_src, blo, bhi, &sum) && lane == b) publish(acc + sum);
-      }
-      if (__all(done)) break;
-      if ((++rounds & 255u) == 0u && timed_out(p, t0)) {
-        if (!done) {
-          st_x(p.x, v, 0.0);
-          p.Rout[orig] = acc;
-        }
-        break;
-      }
-      if (__ballot(done) == before) __builtin_amdgcn_s_sleep(1);
-    }
-    return;
-  }
-  // 2b. long chains: synchronous pointer jumping (whole workgroup).  Rows
-  // with many CAC sources first wait wavefront-wide for their sources in
-  // earlier items.
-  unsigned long long m = __ballot(act && lng);
-  while (m) {
-    const int b = __ffsll(m) - 1;
-    m &= m - 1;
+  // rows with many CAC sources: the wavefront waits for and sums the ones in
+  // earlier items; the walk reads the in-item ones from the row itself
+  unsigned long long lm = __ballot(act && lng);
+  while (lm) {
+    const int b = __ffsll(lm) - 1;
+    lm &= lm - 1;
     const uint32_t blo = __shfl(lo, b, 64), bhi = __shfl(hi, b, 64);
     double part = 0.0;
     for (uint32_t e = blo + lane; e < bhi; e += 64) {
@@ -614,81 +578,122 @@ __device__ void run_verts(const SolveParams& p, int vbeg, int vend, int chain, W
     part = wave_sum(part);
     if (lane == b) acc += part;
   }
-  int npred = 0, single = -1;
-  for (uint32_t e = lo; e < hi; ++e) {
-    const int u = p.int_src[e];
-    if (inside(u)) {
-      ++npred;
-      single = u - vbeg;
-    }
+  if (lng || np > 4u) np = 7u;
+  const int orig = act ? p.perm[v] : 0;
+  if (act) {
+    // hop kind: 0 no in-item source, 1 the path predecessor is the only one,
+    // 2 anything else (sources on other paths)
+    const int qw = sQ[i];
+    const uint32_t kind = np == 0u ? 0u : (np == 1u && !(qw & 0x10000)) ? 1u : 2u;
+    const int q = qw & 0xffff;
+    sA[q] = acc;
+    sC[q] = p.c * p.inv64[v];
+    sP[q] = pk;
+    sI[q] = (uint32_t)i | (kind << 8) | (np << 10) | (early ? 0x2000u : 0u);
   }
-  double R = acc;
-  if (act && npred == 0) publish(acc);
-  int state = done ? 0 : (npred == 1 ? 1 : 2);
-  double a = acc, b = 0.0;
-  int t = -1;
-  if (state == 1) {
-    b = p.c * p.inv64[vbeg + single];
-    t = single;
-  }
-  sR[i] = R;
-  sA[i] = a;
-  sB[i] = b;
-  sT[i] = t;
-  sS[i] = state;
+  if (p.trace && lane == 0) atomicMax(tile->rdy, wall_clock64());
   __syncthreads();
+  // 2. walk the paths; lanes retry in rounds until every path is done
+  int q = 0, qe = 0;
+  {
+    int tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) tot += sWc[w];
+    if (i < tot) {
+      q = sPB[i];
+      qe = sPB[i + 1];
+    }
+  }
+  double xprev = 0.0;
+  int prev = -1;
+  unsigned rounds = 0;
   const unsigned long long t0 = wall_clock64();
-  for (unsigned round = 0;; ++round) {
-    int ns = state, nt = t;
-    double na = a, nb = b, nR = R;
-    if (state == 1) {
-      const int st = sS[t];
-      if (st == 0) {
-        nR = a + b * sR[t];
-        ns = 0;
-      } else if (st == 1) {
-        na = a + b * sA[t];
-        nb = b * sB[t];
-        nt = sT[t];
+  while (true) {
+    const int qb = q;
+    bool stop = q >= qe;
+    while (!stop) {
+      // the next eight positions in one LDS round trip; hops of kind 0 and 1
+      // then run from registers
+      double a8[8], c8[8];
+      uint32_t i8[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int qq = q + j < qe ? q + j : qe - 1;
+        a8[j] = sA[qq];
+        c8[j] = sC[qq];
+        i8[j] = sI[qq];
       }
-    } else if (state == 2) {
-      bool ready = true;
-      for (uint32_t e = lo; e < hi && ready; ++e) {
-        const int u = p.int_src[e];
-        if (inside(u) && sS[u - vbeg] != 0) ready = false;
-      }
-      if (ready) {
-        double sum = acc;
-        for (uint32_t e = lo; e < hi; ++e) {
-          const int u = p.int_src[e];
-          if (inside(u)) sum += sX[u - vbeg];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (!stop) {
+          const int loc = (int)(i8[j] & 0xffu);
+          const uint32_t kind = (i8[j] >> 8) & 3u;
+          double r = a8[j];
+          bool ok = true;
+          if (kind == 1u) {
+            r += xprev;
+          } else if (kind == 2u) {
+            const uint32_t n = (i8[j] >> 10) & 7u;
+            if (n == 7u) {
+              const uint32_t l0 = p.int_ptr[vbeg + loc], l1 = p.int_ptr[vbeg + loc + 1];
+              for (uint32_t e = l0; e < l1 && ok; ++e) {
+                const int u = p.int_src[e];
+                if (!inside(u)) continue;
+                const double xv = u - vbeg == prev ? xprev : ld_lx(u - vbeg);
+                if (xv < 0.0) ok = false;
+                else r += xv;
+              }
+            } else {
+              const uint32_t pk4 = sP[q];
+              double xs[4];
+#pragma unroll
+              for (int m = 0; m < 4; ++m) {
+                const int u = (int)((pk4 >> (8 * m)) & 0xffu);
+                xs[m] = (uint32_t)m < n ? (u == prev ? xprev : ld_lx(u)) : 0.0;
+              }
+#pragma unroll
+              for (int m = 0; m < 4; ++m) {
+                if ((uint32_t)m < n) {
+                  ok = ok && xs[m] >= 0.0;
+                  r += xs[m];
+                }
+              }
+            }
+          }
+          if (!ok) {
+            stop = true;
+          } else {
+            const double xv = c8[j] * r;
+            st_lx(loc, xv);
+            sR[loc] = r;
+            if (i8[j] & 0x2000u) st_x(p.x, vbeg + loc, xv);
+            xprev = xv;
+            prev = loc;
+            ++q;
+            if (q >= qe) stop = true;
+          }
         }
-        nR = sum;
-        ns = 0;
       }
     }
-    const bool pending = __syncthreads_or(ns != 0);  // every read of this round is done
-    if (ns == 0 && state != 0) publish(nR);
-    state = ns;
-    t = nt;
-    a = na;
-    b = nb;
-    R = nR;
-    sR[i] = R;
-    sA[i] = a;
-    sB[i] = b;
-    sT[i] = t;
-    sS[i] = state;
-    __syncthreads();
-    if (!pending) break;
-    // bounded: a malformed plan cannot hold the workgroup (uniform test)
-    if ((round & 255u) == 255u && __syncthreads_or(threadIdx.x == 0 && timed_out(p, t0))) {
-      if (state != 0) {
-        st_x(p.x, v, cinv * R);
-        p.Rout[orig] = R;
+    if (__all(q >= qe)) break;
+    if (!__any(q != qb)) __builtin_amdgcn_s_sleep(1);
+    // bounded: a malformed plan cannot hold the workgroup
+    if ((++rounds & 255u) == 0u && timed_out(p, t0)) {
+      for (; q < qe; ++q) {
+        const int loc = (int)(sI[q] & 0xffu);
+        sR[loc] = sA[q];
+        st_lx(loc, 0.0);
+        if (sI[q] & 0x2000u) st_x(p.x, vbeg + loc, 0.0);
       }
-      break;
     }
+  }
+  // 3. publish the rest of the item's x in one coalesced store per
+  // wavefront (single-lane stores, one per vertex of a path, would be issued
+  // back to back to the same cache lines)
+  __syncthreads();
+  if (act) {
+    if (!early) st_x(p.x, v, sX[i]);
+    p.Rout[orig] = sR[i];
   }
 }
 
@@ -808,7 +813,7 @@ __device__ WarmOut warm_preamble(const SolveParams& p, int vbeg, int nv, double 
 // term touches only LDS and registers (R stays in registers, four rows per
 // lane).
 template <typename YT, bool WARM>
-__device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned long long* wst, WaveTile* tile) {
+__device__ __attribute__((always_inline)) void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned long long* wst, WaveTile* tile) {
   const int lane = threadIdx.x & 63;
   const int vbeg = p.comp_vbeg[rank];
   const int nv = p.comp_vbeg[rank + 1] - vbeg;
@@ -1027,7 +1032,7 @@ __device__ void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned lon
 // during the iteration; otherwise the vectors stay in global memory, touched
 // only by this workgroup.
 template <typename YT, int RPW, bool WARM>
-__device__ void run_medium(const SolveParams& p, int rank, double* red, unsigned long long* wst, WaveTile* tiles,
+__device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, int rank, double* red, unsigned long long* wst, WaveTile* tiles,
                            unsigned char* raw, size_t raw_bytes) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   WaveTile* tile = tiles + wave;
@@ -1239,7 +1244,8 @@ __device__ inline void flush_stats(const SolveParams& p, unsigned long long* s_s
 // are gathered, and a vertex item keeps its local x values in the second part.
 constexpr size_t kSegLds = 53 * 1024;  // three workgroups per CU (the VGPR limit too)
 static_assert(kWaves * sizeof(WaveTile) + kWaves * 2 * kSmallMax * sizeof(double) <= kSegLds, "segment LDS");
-static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + 2 * kThreads * sizeof(int32_t) <= kSegLds,
+static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + (4 * kThreads + 1 + kWaves) * sizeof(int32_t) <=
+                  kSegLds,
               "vertex item LDS");
 
 // Persistent segment kernel.  Items are handed out in plan order by one
@@ -1278,7 +1284,7 @@ __global__ __launch_bounds__(kThreads) void k_segment(SolveParams p) {
     }
     int slot;
     if (it.kind == ITEM_VERTS) {
-      run_verts(p, it.a, it.b, it.c, &tiles[wave], reinterpret_cast<double*>(second));
+      run_verts(p, it.a, it.b, &tiles[wave], reinterpret_cast<double*>(second));
       slot = S_T_VERTS;
     } else if (it.kind == ITEM_SMALL) {
       const int r = it.a + wave;
@@ -1962,28 +1968,69 @@ static void add_gang(const std::vector<uint32_t>& ptr, int G, int vb, int ve, co
   }
   T.gangs.push_back(gd);
 }
-// Longest chain of CAC edges inside each vertex item (the item's vertices
-// are in topological order, so one pass in order gives each vertex's depth).
-__global__ __launch_bounds__(64) void k_item_depth(Item* items, int64_t n_items, const uint32_t* int_ptr,
-                                                    const int32_t* int_src) {
+// Plan of the CAC sweep inside each vertex item.  The item's vertices are in
+// topological order (sub-levels), so one pass in that order gives each
+// vertex's depth (the longest chain of in-item CAC edges ending there; the
+// item's longest goes to Item.c) and a cover of the item by vertex-disjoint
+// paths: a vertex continues the path of its deepest in-item predecessor that
+// no other vertex continues yet (the first such in edge order), else it starts
+// a path.  vpath lists the item's vertices path after path, each path in
+// order (local index in bits 0-7, bit 8 set where a path starts), so that one
+// lane can walk a whole path with the running value in a register.
+// k_item_early then sets bit 16 of vpath[u] for every vertex u with a CAC
+// edge into a later vertex item: those publish x the moment they are final,
+// the others when their item ends.
+__global__ __launch_bounds__(64) void k_item_paths(Item* items, int64_t n_items, const uint32_t* int_ptr,
+                                                    const int32_t* int_src, uint32_t* vpath) {
   __shared__ int32_t depth[kThreads];
+  __shared__ int16_t succ[kThreads];
+  __shared__ uint8_t head[kThreads];
   for (int64_t q = blockIdx.x; q < n_items; q += gridDim.x) {
     const Item it = items[q];
     if (it.kind != ITEM_VERTS) continue;
     if (threadIdx.x == 0) {
+      const int nv = it.b - it.a;
       int32_t best = 0;
-      for (int v = it.a; v < it.b; ++v) {
-        int32_t d = 1;
+      for (int i = 0; i < nv; ++i) succ[i] = -1;
+      for (int i = 0; i < nv; ++i) {
+        const int v = it.a + i;
+        int32_t d = 1, pd = 0;
+        int pick = -1;
         for (uint32_t e = int_ptr[v]; e < int_ptr[v + 1]; ++e) {
-          const int u = int_src[e];
-          if (u >= it.a && u < v) d = max(d, depth[u - it.a] + 1);
+          const int u = int_src[e] - it.a;
+          if (u < 0 || u >= i) continue;
+          d = max(d, depth[u] + 1);
+          if (succ[u] < 0 && depth[u] > pd) {
+            pd = depth[u];
+            pick = u;
+          }
         }
-        depth[v - it.a] = d;
+        depth[i] = d;
+        head[i] = pick < 0 ? 1 : 0;
+        if (pick >= 0) succ[pick] = (int16_t)i;
         best = max(best, d);
       }
       items[q].c = best;
+      int pos = 0;
+      for (int h = 0; h < nv; ++h) {
+        if (!head[h]) continue;
+        for (int i = h; i >= 0; i = succ[i]) vpath[it.a + pos++] = (uint32_t)(i | (i == h ? 0x100 : 0));
+      }
     }
     __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(64) void k_item_early(const Item* items, int64_t n_items, const uint32_t* int_ptr,
+                                                    const int32_t* int_src, uint32_t* vpath) {
+  for (int64_t q = blockIdx.x; q < n_items; q += gridDim.x) {
+    const Item it = items[q];
+    if (it.kind != ITEM_VERTS) continue;
+    for (int v = it.a + (int)threadIdx.x; v < it.b; v += 64)
+      for (uint32_t e = int_ptr[v]; e < int_ptr[v + 1]; ++e) {
+        const int u = int_src[e];
+        if (u < it.a) atomicOr(&vpath[u], 0x10000u);
+      }
   }
 }
 
@@ -2077,9 +2124,12 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
     return PR_OK;
   };
   PR_TRY(upload(&lv.items, items));
+  if (!lv.vpath) PR_TRY(dalloc(&lv.vpath, (size_t)std::max<int64_t>(lv.n, 1)));
   if (!items.empty()) {
-    k_item_depth<<<(unsigned)std::min<size_t>(items.size(), 4096), 64, 0, s>>>(lv.items, (int64_t)items.size(),
-                                                                              lv.int_ptr, lv.int_src);
+    const unsigned ng = (unsigned)std::min<size_t>(items.size(), 4096);
+    k_item_paths<<<ng, 64, 0, s>>>(lv.items, (int64_t)items.size(), lv.int_ptr, lv.int_src, lv.vpath);
+    PR_HIP_CHECK(hipGetLastError());
+    k_item_early<<<ng, 64, 0, s>>>(lv.items, (int64_t)items.size(), lv.int_ptr, lv.int_src, lv.vpath);
     PR_HIP_CHECK(hipGetLastError());
   }
   PR_TRY(upload(&lv.gangs, T.gangs));
@@ -2191,6 +2241,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.bnd_src = lv.bnd_src;
   p.int_ptr = plain ? lv.full_ptr : lv.int_ptr;
   p.int_src = plain ? lv.full_src : lv.int_src;
+  p.vpath = lv.vpath;
   p.inv32 = lv.inv_deg32;
   p.inv64 = lv.inv_deg64;
   p.x = lv.x;
