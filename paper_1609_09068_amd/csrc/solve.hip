@@ -268,9 +268,6 @@ __device__ inline double block_max(double v, double* lds) {
 // whole wavefront; a group of LPR lanes hands over rows longer than
 // max(kLongLane, 8 LPR).
 constexpr uint32_t kLongLane = 32;
-// rows of an LDS-resident SCC with more sources than this are summed by a
-// whole wavefront
-constexpr uint32_t kHubLane = 64;
 
 // this lane's share (stride STRIDE from lo) of sum x[src[e]], e in [lo, hi);
 // returns false if a source is not final yet (the sum is then garbage)
@@ -461,20 +458,23 @@ __device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const 
 // One-vertex components and CAC vertices (Sec. 4.3 first bullet, Sec. 4.3.1).
 // R_v = W_v + (rank from higher levels) + sum over v's CAC in-edges u -> v of
 // c R_u / outdeg(u).  The item's (up to 256) vertices are in topological order.
-//  1. One thread per vertex: rank from higher levels (boundary rows) and from
-//     CAC sources in earlier items, waited for through the published x, gives
-//     acc_v; the sources inside the item are noted (up to four, in edge order).
+//  1. One thread per vertex: rank from higher levels (boundary rows, waited
+//     for through the published x) plus W_v gives acc_v; v's CAC sources are
+//     noted in edge order (up to four: an index in the item, or a vertex of
+//     an earlier item).  A vertex with more CAC sources adds the ones of
+//     earlier items here (waiting for them).
 //  2. The plan covers the item by vertex-disjoint paths (k_item_paths).  One
 //     lane walks each path in order with the x of the previous vertex in a
-//     register: R_v = acc_v + the x of v's in-item sources in edge order,
-//     where a source on another path is read from LDS once that lane has
-//     published it (x < 0 means not yet; the lane then retries in the next
-//     round).  A chain inside the item costs one fused multiply-add chain in
-//     one lane instead of one round of LDS traffic per vertex.
+//     register: R_v = acc_v + the x of v's CAC sources in edge order, read
+//     from LDS (sources in the item) or from the published x (earlier items)
+//     once final (x < 0 means not yet; the lane then retries in the next
+//     round).  A chain costs one multiply-add chain in one lane, and an item
+//     starts walking while the items before it are still being walked.
 // x_v = c R_v / outdeg(v) is published the moment R_v is final when a later
 // item needs it (a CAC edge into a later item), else when the item ends.
 // Every sum has a fixed order (the schedule depends only on the graph).
-__device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* tile, double* lds) {
+__device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* tile,
+                                                          double* lds) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int i = (int)threadIdx.x;
@@ -487,19 +487,20 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
   double* sR = lds + kThreads;      // by vertex: R
   double* sA = lds + 2 * kThreads;  // by path position: acc
   double* sC = lds + 3 * kThreads;  // by path position: c / outdeg
-  uint32_t* sP = reinterpret_cast<uint32_t*>(lds + 4 * kThreads);  // by position: in-item sources (bytes)
-  uint32_t* sI = sP + kThreads;  // by position: vertex | source count << 8 (7: more than four)
-  int32_t* sQ = reinterpret_cast<int32_t*>(sI + kThreads);  // by vertex: path position
-  int32_t* sPB = sQ + kThreads;                              // path k: positions [sPB[k], sPB[k+1])
-  int32_t* sWc = sPB + kThreads + 1;                         // path starts per wavefront
+  uint4* sS = reinterpret_cast<uint4*>(lds + 4 * kThreads);  // by position: CAC sources (see kExt)
+  uint32_t* sI = reinterpret_cast<uint32_t*>(sS + kThreads);  // by position: vertex | kind << 8 | count << 10
+  int32_t* sQ = reinterpret_cast<int32_t*>(sI + kThreads);    // by vertex: path position | start << 16
+  int32_t* sPB = sQ + kThreads;                               // path k: positions [sPB[k], sPB[k+1])
+  int32_t* sWc = sPB + kThreads + 1;                          // path starts per wavefront
+  constexpr uint32_t kExt = 0x80000000u;  // source entry: vertex index of an earlier item (else local index)
   auto ld_lx = [&](int k) { return __hip_atomic_load(sX + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
   auto st_lx = [&](int k, double val) {
     __hip_atomic_store(sX + k, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
   // path order: position i holds vertex pw & 255; bit 8 starts a path
   const uint32_t pw = act ? p.vpath[v] : 0u;
-  const bool early = pw & 0x10000u;  // v has a CAC edge into a later item
   const bool pstart = act && (pw & 0x100u);
+  const bool early = pw & 0x10000u;  // v has a CAC edge into a later item
   if (act) sQ[pw & 0xffu] = i | (pstart ? 0x10000 : 0);
   sX[i] = -1.0;  // the LDS still holds the previous item's values
   const unsigned long long sm = __ballot(pstart);
@@ -538,33 +539,46 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
     }
     return xv;
   };
-  // 1. CAC sources in earlier items: four independent loads at a time, then
-  // a wait for any not final yet; in-item sources are noted
-  uint32_t pk = 0u;
-  uint32_t np = 0u;
+  // 1. note the CAC sources (four ids loaded at a time)
+  uint32_t s0 = 0u, s1 = 0u, s2 = 0u, s3 = 0u, ns = 0u;
   if (act && !lng) {
     for (uint32_t e = lo; e < hi; e += 4) {
       int u[4];
-      double xv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) u[j] = e + j < hi ? p.int_src[e + j] : -1;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        u[j] = e + j < hi ? p.int_src[e + j] : -1;
-        xv[j] = (u[j] >= 0 && !inside(u[j])) ? ld_x(p.x, u[j]) : 0.0;
+        if (u[j] >= 0) {
+          const uint32_t w = inside(u[j]) ? (uint32_t)(u[j] - vbeg) : (kExt | (uint32_t)u[j]);
+          if (ns == 0u) s0 = w;
+          else if (ns == 1u) s1 = w;
+          else if (ns == 2u) s2 = w;
+          else if (ns == 3u) s3 = w;
+          ++ns;
+        }
       }
+    }
+    if (ns > 4u) {  // many sources: the ones of earlier items are added now, in edge order
+      for (uint32_t e = lo; e < hi; e += 4) {
+        int u[4];
+        double xv[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (u[j] >= 0 && inside(u[j])) {
-          if (np < 4u) pk |= (uint32_t)(u[j] - vbeg) << (8u * np);
-          ++np;
-        } else {
-          if (xv[j] < 0.0) xv[j] = wait_x(u[j]);
-          acc += xv[j];
+        for (int j = 0; j < 4; ++j) {
+          u[j] = e + j < hi ? p.int_src[e + j] : -1;
+          xv[j] = (u[j] >= 0 && !inside(u[j])) ? ld_x(p.x, u[j]) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (u[j] >= 0 && !inside(u[j])) {
+            if (xv[j] < 0.0) xv[j] = wait_x(u[j]);
+            acc += xv[j];
+          }
         }
       }
     }
   }
   // rows with many CAC sources: the wavefront waits for and sums the ones in
-  // earlier items; the walk reads the in-item ones from the row itself
+  // earlier items; the walk adds the ones in the item from the row itself
   unsigned long long lm = __ballot(act && lng);
   while (lm) {
     const int b = __ffsll(lm) - 1;
@@ -578,18 +592,18 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
     part = wave_sum(part);
     if (lane == b) acc += part;
   }
-  if (lng || np > 4u) np = 7u;
   const int orig = act ? p.perm[v] : 0;
   if (act) {
-    // hop kind: 0 no in-item source, 1 the path predecessor is the only one,
-    // 2 anything else (sources on other paths)
+    // hop kind: 0 no CAC source, 1 the path predecessor is the only one, 2 up
+    // to four listed sources, 3 many (the walk reads the row)
     const int qw = sQ[i];
-    const uint32_t kind = np == 0u ? 0u : (np == 1u && !(qw & 0x10000)) ? 1u : 2u;
+    const uint32_t kind =
+        (lng || ns > 4u) ? 3u : ns == 0u ? 0u : (ns == 1u && !(s0 & kExt) && !(qw & 0x10000)) ? 1u : 2u;
     const int q = qw & 0xffff;
     sA[q] = acc;
     sC[q] = p.c * p.inv64[v];
-    sP[q] = pk;
-    sI[q] = (uint32_t)i | (kind << 8) | (np << 10) | (early ? 0x2000u : 0u);
+    sS[q] = make_uint4(s0, s1, s2, s3);
+    sI[q] = (uint32_t)i | (kind << 8) | ((ns > 4u ? 7u : ns) << 10) | (early ? 0x2000u : 0u);
   }
   if (p.trace && lane == 0) atomicMax(tile->rdy, wall_clock64());
   __syncthreads();
@@ -634,30 +648,32 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
             r += xprev;
           } else if (kind == 2u) {
             const uint32_t n = (i8[j] >> 10) & 7u;
-            if (n == 7u) {
-              const uint32_t l0 = p.int_ptr[vbeg + loc], l1 = p.int_ptr[vbeg + loc + 1];
-              for (uint32_t e = l0; e < l1 && ok; ++e) {
-                const int u = p.int_src[e];
-                if (!inside(u)) continue;
-                const double xv = u - vbeg == prev ? xprev : ld_lx(u - vbeg);
-                if (xv < 0.0) ok = false;
-                else r += xv;
-              }
-            } else {
-              const uint32_t pk4 = sP[q];
-              double xs[4];
+            const uint4 s4 = sS[q];
+            const uint32_t w4[4] = {s4.x, s4.y, s4.z, s4.w};
+            double xs[4];
 #pragma unroll
-              for (int m = 0; m < 4; ++m) {
-                const int u = (int)((pk4 >> (8 * m)) & 0xffu);
-                xs[m] = (uint32_t)m < n ? (u == prev ? xprev : ld_lx(u)) : 0.0;
-              }
+            for (int m = 0; m < 4; ++m) {
+              const uint32_t w = w4[m];
+              xs[m] = (uint32_t)m >= n ? 0.0
+                      : (w & kExt)     ? ld_x(p.x, (int)(w & ~kExt))
+                      : (int)w == prev ? xprev
+                                       : ld_lx((int)w);
+            }
 #pragma unroll
-              for (int m = 0; m < 4; ++m) {
-                if ((uint32_t)m < n) {
-                  ok = ok && xs[m] >= 0.0;
-                  r += xs[m];
-                }
+            for (int m = 0; m < 4; ++m) {
+              if ((uint32_t)m < n) {
+                ok = ok && xs[m] >= 0.0;
+                r += xs[m];
               }
+            }
+          } else if (kind == 3u) {
+            const uint32_t l0 = p.int_ptr[vbeg + loc], l1 = p.int_ptr[vbeg + loc + 1];
+            for (uint32_t e = l0; e < l1 && ok; ++e) {
+              const int u = p.int_src[e];
+              if (!inside(u)) continue;
+              const double xv = u - vbeg == prev ? xprev : ld_lx(u - vbeg);
+              if (xv < 0.0) ok = false;
+              else r += xv;
             }
           }
           if (!ok) {
@@ -1096,78 +1112,123 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
     }
   }
   const unsigned long long t_it = wall_clock64();
-  // LDS layout when staged: R (double) | y0 | y1 | inv (float) | ptr (u32, nv+1) | src (u16)
-  const size_t need = (size_t)nv * (8 + 2 * sizeof(YT) + 4) + 2 * sizeof(YT) + 4 * (size_t)(nv + 1) +
-                      2 * (size_t)ne + 64;
-  const bool staged = need <= raw_bytes && nv <= 65535;
+  // Staged in LDS when it fits: R (double) | y0 | y1 (nv terms and a zero
+  // pad each) | 1/outdeg | slot sums (all YT) | sources (u16) | slot starts
+  // (u16) | first slot of each row (u16).  The in-edges of each row are cut
+  // into slots of at most kSlot; a term is (A) every thread sums whole slots,
+  // (B) every row adds its slot sums in slot order (a row with more than
+  // kSlot slots: the whole wavefront), so the work of a term is spread evenly
+  // over the workgroup whatever the in-degrees.
+  constexpr uint32_t kSlot = 8;
+  const uint32_t sbound = ne / kSlot + (uint32_t)nv;  // slots: at most this many
+  const size_t need = (size_t)nv * 8 + (3 * (size_t)nv + 2 + sbound) * sizeof(YT) + 2 * (size_t)ne +
+                      2 * ((size_t)sbound + 1) + 2 * ((size_t)nv + 1) + 64;
+  const bool staged = need <= raw_bytes && nv <= 65535 && ne <= 65535 && sbound < 65535;
   if (staged) {
     double* lR = reinterpret_cast<double*>(raw);
-    YT* l0 = reinterpret_cast<YT*>(lR + nv);  // nv terms and a zero pad
+    YT* l0 = reinterpret_cast<YT*>(lR + nv);
     YT* l1 = l0 + nv + 1;
-    float* linv = reinterpret_cast<float*>(l1 + nv + 1);
-    uint32_t* lptr = reinterpret_cast<uint32_t*>(linv + nv);
-    uint16_t* lsrc = reinterpret_cast<uint16_t*>(lptr + nv + 1);
+    YT* linv = l1 + nv + 1;
+    YT* lpart = linv + nv;
+    uint16_t* lsrc = reinterpret_cast<uint16_t*>(lpart + sbound);
+    uint16_t* lsst = lsrc + ne;
+    uint16_t* lfs = lsst + sbound + 1;
     for (int q = threadIdx.x; q < nv; q += kThreads) {
       lR[q] = p.R[vb + q];
       l0[q] = ya[vb + q];
-      linv[q] = p.inv32[vb + q];
+      if constexpr (sizeof(YT) == 8) linv[q] = p.inv64[vb + q];
+      else linv[q] = p.inv32[vb + q];
     }
-    for (int q = threadIdx.x; q <= nv; q += kThreads) lptr[q] = ptr[vb + q] - eb;
     if (threadIdx.x == 0) {
       l0[nv] = (YT)0;
       l1[nv] = (YT)0;
     }
     for (uint32_t q = threadIdx.x; q < ne; q += kThreads) lsrc[q] = (uint16_t)(src[eb + q] - vb);
-    __syncthreads();
+    // slots: thread t cuts the rows of its contiguous block; an exclusive
+    // scan of the per-thread slot counts places them
+    {
+      const int chunk = (nv + kThreads - 1) / kThreads;
+      const int r0 = min(nv, (int)threadIdx.x * chunk), r1 = min(nv, r0 + chunk);
+      uint32_t cnt = 0;
+      for (int r = r0; r < r1; ++r) cnt += (ptr[vb + r + 1] - ptr[vb + r] + kSlot - 1) / kSlot;
+      uint32_t incl = cnt;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+      }
+      uint32_t* wtot = reinterpret_cast<uint32_t*>(red);
+      if (lane == 63) wtot[wave] = incl;
+      __syncthreads();
+      uint32_t run = incl - cnt, total = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) run += wtot[w];
+        total += wtot[w];
+      }
+      for (int r = r0; r < r1; ++r) {
+        lfs[r] = (uint16_t)run;
+        const uint32_t e0 = ptr[vb + r] - eb, e1 = ptr[vb + r + 1] - eb;
+        for (uint32_t e = e0; e < e1; e += kSlot) lsst[run++] = (uint16_t)e;
+      }
+      if (threadIdx.x == 0) {
+        lfs[nv] = (uint16_t)total;
+        lsst[total] = (uint16_t)ne;
+      }
+      __syncthreads();
+    }
+    const int nslot = lfs[nv];
     YT* la = l0;
     YT* lb = l1;
     if (!skip) {
       conv = false;
       while (k < p.max_iter) {
         ++k;
+        // (A) slot sums: eight independent source ids, then eight values
+        for (int sl = threadIdx.x; sl < nslot; sl += kThreads) {
+          const uint32_t e0 = lsst[sl], e1 = lsst[sl + 1];
+          uint32_t ix[kSlot];
+#pragma unroll
+          for (uint32_t j = 0; j < kSlot; ++j) ix[j] = e0 + j < e1 ? lsrc[e0 + j] : (uint32_t)nv;
+          YT g[kSlot];
+#pragma unroll
+          for (uint32_t j = 0; j < kSlot; ++j) g[j] = la[ix[j]];
+          lpart[sl] = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
+        }
+        __syncthreads();
+        // (B) row sums
         part = 0.0;
         double pm = 0.0;
-        auto finish = [&](int r, YT s) {
-          lR[r] += (double)s;
-          if constexpr (sizeof(YT) == 8) lb[r] = cy * s * p.inv64[vb + r];
-          else lb[r] = cy * s * linv[r];
-          part += fabs((double)s);
-          pm = fmax(pm, fabs((double)s));
+        auto finish = [&](int r, YT sv) {
+          lR[r] += (double)sv;
+          lb[r] = cy * sv * linv[r];
+          part += fabs((double)sv);
+          pm = fmax(pm, fabs((double)sv));
         };
         for (int rb = wave * 64; rb < nv; rb += kThreads) {
           const int r = rb + lane;
-          const uint32_t lo = r < nv ? lptr[r] : 0u, hi = r < nv ? lptr[r + 1] : 0u;
-          // a row with more than kHubLane sources is summed by the whole
-          // wavefront below; the others by their lane, eight independent
-          // gathers per step (source ids, then values: one LDS wait each)
-          const bool hub = hi - lo > kHubLane;
-          if (r < nv && !hub) {
-            YT s = 0;
-            for (uint32_t e = lo; e < hi; e += 8) {
-              uint32_t ix[8];
+          const uint32_t f0 = r < nv ? lfs[r] : 0u, f1 = r < nv ? lfs[r + 1] : 0u;
+          const bool wide = f1 - f0 > kSlot;
+          if (r < nv && !wide) {
+            YT h[kSlot];
 #pragma unroll
-              for (int j = 0; j < 8; ++j) ix[j] = e + j < hi ? lsrc[e + j] : (uint32_t)nv;
-              YT g[8];
-#pragma unroll
-              for (int j = 0; j < 8; ++j) g[j] = la[ix[j]];
-              s += ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
-            }
-            finish(r, s);
+            for (uint32_t j = 0; j < kSlot; ++j) h[j] = f0 + j < f1 ? lpart[f0 + j] : (YT)0;
+            finish(r, ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])));
           }
-          unsigned long long m = __ballot(r < nv && hub);
+          unsigned long long m = __ballot(r < nv && wide);
           while (m) {
             const int b = __ffsll(m) - 1;
             m &= m - 1;
-            const uint32_t blo = __shfl(lo, b, 64), bhi = __shfl(hi, b, 64);
-            YT s = 0;
+            const uint32_t blo = __shfl(f0, b, 64), bhi = __shfl(f1, b, 64);
+            YT sv = 0;
             for (uint32_t e = blo + lane; e < bhi; e += 256) {
               YT g[4];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) g[j] = e + 64 * j < bhi ? la[lsrc[e + 64 * j]] : (YT)0;
-              s += (g[0] + g[1]) + (g[2] + g[3]);
+              for (int j = 0; j < 4; ++j) g[j] = e + 64 * j < bhi ? lpart[e + 64 * j] : (YT)0;
+              sv += (g[0] + g[1]) + (g[2] + g[3]);
             }
-            s = wave_sum(s);
-            if (lane == b) finish(r, s);
+            sv = wave_sum(sv);
+            if (lane == b) finish(r, sv);
           }
         }
         double norm, mx;
@@ -1244,7 +1305,8 @@ __device__ inline void flush_stats(const SolveParams& p, unsigned long long* s_s
 // are gathered, and a vertex item keeps its local x values in the second part.
 constexpr size_t kSegLds = 53 * 1024;  // three workgroups per CU (the VGPR limit too)
 static_assert(kWaves * sizeof(WaveTile) + kWaves * 2 * kSmallMax * sizeof(double) <= kSegLds, "segment LDS");
-static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + (4 * kThreads + 1 + kWaves) * sizeof(int32_t) <=
+static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + kThreads * sizeof(uint4) +
+                      (3 * kThreads + 1 + kWaves) * sizeof(int32_t) <=
                   kSegLds,
               "vertex item LDS");
 
