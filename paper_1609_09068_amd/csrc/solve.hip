@@ -503,6 +503,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
   const bool early = pw & 0x10000u;  // v has a CAC edge into a later item
   if (act) sQ[pw & 0xffu] = i | (pstart ? 0x10000 : 0);
   sX[i] = -1.0;  // the LDS still holds the previous item's values
+  sI[i] = 0u;    // bit 15 marks a position whose entries are written
   const unsigned long long sm = __ballot(pstart);
   if (lane == 0) sWc[wave] = (int32_t)__popcll(sm);
   __syncthreads();
@@ -603,11 +604,14 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
     sA[q] = acc;
     sC[q] = p.c * p.inv64[v];
     sS[q] = make_uint4(s0, s1, s2, s3);
-    sI[q] = (uint32_t)i | (kind << 8) | ((ns > 4u ? 7u : ns) << 10) | (early ? 0x2000u : 0u);
+    __hip_atomic_store(sI + q, (uint32_t)i | (kind << 8) | ((ns > 4u ? 7u : ns) << 10) | (early ? 0x2000u : 0u) | 0x8000u,
+                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   if (p.trace && lane == 0) atomicMax(tile->rdy, wall_clock64());
-  __syncthreads();
-  // 2. walk the paths; lanes retry in rounds until every path is done
+  // 2. walk the paths; lanes retry in rounds until every path is done.  No
+  // barrier: a lane walks as far as the positions whose entries are written
+  // (sI bit 15), so a wavefront still waiting for rank from higher levels
+  // holds back only the paths through its own vertices.
   int q = 0, qe = 0;
   {
     int tot = 0;
@@ -633,9 +637,34 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int qq = q + j < qe ? q + j : qe - 1;
+        i8[j] = __hip_atomic_load(sI + qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int qq = q + j < qe ? q + j : qe - 1;
         a8[j] = sA[qq];
         c8[j] = sC[qq];
-        i8[j] = sI[qq];
+      }
+      // eight written hops of kind 0 or 1 (kind bit 9 clear) inside the
+      // path: a straight run with no per-hop branch on the kind
+      const uint32_t all8 = ((i8[0] & i8[1]) & (i8[2] & i8[3])) & ((i8[4] & i8[5]) & (i8[6] & i8[7]));
+      const uint32_t any8 = ((i8[0] | i8[1]) | (i8[2] | i8[3])) | ((i8[4] | i8[5]) | (i8[6] | i8[7]));
+      if (q + 8 <= qe && (all8 & 0x8000u) && (any8 & 0x200u) == 0u) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int loc = (int)(i8[j] & 0xffu);
+          const double r = (i8[j] & 0x100u) ? a8[j] + xprev : a8[j];
+          const double xv = c8[j] * r;
+          st_lx(loc, xv);
+          sR[loc] = r;
+          if (i8[j] & 0x2000u) st_x(p.x, vbeg + loc, xv);
+          xprev = xv;
+        }
+        prev = (int)(i8[7] & 0xffu);
+        q += 8;
+        stop = q >= qe;
+        continue;
       }
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -643,8 +672,9 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
           const int loc = (int)(i8[j] & 0xffu);
           const uint32_t kind = (i8[j] >> 8) & 3u;
           double r = a8[j];
-          bool ok = true;
-          if (kind == 1u) {
+          bool ok = (i8[j] & 0x8000u) != 0u;
+          if (!ok) {
+          } else if (kind == 1u) {
             r += xprev;
           } else if (kind == 2u) {
             const uint32_t n = (i8[j] >> 10) & 7u;
@@ -1112,40 +1142,36 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
     }
   }
   const unsigned long long t_it = wall_clock64();
-  // Staged in LDS when it fits: R (double) | y0 | y1 (nv terms and a zero
-  // pad each) | 1/outdeg | slot sums (all YT) | sources (u16) | slot starts
-  // (u16) | first slot of each row (u16).  The in-edges of each row are cut
-  // into slots of at most kSlot; a term is (A) every thread sums whole slots,
+  // Register-resident iteration when the component is small enough.  The
+  // in-edges of each row are cut into slots of at most kSlot; slot s belongs
+  // to thread s % 256 and row r to thread r % 256.  Each thread keeps its
+  // slots' source ids, and its rows' R, 1/outdeg and slot ranges, in
+  // registers; only the terms (y0, y1: nv values and a zero pad each) and the
+  // slot sums live in LDS.  A term is (A) every thread sums its slots,
   // (B) every row adds its slot sums in slot order (a row with more than
   // kSlot slots: the whole wavefront), so the work of a term is spread evenly
   // over the workgroup whatever the in-degrees.
   constexpr uint32_t kSlot = 8;
-  const uint32_t sbound = ne / kSlot + (uint32_t)nv;  // slots: at most this many
-  const size_t need = (size_t)nv * 8 + (3 * (size_t)nv + 2 + sbound) * sizeof(YT) + 2 * (size_t)ne +
-                      2 * ((size_t)sbound + 1) + 2 * ((size_t)nv + 1) + 64;
-  const bool staged = need <= raw_bytes && nv <= 65535 && ne <= 65535 && sbound < 65535;
+  constexpr int kSPT = 4;  // slots per thread
+  constexpr int kRPT = 4;  // rows per thread
+  uint32_t nslot = 0;
+  {
+    // slot count of each row; thread t counts the rows of its contiguous block
+    const int chunk = (nv + kThreads - 1) / kThreads;
+    const int r0 = min(nv, (int)threadIdx.x * chunk), r1 = min(nv, r0 + chunk);
+    uint32_t cnt = 0;
+    for (int r = r0; r < r1; ++r) cnt += (ptr[vb + r + 1] - ptr[vb + r] + kSlot - 1) / kSlot;
+    nslot = (uint32_t)block_sum((double)cnt, red);
+  }
+  const size_t need = (2 * ((size_t)nv + 1) + nslot) * sizeof(YT) + 2 * ((size_t)nslot + 1) + 2 * ((size_t)nv + 1) + 64;
+  const bool staged = need <= raw_bytes && nv <= kThreads * kRPT && nslot <= (uint32_t)(kThreads * kSPT) &&
+                      ne <= 65535;
   if (staged) {
-    double* lR = reinterpret_cast<double*>(raw);
-    YT* l0 = reinterpret_cast<YT*>(lR + nv);
+    YT* l0 = reinterpret_cast<YT*>(raw);
     YT* l1 = l0 + nv + 1;
-    YT* linv = l1 + nv + 1;
-    YT* lpart = linv + nv;
-    uint16_t* lsrc = reinterpret_cast<uint16_t*>(lpart + sbound);
-    uint16_t* lsst = lsrc + ne;
-    uint16_t* lfs = lsst + sbound + 1;
-    for (int q = threadIdx.x; q < nv; q += kThreads) {
-      lR[q] = p.R[vb + q];
-      l0[q] = ya[vb + q];
-      if constexpr (sizeof(YT) == 8) linv[q] = p.inv64[vb + q];
-      else linv[q] = p.inv32[vb + q];
-    }
-    if (threadIdx.x == 0) {
-      l0[nv] = (YT)0;
-      l1[nv] = (YT)0;
-    }
-    for (uint32_t q = threadIdx.x; q < ne; q += kThreads) lsrc[q] = (uint16_t)(src[eb + q] - vb);
-    // slots: thread t cuts the rows of its contiguous block; an exclusive
-    // scan of the per-thread slot counts places them
+    YT* lpart = l1 + nv + 1;
+    uint16_t* lsst = reinterpret_cast<uint16_t*>(lpart + nslot);  // slot starts (staging only)
+    uint16_t* lfs = lsst + nslot + 1;                              // first slot of each row (staging only)
     {
       const int chunk = (nv + kThreads - 1) / kThreads;
       const int r0 = min(nv, (int)threadIdx.x * chunk), r1 = min(nv, r0 + chunk);
@@ -1160,75 +1186,105 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
       uint32_t* wtot = reinterpret_cast<uint32_t*>(red);
       if (lane == 63) wtot[wave] = incl;
       __syncthreads();
-      uint32_t run = incl - cnt, total = 0;
+      uint32_t run = incl - cnt;
 #pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
+      for (int w = 0; w < kWaves; ++w)
         if (w < wave) run += wtot[w];
-        total += wtot[w];
-      }
       for (int r = r0; r < r1; ++r) {
         lfs[r] = (uint16_t)run;
         const uint32_t e0 = ptr[vb + r] - eb, e1 = ptr[vb + r + 1] - eb;
         for (uint32_t e = e0; e < e1; e += kSlot) lsst[run++] = (uint16_t)e;
       }
       if (threadIdx.x == 0) {
-        lfs[nv] = (uint16_t)total;
-        lsst[total] = (uint16_t)ne;
+        lfs[nv] = (uint16_t)nslot;
+        lsst[nslot] = (uint16_t)ne;
+      }
+      for (int q = threadIdx.x; q < nv; q += kThreads) l0[q] = ya[vb + q];
+      if (threadIdx.x == 0) {
+        l0[nv] = (YT)0;
+        l1[nv] = (YT)0;
       }
       __syncthreads();
     }
-    const int nslot = lfs[nv];
+    // this thread's slots (source ids, two per register; nv is the zero pad)
+    // and rows
+    uint32_t sid[kSPT][kSlot / 2];
+#pragma unroll
+    for (int j = 0; j < kSPT; ++j) {
+      const uint32_t sl = threadIdx.x + kThreads * j;
+      const uint32_t e0 = sl < nslot ? lsst[sl] : 0u, e1 = sl < nslot ? lsst[sl + 1] : 0u;
+#pragma unroll
+      for (uint32_t m = 0; m < kSlot; m += 2) {
+        const uint32_t a0 = e0 + m < e1 ? (uint32_t)(src[eb + e0 + m] - vb) : (uint32_t)nv;
+        const uint32_t a1 = e0 + m + 1 < e1 ? (uint32_t)(src[eb + e0 + m + 1] - vb) : (uint32_t)nv;
+        sid[j][m / 2] = a0 | (a1 << 16);
+      }
+    }
+    double Rr[kRPT];
+    YT ir[kRPT];
+    uint32_t fr[kRPT];
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int r = threadIdx.x + kThreads * j;
+      Rr[j] = r < nv ? p.R[vb + r] : 0.0;
+      if constexpr (sizeof(YT) == 8) ir[j] = r < nv ? p.inv64[vb + r] : 0.0;
+      else ir[j] = r < nv ? p.inv32[vb + r] : 0.0f;
+      fr[j] = r < nv ? ((uint32_t)lfs[r] | ((uint32_t)lfs[r + 1] << 16)) : 0u;
+    }
     YT* la = l0;
     YT* lb = l1;
     if (!skip) {
       conv = false;
       while (k < p.max_iter) {
         ++k;
-        // (A) slot sums: eight independent source ids, then eight values
-        for (int sl = threadIdx.x; sl < nslot; sl += kThreads) {
-          const uint32_t e0 = lsst[sl], e1 = lsst[sl + 1];
-          uint32_t ix[kSlot];
+        // (A) slot sums
 #pragma unroll
-          for (uint32_t j = 0; j < kSlot; ++j) ix[j] = e0 + j < e1 ? lsrc[e0 + j] : (uint32_t)nv;
-          YT g[kSlot];
+        for (int j = 0; j < kSPT; ++j) {
+          const uint32_t sl = threadIdx.x + kThreads * j;
+          if (sl < nslot) {
+            YT g[kSlot];
 #pragma unroll
-          for (uint32_t j = 0; j < kSlot; ++j) g[j] = la[ix[j]];
-          lpart[sl] = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
+            for (uint32_t m = 0; m < kSlot; ++m) g[m] = la[(sid[j][m / 2] >> (16 * (m & 1))) & 0xffffu];
+            lpart[sl] = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
+          }
         }
         __syncthreads();
         // (B) row sums
-        part = 0.0;
-        double pm = 0.0;
-        auto finish = [&](int r, YT sv) {
-          lR[r] += (double)sv;
-          lb[r] = cy * sv * linv[r];
-          part += fabs((double)sv);
-          pm = fmax(pm, fabs((double)sv));
-        };
-        for (int rb = wave * 64; rb < nv; rb += kThreads) {
-          const int r = rb + lane;
-          const uint32_t f0 = r < nv ? lfs[r] : 0u, f1 = r < nv ? lfs[r + 1] : 0u;
-          const bool wide = f1 - f0 > kSlot;
-          if (r < nv && !wide) {
-            YT h[kSlot];
+        double part = 0.0, pm = 0.0;
 #pragma unroll
-            for (uint32_t j = 0; j < kSlot; ++j) h[j] = f0 + j < f1 ? lpart[f0 + j] : (YT)0;
-            finish(r, ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])));
-          }
-          unsigned long long m = __ballot(r < nv && wide);
-          while (m) {
-            const int b = __ffsll(m) - 1;
-            m &= m - 1;
-            const uint32_t blo = __shfl(f0, b, 64), bhi = __shfl(f1, b, 64);
+        for (int j = 0; j < kRPT; ++j) {
+          if (kThreads * j + wave * 64 < nv) {  // wave-uniform
+            const int r = threadIdx.x + kThreads * j;
+            const uint32_t f0 = fr[j] & 0xffffu, f1 = fr[j] >> 16;
+            const bool wide = f1 - f0 > kSlot;
             YT sv = 0;
-            for (uint32_t e = blo + lane; e < bhi; e += 256) {
-              YT g[4];
+            if (r < nv && !wide) {
+              YT h[kSlot];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) g[j] = e + 64 * j < bhi ? lpart[e + 64 * j] : (YT)0;
-              sv += (g[0] + g[1]) + (g[2] + g[3]);
+              for (uint32_t m = 0; m < kSlot; ++m) h[m] = f0 + m < f1 ? lpart[f0 + m] : (YT)0;
+              sv = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));
             }
-            sv = wave_sum(sv);
-            if (lane == b) finish(r, sv);
+            unsigned long long m = __ballot(r < nv && wide);
+            while (m) {
+              const int b = __ffsll(m) - 1;
+              m &= m - 1;
+              const uint32_t blo = __shfl(f0, b, 64), bhi = __shfl(f1, b, 64);
+              YT ws = 0;
+              for (uint32_t e = blo + lane; e < bhi; e += 256) {
+                YT g[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) g[q] = e + 64 * q < bhi ? lpart[e + 64 * q] : (YT)0;
+                ws += (g[0] + g[1]) + (g[2] + g[3]);
+              }
+              ws = wave_sum(ws);
+              if (lane == b) sv = ws;
+            }
+            if (r < nv) {
+              Rr[j] += (double)sv;
+              lb[r] = cy * sv * ir[j];
+              part += fabs((double)sv);
+              pm = fmax(pm, fabs((double)sv));
+            }
           }
         }
         double norm, mx;
@@ -1243,10 +1299,13 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
         }
       }
     }
-    for (int q = threadIdx.x; q < nv; q += kThreads) {
-      const double r = lR[q];
-      p.Rout[p.perm[vb + q]] = r;
-      st_x(p.x, vb + q, c * r * p.inv64[vb + q]);
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int r = threadIdx.x + kThreads * j;
+      if (r < nv) {
+        p.Rout[p.perm[vb + r]] = Rr[j];
+        st_x(p.x, vb + r, c * Rr[j] * p.inv64[vb + r]);
+      }
     }
   } else {
     if (!skip) {
@@ -1316,7 +1375,7 @@ static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + kThrea
 // handed out before it, and those are held by running workgroups; the
 // lowest unfinished item has nothing left to wait for.
 template <typename YT, int RPW, bool WARM>
-__global__ __launch_bounds__(kThreads) void k_segment(SolveParams p) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ? 1 : 3))) void k_segment(SolveParams p) {
   __shared__ double s_red[16];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kSegLds];
   __shared__ unsigned long long s_stats[kWgStats];
