@@ -235,7 +235,9 @@ def main():
     ap.add_argument("--study", action="store_true",
                     help="precision study: c in {0.85, 0.99} x {mixed, fp64} x {componentwise, plain}; prints one "
                          "JSON line of its own instead of the benchmark line")
-    ap.add_argument("--graph", type=int, default=0, help="replay a captured hipGraph")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="time hipGraph replays of the solve (1, default) or eager launches (0); the per-kernel "
+                         "durations always come from a second, eager pass with an event pair around every launch")
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--small-cutoff", type=int, default=0)
     ap.add_argument("--team-edges", type=int, default=0)
@@ -303,8 +305,7 @@ def main():
     if args.study:
         run_study(args, pr, torch, g, lv, info, W, R, t_part, t_build)
         return
-    common = dict(eps=args.eps, precision=args.precision, use_graph=args.graph,
-                  kernel_timing=0 if args.graph else 1)
+    common = dict(eps=args.eps, precision=args.precision, use_graph=args.graph, kernel_timing=0)
 
     def run(method, Rout, steps, **extra):
         stats = []
@@ -322,8 +323,8 @@ def main():
         net = None
         if meth == 0 and not args.no_warm and os.path.exists(args.warm_net):
             net = pr.Mlp.load_file(args.warm_net)
-        for _ in range(args.warmup + args.steps):
-            run(meth, R, 1, **(dict(warm_start=net) if net is not None else {}))
+        for _ in range(args.warmup + args.steps):  # eager launches: one profiler record per kernel
+            run(meth, R, 1, use_graph=0, **(dict(warm_start=net) if net is not None else {}))
         if args.calib_copy_mb:
             calib_copy(torch, args.calib_copy_mb)
         log(f"{args.only}: {args.warmup + args.steps} solves done")
@@ -339,15 +340,20 @@ def main():
         run(0, R, 1, **wopt)
         run(0, Rn, 1)
         run(1, Rp, 1)
-    # the same solve without per-launch events: shows what the events cost
-    t_ne, _ = run(0, R, 2, kernel_timing=0, **wopt)
-    log(f"warmup done; componentwise without launch events {t_ne / 2 * 1e3:.3f} ms")
+    mode = "hipGraph replay" if args.graph else "eager launches"
+    log(f"warmup done; timing {args.steps} solves of each ({mode})")
     t_cw, st_cw = run(0, R, args.steps, **wopt)
     log(f"componentwise{' + starting guess' if net else ''}: {t_cw / args.steps * 1e3:.3f} ms/step")
     t_cn, st_cn = run(0, Rn, args.steps)
     log(f"componentwise, plain start: {t_cn / args.steps * 1e3:.3f} ms/step")
     t_pl, st_pl = run(1, Rp, args.steps)
     log(f"plain: {t_pl / args.steps * 1e3:.3f} ms/step")
+    # per-kernel durations: the same solves, eager, an event pair around every
+    # launch on the solve stream (the events add a little host time per launch)
+    t_ecw, st_ecw = run(0, R, args.steps, use_graph=0, kernel_timing=1, **wopt)
+    t_epl, st_epl = run(1, Rp, args.steps, use_graph=0, kernel_timing=1)
+    log(f"eager with launch events: componentwise {t_ecw / args.steps * 1e3:.3f} ms/step, "
+        f"plain {t_epl / args.steps * 1e3:.3f} ms/step")
 
     if args.calib_copy_mb:
         calib_copy(torch, args.calib_copy_mb)
@@ -363,8 +369,8 @@ def main():
         d["kernel_ms"] = float(np.mean([x["kernel_ms"] for x in sts]))
         return d
 
-    mcw = mean_stats(st_cw)
-    mpl = mean_stats(st_pl)
+    mcw = mean_stats(st_ecw)
+    mpl = mean_stats(st_epl)
     value = s["edge_iters"] / (ms_cw * 1e-3) / 1e9
     dom = int(np.argmax(mcw["kt_ms"])) if any(mcw["kt_ms"]) else 0
     traffic_cw = load_traffic(args.traffic, FAMILIES[dom] + "/componentwise")
@@ -448,9 +454,10 @@ def main():
                    "autotuned": bool(bopts.get("autotune", 0))},
         "time_to_1e-6_ms": {"componentwise": round(ms_cw, 4), "plain": round(ms_pl, 4),
                             "componentwise_plain_start": round(t_cn / args.steps * 1e3, 4),
-                            "componentwise_device": round(mcw["kernel_ms"], 4),
-                            "plain_device": round(mpl["kernel_ms"], 4),
-                            "componentwise_no_launch_events": round(t_ne / 2 * 1e3, 4)},
+                            "componentwise_device_eager": round(mcw["kernel_ms"], 4),
+                            "plain_device_eager": round(mpl["kernel_ms"], 4),
+                            "componentwise_eager_with_launch_events": round(t_ecw / args.steps * 1e3, 4),
+                            "plain_eager_with_launch_events": round(t_epl / args.steps * 1e3, 4)},
         "speedup_vs_plain": round(ms_pl / ms_cw, 3),
         "plain_gedge_iter_s": round(sp["edge_iters"] / (ms_pl * 1e-3) / 1e9, 4),
         "plain_equivalent_gedge_iter_s": round(sp["edge_iters"] / (ms_cw * 1e-3) / 1e9, 4),
