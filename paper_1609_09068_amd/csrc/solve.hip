@@ -473,6 +473,7 @@ __device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const 
 // x_v = c R_v / outdeg(v) is published the moment R_v is final when a later
 // item needs it (a CAC edge into a later item), else when the item ends.
 // Every sum has a fixed order (the schedule depends only on the graph).
+constexpr int kWalkBatches = 2;
 __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* tile,
                                                           double* lds) {
   const int lane = threadIdx.x & 63;
@@ -629,7 +630,11 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
   while (true) {
     const int qb = q;
     bool stop = q >= qe;
-    while (!stop) {
+    // at most kWalkBatches batches per round: the lanes of a wavefront run in
+    // lockstep, so a lane blocked on another path retries only when every
+    // lane of its wavefront has ended the round
+    int nb = 0;
+    while (!stop && nb++ < kWalkBatches) {
       // the next eight positions in one LDS round trip; hops of kind 0 and 1
       // then run from registers
       double a8[8], c8[8];
