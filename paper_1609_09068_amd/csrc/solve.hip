@@ -352,6 +352,7 @@ __device__ inline bool wave_gather_x_try(const SolveParams& p, const int32_t* sr
 // result does not depend on timing.  With WAIT_X the values are the x
 // vector and a chunk is re-read until every source is final.
 constexpr int kChunk = 512;
+constexpr uint32_t kBigPart = 16;  // per lane of a row: above this the whole wavefront sums the row's part
 
 struct WaveTile {
   double buf[kChunk];
@@ -438,15 +439,30 @@ __device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const 
       const int row = b * RPW + lane / LPR;
       const int sub = lane % LPR;
       VT s = (VT)0;
-      bool touch = false;
+      bool touch = false, big = false;
+      uint32_t a = 0, z = 0;
       if (row < nr) {
         const uint32_t rl = t->rlo[row], rh = t->rhi[row];
-        const uint32_t a = rl > cs ? rl : cs, z = rh < ce ? rh : ce;
+        a = rl > cs ? rl : cs;
+        z = rh < ce ? rh : ce;
         touch = a < z;
-        for (uint32_t e = a + sub; e < z; e += LPR) s += buf[e - cs];
+        // a row with many sources in this chunk is summed by the wavefront
+        big = z > a + kBigPart * LPR;
+        if (!big)
+          for (uint32_t e = a + sub; e < z; e += LPR) s += buf[e - cs];
       }
       s = group_sum<LPR>(s);
-      if (touch && sub == 0) racc[row] += s;
+      if (touch && !big && sub == 0) racc[row] += s;
+      unsigned long long mb = __ballot(big && sub == 0);
+      while (mb) {
+        const int bl = __ffsll(mb) - 1;
+        mb &= mb - 1;
+        const uint32_t ba = __shfl(a, bl, 64), bz = __shfl(z, bl, 64);
+        VT h = (VT)0;
+        for (uint32_t e = ba + lane; e < bz; e += 64) h += buf[e - cs];
+        h = wave_sum(h);
+        if (lane == bl) racc[row] += h;
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
