@@ -97,6 +97,8 @@ struct SolveParams {
   void* y1;
   const Item* items;
   const uint32_t* vpath;
+  const uint32_t* mslot_ptr;
+  const uint4* mslot_src;
   const int32_t* comp_vbeg;
   int32_t* iters;
   double* lastnorm;
@@ -1172,60 +1174,126 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
   // (B) every row adds its slot sums in slot order (a row with more than
   // kSlot slots: the whole wavefront), so the work of a term is spread evenly
   // over the workgroup whatever the in-degrees.
-  constexpr uint32_t kSlot = 8;
-  constexpr int kSPT = 4;  // slots per thread
-  constexpr int kRPT = 4;  // rows per thread
-  uint32_t nslot = 0;
-  {
-    // slot count of each row; thread t counts the rows of its contiguous block
-    const int chunk = (nv + kThreads - 1) / kThreads;
-    const int r0 = min(nv, (int)threadIdx.x * chunk), r1 = min(nv, r0 + chunk);
-    uint32_t cnt = 0;
-    for (int r = r0; r < r1; ++r) cnt += (ptr[vb + r + 1] - ptr[vb + r] + kSlot - 1) / kSlot;
-    nslot = (uint32_t)block_sum((double)cnt, red);
-  }
-  const size_t need = (2 * ((size_t)nv + 1) + nslot) * sizeof(YT) + 2 * ((size_t)nslot + 1) + 2 * ((size_t)nv + 1) + 64;
-  const bool staged = need <= raw_bytes && nv <= kThreads * kRPT && nslot <= (uint32_t)(kThreads * kSPT) &&
-                      ne <= 65535;
-  if (staged) {
+  constexpr uint32_t kSlot = 8;  // the plan's slot width (k_medium_slots)
+  constexpr int kSPT = 4;         // slots per thread
+  constexpr int kRPT = 4;         // rows per thread
+  const uint32_t sb = p.mslot_ptr[vb];
+  const uint32_t nslot = p.mslot_ptr[ve] - sb;
+  const size_t need = (2 * ((size_t)nv + 1) + nslot) * sizeof(YT) + 64;
+  const bool staged = need <= raw_bytes && nv <= kThreads * kRPT && nslot <= (uint32_t)(kThreads * kSPT);
+  // (the plan cuts slots only for components of at most 65535 vertices: the
+  // ids are 16-bit and the component size is the zero pad)
+  // larger components: the same two phases with the slots read from the plan
+  // every term (L2-resident) and R, 1/outdeg and the row slot ranges in LDS
+  const size_t need_big = (3 * (size_t)nv + 2 + nslot) * sizeof(YT) + 8 * (size_t)nv + 4 * ((size_t)nv + 1) + 64;
+  const bool staged_big = !staged && need_big <= raw_bytes && nv <= 65535;
+  if (staged_big) {
+    double* lR = reinterpret_cast<double*>(raw);
+    YT* l0 = reinterpret_cast<YT*>(lR + nv);
+    YT* l1 = l0 + nv + 1;
+    YT* linv = l1 + nv + 1;
+    YT* lpart = linv + nv;
+    uint32_t* lfs = reinterpret_cast<uint32_t*>(lpart + nslot);
+    for (int q = threadIdx.x; q < nv; q += kThreads) {
+      lR[q] = p.R[vb + q];
+      l0[q] = ya[vb + q];
+      if constexpr (sizeof(YT) == 8) linv[q] = p.inv64[vb + q];
+      else linv[q] = p.inv32[vb + q];
+    }
+    for (int q = threadIdx.x; q <= nv; q += kThreads) lfs[q] = p.mslot_ptr[vb + q] - sb;
+    if (threadIdx.x == 0) {
+      l0[nv] = (YT)0;
+      l1[nv] = (YT)0;
+    }
+    __syncthreads();
+    const uint4* gs = p.mslot_src + sb;
+    YT* la = l0;
+    YT* lb = l1;
+    if (!skip) {
+      conv = false;
+      while (k < p.max_iter) {
+        ++k;
+        // (A) slot sums, four slots' ids in flight per thread
+        for (uint32_t base = threadIdx.x; base < nslot; base += 4 * kThreads) {
+          uint4 w[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t sl = base + kThreads * j;
+            w[j] = sl < nslot ? gs[sl] : make_uint4(0u, 0u, 0u, 0u);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t sl = base + kThreads * j;
+            if (sl < nslot) {
+              const uint32_t wv[4] = {w[j].x, w[j].y, w[j].z, w[j].w};
+              YT g[kSlot];
+#pragma unroll
+              for (uint32_t m = 0; m < kSlot; ++m) g[m] = la[(wv[m / 2] >> (16 * (m & 1))) & 0xffffu];
+              lpart[sl] = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
+            }
+          }
+        }
+        __syncthreads();
+        // (B) row sums
+        double part = 0.0, pm = 0.0;
+        for (int rb = wave * 64; rb < nv; rb += kThreads) {
+          const int r = rb + lane;
+          const uint32_t f0 = r < nv ? lfs[r] : 0u, f1 = r < nv ? lfs[r + 1] : 0u;
+          const bool wide = f1 - f0 > kSlot;
+          YT sv = 0;
+          if (r < nv && !wide) {
+            YT h[kSlot];
+#pragma unroll
+            for (uint32_t m = 0; m < kSlot; ++m) h[m] = f0 + m < f1 ? lpart[f0 + m] : (YT)0;
+            sv = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));
+          }
+          unsigned long long m = __ballot(r < nv && wide);
+          while (m) {
+            const int bl = __ffsll(m) - 1;
+            m &= m - 1;
+            const uint32_t blo = __shfl(f0, bl, 64), bhi = __shfl(f1, bl, 64);
+            YT ws = 0;
+            for (uint32_t e = blo + lane; e < bhi; e += 256) {
+              YT g[4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) g[q] = e + 64 * q < bhi ? lpart[e + 64 * q] : (YT)0;
+              ws += (g[0] + g[1]) + (g[2] + g[3]);
+            }
+            ws = wave_sum(ws);
+            if (lane == bl) sv = ws;
+          }
+          if (r < nv) {
+            lR[r] += (double)sv;
+            lb[r] = cy * sv * linv[r];
+            part += fabs((double)sv);
+            pm = fmax(pm, fabs((double)sv));
+          }
+        }
+        double norm, mx;
+        block_sum_max(part, pm, red, (int)(k & 1), &norm, &mx);  // the barrier also publishes lb
+        last = norm;
+        YT* tt = la;
+        la = lb;
+        lb = tt;
+        if (stop_now(p, norm, mx, thresh)) {
+          conv = true;
+          break;
+        }
+      }
+    }
+    for (int q = threadIdx.x; q < nv; q += kThreads) {
+      const double r = lR[q];
+      p.Rout[p.perm[vb + q]] = r;
+      st_x(p.x, vb + q, c * r * p.inv64[vb + q]);
+    }
+  } else if (staged) {
     YT* l0 = reinterpret_cast<YT*>(raw);
     YT* l1 = l0 + nv + 1;
     YT* lpart = l1 + nv + 1;
-    uint16_t* lsst = reinterpret_cast<uint16_t*>(lpart + nslot);  // slot starts (staging only)
-    uint16_t* lfs = lsst + nslot + 1;                              // first slot of each row (staging only)
-    {
-      const int chunk = (nv + kThreads - 1) / kThreads;
-      const int r0 = min(nv, (int)threadIdx.x * chunk), r1 = min(nv, r0 + chunk);
-      uint32_t cnt = 0;
-      for (int r = r0; r < r1; ++r) cnt += (ptr[vb + r + 1] - ptr[vb + r] + kSlot - 1) / kSlot;
-      uint32_t incl = cnt;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += o;
-      }
-      uint32_t* wtot = reinterpret_cast<uint32_t*>(red);
-      if (lane == 63) wtot[wave] = incl;
-      __syncthreads();
-      uint32_t run = incl - cnt;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w)
-        if (w < wave) run += wtot[w];
-      for (int r = r0; r < r1; ++r) {
-        lfs[r] = (uint16_t)run;
-        const uint32_t e0 = ptr[vb + r] - eb, e1 = ptr[vb + r + 1] - eb;
-        for (uint32_t e = e0; e < e1; e += kSlot) lsst[run++] = (uint16_t)e;
-      }
-      if (threadIdx.x == 0) {
-        lfs[nv] = (uint16_t)nslot;
-        lsst[nslot] = (uint16_t)ne;
-      }
-      for (int q = threadIdx.x; q < nv; q += kThreads) l0[q] = ya[vb + q];
-      if (threadIdx.x == 0) {
-        l0[nv] = (YT)0;
-        l1[nv] = (YT)0;
-      }
-      __syncthreads();
+    for (int q = threadIdx.x; q < nv; q += kThreads) l0[q] = ya[vb + q];
+    if (threadIdx.x == 0) {
+      l0[nv] = (YT)0;
+      l1[nv] = (YT)0;
     }
     // this thread's slots (source ids, two per register; nv is the zero pad)
     // and rows
@@ -1233,13 +1301,11 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
 #pragma unroll
     for (int j = 0; j < kSPT; ++j) {
       const uint32_t sl = threadIdx.x + kThreads * j;
-      const uint32_t e0 = sl < nslot ? lsst[sl] : 0u, e1 = sl < nslot ? lsst[sl + 1] : 0u;
-#pragma unroll
-      for (uint32_t m = 0; m < kSlot; m += 2) {
-        const uint32_t a0 = e0 + m < e1 ? (uint32_t)(src[eb + e0 + m] - vb) : (uint32_t)nv;
-        const uint32_t a1 = e0 + m + 1 < e1 ? (uint32_t)(src[eb + e0 + m + 1] - vb) : (uint32_t)nv;
-        sid[j][m / 2] = a0 | (a1 << 16);
-      }
+      const uint4 w = sl < nslot ? p.mslot_src[sb + sl] : make_uint4(0u, 0u, 0u, 0u);
+      sid[j][0] = w.x;
+      sid[j][1] = w.y;
+      sid[j][2] = w.z;
+      sid[j][3] = w.w;
     }
     double Rr[kRPT];
     YT ir[kRPT];
@@ -1250,8 +1316,9 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
       Rr[j] = r < nv ? p.R[vb + r] : 0.0;
       if constexpr (sizeof(YT) == 8) ir[j] = r < nv ? p.inv64[vb + r] : 0.0;
       else ir[j] = r < nv ? p.inv32[vb + r] : 0.0f;
-      fr[j] = r < nv ? ((uint32_t)lfs[r] | ((uint32_t)lfs[r + 1] << 16)) : 0u;
+      fr[j] = r < nv ? ((p.mslot_ptr[vb + r] - sb) | ((p.mslot_ptr[vb + r + 1] - sb) << 16)) : 0u;
     }
+    __syncthreads();
     YT* la = l0;
     YT* lb = l1;
     if (!skip) {
@@ -2176,6 +2243,35 @@ __global__ __launch_bounds__(64) void k_item_early(const Item* items, int64_t n_
   }
 }
 
+// Slots of the rows of workgroup SCCs: each row's in-edges inside its SCC
+// cut into groups of up to eight, each group stored as eight 16-bit source
+// ids local to the SCC (two per word; the SCC's size pads a short group).
+// One 16-byte load gives a thread a whole slot.
+__global__ __launch_bounds__(256) void k_medium_slots(const Item* items, int64_t n_items, const int32_t* comp_vbeg,
+                                                      const uint32_t* int_ptr, const int32_t* int_src,
+                                                      const uint32_t* mslot_ptr, uint4* mslot_src) {
+  for (int64_t q = blockIdx.x; q < n_items; q += gridDim.x) {
+    const Item it = items[q];
+    if (it.kind != ITEM_MEDIUM) continue;
+    const int vb = comp_vbeg[it.a], ve = comp_vbeg[it.a + 1];
+    const uint32_t pad = (uint32_t)(ve - vb);
+    if (pad > 65535u) continue;
+    for (int v = vb + (int)threadIdx.x; v < ve; v += blockDim.x) {
+      const uint32_t e0 = int_ptr[v], e1 = int_ptr[v + 1];
+      uint32_t sl = mslot_ptr[v];
+      for (uint32_t e = e0; e < e1; e += 8, ++sl) {
+        uint32_t w[4];
+        for (int m = 0; m < 4; ++m) {
+          const uint32_t a0 = e + 2 * m < e1 ? (uint32_t)(int_src[e + 2 * m] - vb) : pad;
+          const uint32_t a1 = e + 2 * m + 1 < e1 ? (uint32_t)(int_src[e + 2 * m + 1] - vb) : pad;
+          w[m] = a0 | (a1 << 16);
+        }
+        mslot_src[sl] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+  }
+}
+
 int32_t make_schedule(Levels& lv, hipStream_t s) {
   PR_TRY(grid_for(lv.opts.rows_per_wave, &lv.grid, &lv.ggrid));
   lv.sgrid = std::max(lv.grid, lv.ggrid);
@@ -2237,9 +2333,11 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   // device copies
   void* old[] = {lv.items, lv.gangs, lv.gsccs, lv.gbounds, lv.gpart, lv.gpmx, lv.gwsum, lv.gdone, lv.wgstats,
                  lv.trace, lv.seg_heads, lv.ghubs, lv.gpieces, lv.gpiece_ptr, lv.gpiece_part, lv.ghub_pieces,
-                 lv.warm_buf, lv.warm_gws};
+                 lv.warm_buf, lv.warm_gws, lv.mslot_ptr, lv.mslot_src};
   for (void* q : old)
     if (q) (void)hipFree(q);
+  lv.mslot_ptr = nullptr;
+  lv.mslot_src = nullptr;
   lv.warm_buf = nullptr;  // sized by the schedule: allocated again on first use
   lv.warm_gws = nullptr;
   lv.items = nullptr;
@@ -2273,6 +2371,35 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
     PR_HIP_CHECK(hipGetLastError());
     k_item_early<<<ng, 64, 0, s>>>(lv.items, (int64_t)items.size(), lv.int_ptr, lv.int_src, lv.vpath);
     PR_HIP_CHECK(hipGetLastError());
+  }
+  {
+    // slot offsets of the rows of workgroup SCCs (every other row owns none)
+    std::vector<uint32_t> msp((size_t)lv.n + 1);
+    std::vector<std::pair<int32_t, int32_t>> med;
+    for (const Item& it : items)
+      if (it.kind == ITEM_MEDIUM) med.push_back({lv.h_comp_vbeg[it.a], lv.h_comp_vbeg[it.a + 1]});
+    std::sort(med.begin(), med.end());
+    uint64_t run = 0;
+    size_t mi = 0;
+    for (int64_t v = 0; v < lv.n; ++v) {
+      while (mi < med.size() && med[mi].second <= v) ++mi;
+      msp[v] = (uint32_t)run;
+      if (mi < med.size() && med[mi].first <= v && med[mi].second - med[mi].first <= 65535)
+        run += (lv.h_int_ptr[v + 1] - lv.h_int_ptr[v] + 7) / 8;
+    }
+    msp[lv.n] = (uint32_t)run;
+    if (run >= (1ull << 32)) {
+      set_error("too many SCC slots (%llu)", (unsigned long long)run);
+      return PR_EINVAL;
+    }
+    lv.n_mslots = (int64_t)run;
+    PR_TRY(upload(&lv.mslot_ptr, msp));
+    PR_TRY(dalloc(&lv.mslot_src, std::max<size_t>(run, 1)));
+    if (run > 0) {
+      k_medium_slots<<<(unsigned)std::min<size_t>(items.size(), 4096), 256, 0, s>>>(
+          lv.items, (int64_t)items.size(), lv.comp_vbeg, lv.int_ptr, lv.int_src, lv.mslot_ptr, lv.mslot_src);
+      PR_HIP_CHECK(hipGetLastError());
+    }
   }
   PR_TRY(upload(&lv.gangs, T.gangs));
   PR_TRY(upload(&lv.gsccs, T.sccs));
@@ -2326,6 +2453,8 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   lv.graph_exec = nullptr;
   lv.graph = nullptr;
   lv.graph_key = 0;
+  // the uploads above read host vectors that end with this function
+  PR_HIP_CHECK(hipStreamSynchronize(s));
   return PR_OK;
 }
 
@@ -2384,6 +2513,8 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.int_ptr = plain ? lv.full_ptr : lv.int_ptr;
   p.int_src = plain ? lv.full_src : lv.int_src;
   p.vpath = lv.vpath;
+  p.mslot_ptr = lv.mslot_ptr;
+  p.mslot_src = lv.mslot_src;
   p.inv32 = lv.inv_deg32;
   p.inv64 = lv.inv_deg64;
   p.x = lv.x;
