@@ -155,6 +155,8 @@ struct Levels {
   double* gpiece_part = nullptr;  // [n_pieces] piece sums of the current term
   std::vector<int32_t> h_gang_nhub;  // hubs per gang (host)
   std::vector<int32_t> h_gang_rank;  // component ranks of the componentwise gang SCCs (host)
+  std::vector<std::pair<int32_t, int32_t>> h_gang_sccs;  // per gang: its range in the GangScc table
+  std::vector<int64_t> h_gang_hint;  // per gang: most terms any solve of this plan needed (0: none yet)
   int64_t n_ghubs = 0, n_gpieces = 0;
   int32_t* gdone = nullptr;       // [n_gscc + 1] iterations when converged, -1 while running
   std::vector<uint32_t> h_int_ptr, h_full_ptr;

@@ -2328,7 +2328,12 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   lv.n_ghubs = (int64_t)T.hubs.size();
   lv.n_gpieces = (int64_t)T.pieces.size();
   lv.h_gang_nhub.clear();
-  for (const GangDesc& gd : T.gangs) lv.h_gang_nhub.push_back(gd.h1 - gd.h0);
+  lv.h_gang_sccs.clear();
+  for (const GangDesc& gd : T.gangs) {
+    lv.h_gang_nhub.push_back(gd.h1 - gd.h0);
+    lv.h_gang_sccs.push_back({gd.s0, gd.s1});
+  }
+  lv.h_gang_hint.assign(T.gangs.size(), 0);
   lv.phases = phases;
   // device copies
   void* old[] = {lv.items, lv.gangs, lv.gsccs, lv.gbounds, lv.gpart, lv.gpmx, lv.gwsum, lv.gdone, lv.wgstats,
@@ -2627,10 +2632,28 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     return PR_OK;
   };
   const WarmGangFn wk = pick_gang_warm(o.precision, lv.opts.rows_per_wave);
+  // A gang runs one launch per term up to a bound fixed before the solve
+  // (the launches after its SCCs stop return at once).  Once a solve of this
+  // plan has shown how many terms a gang needs, later solves launch that many
+  // plus a margin instead of the worst case; a solve whose gang reaches the
+  // shorter bound without its stop rule is run again with the worst case, so
+  // results never depend on the bound.
+  auto budget = [&](int gang) -> int64_t {
+    const int64_t h = lv.h_gang_hint[gang];
+    return h > 0 ? std::min(kb, h + std::max<int64_t>(4, h / 4)) : kb;
+  };
+  std::vector<int> gangs_run;
+  if (plain) {
+    gangs_run.push_back((int)lv.n_gangs);
+  } else {
+    for (const Phase& ph : lv.phases)
+      if (ph.kind == 1) gangs_run.push_back(ph.a);
+  }
   auto launch_gang = [&](int gang) -> int32_t {
     const int nh = lv.h_gang_nhub[gang];
-    for (int64_t k = 0; k <= kb + 1; ++k) {
-      const int fin = k == kb + 1 ? 1 : 0;
+    const int64_t kg = budget(gang);
+    for (int64_t k = 0; k <= kg + 1; ++k) {
+      const int fin = k == kg + 1 ? 1 : 0;
       hipLaunchKernelGGL(gk, dim3(lv.ggrid), dim3(kThreads), 0, s, p, gang, (int)k, fin);
       PR_TRY(mark(1));
       if (nh > 0 && !fin) {
@@ -2690,6 +2713,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     key = mix64(key, (uint64_t)(o.stop * 16 + o.precision * 4 + o.method));
     key = mix64(key, (uint64_t)(uintptr_t)p.mlp);
     key = mix64(key, (uint64_t)(uintptr_t)p.gmlp);
+    for (int gg : gangs_run) key = mix64(key, (uint64_t)budget(gg));
     if (!lv.graph_exec || lv.graph_key != key) {
       if (lv.graph_exec) (void)hipGraphExecDestroy(lv.graph_exec);
       if (lv.graph) (void)hipGraphDestroy(lv.graph);
@@ -2741,6 +2765,24 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   if (cnt[C_ERROR]) {
     set_error("internal: a dependency wait timed out (flags %llu)", cnt[C_ERROR]);
     return PR_EHIP;
+  }
+  if (!gangs_run.empty()) {
+    // terms each gang needed; a gang cut by a shortened bound is run again
+    std::vector<int32_t> gd((size_t)std::max<int64_t>(lv.n_gscc, 1));
+    PR_HIP_CHECK(hipMemcpy(gd.data(), lv.gdone, sizeof(int32_t) * gd.size(), hipMemcpyDeviceToHost));
+    bool cut = false;
+    for (int gg : gangs_run) {
+      int64_t need = 0;
+      for (int32_t si = lv.h_gang_sccs[gg].first; si < lv.h_gang_sccs[gg].second; ++si)
+        need = std::max<int64_t>(need, gd[si]);
+      if (budget(gg) < kb && need >= budget(gg)) {
+        lv.h_gang_hint[gg] = 0;
+        cut = true;
+      } else {
+        lv.h_gang_hint[gg] = std::max(lv.h_gang_hint[gg], need);
+      }
+    }
+    if (cut) return solve_levels(lv, c, W, R, o, s, st);
   }
   local.edge_iters = (int64_t)cnt[S_EDGE_ITERS] + (plain ? 0 : (lv.info.m_between + lv.info.m_cac_internal));
   local.iters_max = (int64_t)cnt[S_ITERS_MAX];
