@@ -31,7 +31,8 @@ from .partition import partition_theorem
 
 
 def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e-6,
-                        tol=None, max_iter=1_000_000, return_stats=False, warm=None, warm_fn=None):
+                        tol=None, max_iter=1_000_000, return_stats=False, warm=None, warm_fn=None,
+                        direct_max=0):
     """Componentwise R^(3).
 
     Stop rule per SCC C (one term added per iteration, k >= 1):
@@ -47,6 +48,11 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
     network (F: feature rows of the vertices Vs, s: their component scale),
     e.g. to plant a perfect or a useless guess.  The stats then also hold, per component, the accept flag
     (1 kept, 0 fell back, -1 not an SCC).
+
+    direct_max: SCCs of at most this many vertices are solved directly,
+    (I - c A_CC^T) R_C = W'_C with a dense LAPACK solve: the paper's choice
+    for small SCCs in the per-component method dispatch of Sec. 4.3 (zero
+    iterations, zero last-term norm).
     """
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
@@ -98,8 +104,14 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
         cac_mask = (ctype[cV] == 0) & ~single
         if np.any(cac_mask):
             _cac_sweep(V[cac_mask], Wp[cac_mask], comp, c, deg, nbr_ptr, nbr, R)
-        # SCCs: power series per component
+        # SCCs: small ones solved directly when asked, the rest by the power
+        # series per component
         scc_mask = ctype[cV] == 1
+        if direct_max > 0:
+            dmask = scc_mask & (csize[cV] <= direct_max)
+            if np.any(dmask):
+                _scc_direct(V[dmask], Wp[dmask], comp, c, AT, R)
+            scc_mask = scc_mask & ~dmask
         if np.any(scc_mask):
             Vs = V[scc_mask]
             _scc_series(Vs, Wp[scc_mask], comp, c, AT, R, iters, last, stop, eps, tol, max_iter, feat)
@@ -141,6 +153,17 @@ def _cac_sweep(Vc, Wp, comp, c, deg, nbr_ptr, nbr, R):
                 degree[j] -= 1  # never enqueued again
     assert np.all(degree == -1), "CAC sweep left vertices unvisited (cycle?)"
     R[Vc] = rank
+
+
+def _scc_direct(Vd, Wp, comp, c, AT, R):
+    """Each SCC C among the vertices Vd: R_C = (I - c A_CC^T)^{-1} W'_C, the
+    definition (Def. 3.4/3.5) restricted to C, by one dense solve."""
+    cid = comp[Vd]
+    for C in np.unique(cid):
+        m = cid == C
+        idx = Vd[m]
+        M = np.eye(len(idx)) - c * AT[idx, :][:, idx].toarray()
+        R[idx] = np.linalg.solve(M, Wp[m])
 
 
 def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter, feat=None):

@@ -242,3 +242,71 @@ def test_residual_bound_covers_the_error():
         assert bound < 50 * err  # and it is not vacuous on these perturbations
     bound, _ = residual_bound(g.n, g.row_ptr, g.col, c, W, exact)
     assert bound < 1e-13
+
+
+# ------------------------------------------- direct solve of small SCCs
+
+@pytest.mark.parametrize("m", [2, 5, 9])
+def test_direct_small_scc_cycle_closed_form(m):
+    """A bare m-cycle with W = 1 has R = 1/(1-c) on every vertex, exactly:
+    the direct route must hit it to rounding, with no series term counted."""
+    g = _g(m, [(i, (i + 1) % m) for i in range(m)])
+    R, st = CW.componentwise_solve(g.n, g.row_ptr, g.col, C, np.ones(m), eps=1e-3, direct_max=m,
+                                   return_stats=True)
+    assert np.allclose(R, 1.0 / (1.0 - C), rtol=1e-14, atol=0)
+    assert st["iters"].max() == 0
+    # the series at eps 1e-3 is visibly off, so the test does tell the routes apart
+    Ri = CW.componentwise_solve(g.n, g.row_ptr, g.col, C, np.ones(m), eps=1e-3)
+    assert not np.allclose(Ri, 1.0 / (1.0 - C), rtol=1e-6, atol=0)
+
+
+def _blocks_graph(seed, nblocks=30):
+    """SCC blocks of 2-24 vertices (a cycle plus chords), forward links
+    between blocks and a few dangling tails: many small SCCs on several
+    levels."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(2, 25, nblocks)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    src, dst = [], []
+    for b in range(nblocks):
+        v = np.arange(starts[b], starts[b + 1])
+        src += list(v)
+        dst += list(np.roll(v, -1))
+        for _ in range(len(v)):
+            src.append(rng.choice(v))
+            dst.append(rng.choice(v))
+    n0 = int(starts[-1])
+    for _ in range(2 * nblocks):
+        a, b = sorted(rng.choice(nblocks, 2, replace=False))
+        src.append(rng.integers(starts[a], starts[a + 1]))
+        dst.append(rng.integers(starts[b], starts[b + 1]))
+    tails = np.arange(n0, n0 + 20)
+    for t in tails:
+        src.append(rng.integers(0, n0))
+        dst.append(t)
+    return csr_from_edges(n0 + 20, np.array(src), np.array(dst)), sizes
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_direct_small_sccs_equal_dense(seed):
+    """Many small SCCs on several levels: direct solves of every SCC up to
+    16 vertices plus the series on the larger ones equal the whole-graph
+    LAPACK solve (an independent route) to rounding."""
+    g, sizes = _blocks_graph(seed)
+    W = np.random.default_rng(seed).uniform(0.5, 1.5, g.n)
+    Rd = PR.pagerank_dense(g.n, g.row_ptr, g.col, C, W)
+    R, st = CW.componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=1e-14, direct_max=16, return_stats=True)
+    assert np.allclose(R, Rd, rtol=1e-11, atol=0)
+    part = CW.partition_theorem(g.n, g.row_ptr, g.col)
+    small = (part["comp_type"] == 1) & (part["comp_size"] <= 16)
+    assert small.sum() >= 5 and np.all(st["iters"][small] == 0)
+    assert np.all(st["iters"][(part["comp_type"] == 1) & ~small] > 0)
+
+
+def test_direct_planted_sign_mistake_is_caught():
+    """(I + cA^T) in place of (I - cA^T) must break the cycle closed form."""
+    m = 4
+    g = _g(m, [(i, (i + 1) % m) for i in range(m)])
+    AT = PR.transition_dense(m, g.row_ptr, g.col).T
+    wrong = np.linalg.solve(np.eye(m) + C * AT, np.ones(m))
+    assert not np.allclose(wrong, 1.0 / (1.0 - C), rtol=1e-6)
