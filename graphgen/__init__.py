@@ -7,6 +7,7 @@ from .generators import (  # noqa: F401
     Graph,
     csr_from_edges,
     random_digraph,
+    scc_blocks,
     small_plain,
     web_like,
     config_graph,

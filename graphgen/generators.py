@@ -78,6 +78,34 @@ def random_digraph(n: int, m: int, seed: int, *, loops: bool = False,
 # helpers
 # ---------------------------------------------------------------------------
 
+def scc_blocks(seed: int, nblocks: int = 30, min_size: int = 2, max_size: int = 24, tails: int = 20) -> "Graph":
+    """SCC blocks of min_size..max_size vertices (a Hamiltonian cycle plus as
+    many random chords), two forward links per block between random pairs of
+    blocks (so the blocks sit on several levels), and `tails` one-vertex
+    sinks fed from random block vertices.  Many small SCCs: the case of the
+    direct small-SCC solve."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(min_size, max_size + 1, nblocks)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    src, dst = [], []
+    for b in range(nblocks):
+        v = np.arange(starts[b], starts[b + 1])
+        src += list(v)
+        dst += list(np.roll(v, -1))
+        for _ in range(len(v)):
+            src.append(rng.choice(v))
+            dst.append(rng.choice(v))
+    n0 = int(starts[-1])
+    for _ in range(2 * nblocks):
+        a, b = sorted(rng.choice(nblocks, 2, replace=False))
+        src.append(rng.integers(starts[a], starts[a + 1]))
+        dst.append(rng.integers(starts[b], starts[b + 1]))
+    for t in range(n0, n0 + tails):
+        src.append(rng.integers(0, n0))
+        dst.append(t)
+    return csr_from_edges(n0 + tails, np.array(src), np.array(dst))
+
+
 def _zipf_truncated(rng, size, a, dmax):
     k = np.arange(1, dmax + 1, dtype=np.float64)
     cdf = np.cumsum(k ** (-a))

@@ -177,7 +177,13 @@ typedef struct pr_solve_opts {
   int32_t warm_scope;   /* with warm_start: 0 = only the SCCs iterated in gang phases (the large
                            ones, where the guess's two extra passes cost less than the terms it
                            saves), 1 = every SCC */
-  int32_t reserved[5];
+  int32_t small_direct; /* SCCs of at most this many vertices (0..24; default 0 = none) that are
+                           iterated by one wavefront are solved directly instead: (I - cA_CC^T)R_C
+                           = W'_C by FP64 Gauss-Jordan elimination in LDS without pivoting (the
+                           matrix is column diagonally dominant), the paper's choice for small
+                           SCCs in the per-component method dispatch of Sec. 4.3.  Such an SCC
+                           counts zero terms; its FP64 residual enters the certificate. */
+  int32_t reserved[4];
 } pr_solve_opts;
 
 void pr_default_solve_opts(pr_solve_opts* o);

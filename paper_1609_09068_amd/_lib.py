@@ -37,7 +37,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("stop", C.c_int32), ("precision", C.c_int32),
                 ("use_graph", C.c_int32), ("eps", C.c_double), ("tol", C.c_double),
                 ("max_iter", C.c_int64), ("warm_start", C.c_void_p), ("trace", C.c_int32),
-                ("kernel_timing", C.c_int32), ("warm_scope", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("kernel_timing", C.c_int32), ("warm_scope", C.c_int32), ("small_direct", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class SolveStats(C.Structure):

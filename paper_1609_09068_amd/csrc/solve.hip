@@ -49,6 +49,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kSmallMax = 256;  // rows of a wavefront-resident SCC
+constexpr int kDirectMax = 24;  // largest SCC solved directly: 24 x 25 doubles fit a wavefront's tile
 
 // per-workgroup counters (LDS during a kernel, accumulated in global memory
 // across the launches of a solve); the last ones are wall-clock ticks
@@ -63,6 +64,7 @@ struct SolveParams {
   int32_t stop;
   int32_t plain;
   int32_t n_items;  // items of the segment being run
+  int32_t direct_max;  // SCCs of a wavefront with at most this many vertices are solved directly
   double c, eps, tol;
   int64_t max_iter;
   const double* W;
@@ -936,7 +938,55 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
   bool conv = true;
   bool skip = p.stop == PR_STOP_CERT_L1 && wsum == 0.0;
   int ws = -1;
-  if (WARM && !skip) {
+  if (nv <= p.direct_max && nv <= kDirectMax && !skip) {
+    // Direct solve (Sec. 4.3, small SCCs): Gauss-Jordan elimination of
+    // [I - c A_CC^T | W'] in LDS, in FP64, without pivoting; every column of
+    // I - c A_CC^T has diagonal 1 and off-diagonal sum at most c < 1, so the
+    // pivots stay at least 1 - c.  The matrix takes the tile (its staged
+    // rows are not needed on this path).
+    double* M = reinterpret_cast<double*>(tile->buf);
+    const int ld = nv + 1;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int q = lane; q < nv * ld; q += 64) M[q] = 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const double wp = Rj[0];
+    if (lane < nv) {
+      M[lane * ld + lane] = 1.0;
+      M[lane * ld + nv] = wp;
+      for (uint32_t e = rlo[0]; e < rhi[0]; ++e) {
+        const int u = p.int_src[e] - vbeg;
+        M[lane * ld + u] -= p.c * p.inv64[vbeg + u];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int kk = 0; kk < nv; ++kk) {
+      const double inv_piv = 1.0 / M[kk * ld + kk];
+      const int cols = nv - kk;  // columns kk+1 .. nv
+      for (int q = lane; q < nv * cols; q += 64) {
+        const int i = q / cols, j = kk + 1 + q % cols;
+        if (i != kk) M[i * ld + j] -= (M[i * ld + kk] * inv_piv) * M[kk * ld + j];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    const double xr = lane < nv ? M[lane * ld + nv] / M[lane * ld + lane] : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane < nv) M[lane * ld + nv] = xr;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // residual W' - (I - c A_CC^T) R in FP64: ||R - R*||_1 <= ||r||_1 / (1 - c)
+    double rr = 0.0;
+    if (lane < nv) {
+      double acc = wp - xr;
+      for (uint32_t e = rlo[0]; e < rhi[0]; ++e) {
+        const int u = p.int_src[e] - vbeg;
+        acc += p.c * p.inv64[vbeg + u] * M[u * ld + nv];
+      }
+      rr = fabs(acc);
+    }
+    rr = wave_sum(rr);
+    Rj[0] = xr;
+    last = rr / p.c;  // the certificate adds c / (1 - c) * last
+    skip = true;
+  } else if (WARM && !skip) {
     const WarmOut w = warm_preamble<64>(p, vbeg, nv, wsum, nullptr);
     ws = w.keep ? 1 : 0;
     if (w.keep) {  // start from R_0 + r_0 with the term r_0
@@ -1450,6 +1500,8 @@ __device__ inline void flush_stats(const SolveParams& p, unsigned long long* s_s
 // LDS of the segment kernel: four wavefront tiles followed by the small-SCC
 // term vectors; a single-workgroup SCC may reuse all of it once its weights
 // are gathered, and a vertex item keeps its local x values in the second part.
+static_assert(kDirectMax * (kDirectMax + 1) * sizeof(double) <= 512 * sizeof(double) + 64 * (sizeof(double) + 8),
+              "direct-solve matrix fits the tile");
 constexpr size_t kSegLds = 53 * 1024;  // three workgroups per CU (the VGPR limit too)
 static_assert(kWaves * sizeof(WaveTile) + kWaves * 2 * kSmallMax * sizeof(double) <= kSegLds, "segment LDS");
 static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + kThreads * sizeof(uint4) +
@@ -2518,6 +2570,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.int_ptr = plain ? lv.full_ptr : lv.int_ptr;
   p.int_src = plain ? lv.full_src : lv.int_src;
   p.vpath = lv.vpath;
+  p.direct_max = plain ? 0 : o.small_direct;
   p.mslot_ptr = lv.mslot_ptr;
   p.mslot_src = lv.mslot_src;
   p.inv32 = lv.inv_deg32;
@@ -2711,6 +2764,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     key = mix64(key, (uint64_t)o.max_iter);
     key = mix64(key, (uint64_t)kb);
     key = mix64(key, (uint64_t)(o.stop * 16 + o.precision * 4 + o.method));
+    key = mix64(key, (uint64_t)o.small_direct);
     key = mix64(key, (uint64_t)(uintptr_t)p.mlp);
     key = mix64(key, (uint64_t)(uintptr_t)p.gmlp);
     for (int gg : gangs_run) key = mix64(key, (uint64_t)budget(gg));

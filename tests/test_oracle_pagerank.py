@@ -7,7 +7,7 @@ import pytest
 from hypothesis import HealthCheck, given, settings
 from hypothesis import strategies as st
 
-from graphgen import config_graph, csr_from_edges, random_digraph
+from graphgen import config_graph, csr_from_edges, random_digraph, scc_blocks
 from oracle import componentwise as CW
 from oracle import pagerank as PR
 
@@ -260,39 +260,12 @@ def test_direct_small_scc_cycle_closed_form(m):
     assert not np.allclose(Ri, 1.0 / (1.0 - C), rtol=1e-6, atol=0)
 
 
-def _blocks_graph(seed, nblocks=30):
-    """SCC blocks of 2-24 vertices (a cycle plus chords), forward links
-    between blocks and a few dangling tails: many small SCCs on several
-    levels."""
-    rng = np.random.default_rng(seed)
-    sizes = rng.integers(2, 25, nblocks)
-    starts = np.concatenate([[0], np.cumsum(sizes)])
-    src, dst = [], []
-    for b in range(nblocks):
-        v = np.arange(starts[b], starts[b + 1])
-        src += list(v)
-        dst += list(np.roll(v, -1))
-        for _ in range(len(v)):
-            src.append(rng.choice(v))
-            dst.append(rng.choice(v))
-    n0 = int(starts[-1])
-    for _ in range(2 * nblocks):
-        a, b = sorted(rng.choice(nblocks, 2, replace=False))
-        src.append(rng.integers(starts[a], starts[a + 1]))
-        dst.append(rng.integers(starts[b], starts[b + 1]))
-    tails = np.arange(n0, n0 + 20)
-    for t in tails:
-        src.append(rng.integers(0, n0))
-        dst.append(t)
-    return csr_from_edges(n0 + 20, np.array(src), np.array(dst)), sizes
-
-
 @pytest.mark.parametrize("seed", range(5))
 def test_direct_small_sccs_equal_dense(seed):
     """Many small SCCs on several levels: direct solves of every SCC up to
     16 vertices plus the series on the larger ones equal the whole-graph
     LAPACK solve (an independent route) to rounding."""
-    g, sizes = _blocks_graph(seed)
+    g = scc_blocks(seed)
     W = np.random.default_rng(seed).uniform(0.5, 1.5, g.n)
     Rd = PR.pagerank_dense(g.n, g.row_ptr, g.col, C, W)
     R, st = CW.componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=1e-14, direct_max=16, return_stats=True)
