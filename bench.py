@@ -217,6 +217,38 @@ def run_study(args, pr, torch, g, lv, info, W, R, t_part, t_build):
                       "rows": rows, "device": torch.cuda.get_device_name(0)}), flush=True)
 
 
+def run_tol_sweep(args, pr, torch, g, lv, info, W, R, t_part, t_build):
+    """Time to solve against the tolerance (the experiment of Sec. 5.2 and
+    the B-A figure): componentwise and plain at eps 1e-2 ... 1e-10, hipGraph
+    replays, with each result's error bound from the oracle's FP64 residual."""
+    rows = []
+    AT = None
+    for eps in (1e-2, 1e-4, 1e-6, 1e-8, 1e-10):
+        for meth, direct in ((0, 0), (0, 24), (1, 0)):
+            prec = 0 if eps >= 1e-6 else 1  # FP32 terms cannot certify below about 1e-7
+            for _ in range(2):
+                pr.pr_solve(lv, args.c, W, R, method=meth, precision=prec, eps=eps, use_graph=1, small_direct=direct)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                rc, st = pr.pr_solve(lv, args.c, W, R, method=meth, precision=prec, eps=eps, use_graph=1,
+                                     small_direct=direct)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / args.steps * 1e3
+            bound, AT = residual_bound(g, args.c, R.cpu().numpy(), AT)
+            name = "plain" if meth == 1 else ("componentwise" + ("+small_direct" if direct else ""))
+            row = {"eps": eps, "method": name,
+                   "precision": "mixed" if prec == 0 else "fp64", "ms": round(ms, 3),
+                   "terms_max": st["iters_max"], "edge_iters": st["edge_iters"], "cert_rel": st["cert_rel"],
+                   "rel_l1_bound_vs_oracle_residual": bound}
+            log(json.dumps(row))
+            rows.append(row)
+    print(json.dumps({"study": "tolerance", "config": args.config, "n": g.n, "m": g.m,
+                      "levels": info["n_levels"], "scc_vertices": info["v_scc"],
+                      "partition_ms": round(t_part * 1e3, 1), "build_ms": round(t_build * 1e3, 1),
+                      "rows": rows, "device": torch.cuda.get_device_name(0)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +266,9 @@ def main():
                          "reference up to 20M edges")
     ap.add_argument("--study", action="store_true",
                     help="precision study: c in {0.85, 0.99} x {mixed, fp64} x {componentwise, plain}; prints one "
+                         "JSON line of its own instead of the benchmark line")
+    ap.add_argument("--tol-sweep", action="store_true",
+                    help="time against the tolerance (eps 1e-2 ... 1e-10), componentwise and plain; prints one "
                          "JSON line of its own instead of the benchmark line")
     ap.add_argument("--graph", type=int, default=1,
                     help="time hipGraph replays of the solve (1, default) or eager launches (0); the per-kernel "
@@ -304,6 +339,9 @@ def main():
     Rp = torch.empty_like(W)
     if args.study:
         run_study(args, pr, torch, g, lv, info, W, R, t_part, t_build)
+        return
+    if args.tol_sweep:
+        run_tol_sweep(args, pr, torch, g, lv, info, W, R, t_part, t_build)
         return
     common = dict(eps=args.eps, precision=args.precision, use_graph=args.graph, kernel_timing=0)
 
@@ -449,7 +487,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == 0 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: web-like graph n={g.n} m={g.m}, c={args.c}, "
+        "config": {"workload": f"{args.config}: {'Barabasi-Albert' if 'ba_' in args.config else 'web-like'} "
+                               f"graph n={g.n} m={g.m}, c={args.c}, "
                                f"1-norm certificate eps={args.eps}, W=1, componentwise solve"
                                f"{' with the learned starting guess' if net is not None else ''}, plan resident",
                    "n": g.n, "m": g.m, "levels": info["n_levels"], "components": info["n_comp"],

@@ -5,6 +5,7 @@ partition arithmetic.  Both the oracle and the GPU path consume its output.
 """
 from .generators import (  # noqa: F401
     Graph,
+    barabasi_albert,
     csr_from_edges,
     random_digraph,
     scc_blocks,

@@ -106,6 +106,75 @@ def scc_blocks(seed: int, nblocks: int = 30, min_size: int = 2, max_size: int = 
     return csr_from_edges(n0 + tails, np.array(src), np.array(dst))
 
 
+def barabasi_albert(n: int, m: int, seed: int, *, m0: int = 20, seed_degree: float = 5.0,
+                    batch_frac: float = 0.01, log=None) -> "Graph":
+    """Barabasi-Albert growth, then each vertex keeps ceil(log2 d) of its d
+    incident edges as out-edges (the recipe of the paper's B-A experiments,
+    Sec. 5.1 and the B-A generation subsection).
+
+    Seed: m0 vertices with uniformly random undirected edges of mean degree
+    seed_degree.  Growth: every new vertex joins m distinct existing vertices
+    drawn with probability proportional to their degree.  Vertices are added
+    in batches of batch_frac of the current size that all draw from the
+    degrees at the start of the batch (the exact one-at-a-time process, up to
+    that lag).  Thinning: vertex i that created E_i edges (m for a grown
+    vertex, its seed edges for a seed vertex) keeps ceil(log2 E_i) of its
+    incident edges, chosen uniformly among all of them, as edges i ->
+    neighbour; an edge kept from both ends becomes a 2-cycle.  With m = 2 the
+    result has about one edge per vertex, with m = 24 about five.  (The
+    paper's text leaves open which edges count as originating from a vertex;
+    this reading gives its B-A statistics' shape: about one edge per vertex,
+    a large CAC, many 2-vertex SCCs.)"""
+    rng = np.random.default_rng(seed)
+    n_seed_edges = int(round(m0 * seed_degree / 2))
+    a = rng.integers(0, m0, n_seed_edges)
+    b = rng.integers(0, m0, n_seed_edges)
+    keep = a != b
+    eu, ev = [a[keep]], [b[keep]]
+    ends = np.concatenate([a[keep], b[keep]])  # every edge end once: degree-proportional draws
+    pool = [ends]
+    pool_len = len(ends)
+    v = m0
+    while v < n:
+        bs = max(1, min(n - v, int(batch_frac * v)))
+        flat = np.concatenate(pool) if len(pool) > 1 else pool[0]
+        pool = [flat]
+        new = np.arange(v, v + bs)
+        t = flat[rng.integers(0, pool_len, (bs, m))]
+        # distinct targets per vertex: redraw duplicates uniformly among the
+        # older vertices (rare once the graph has grown)
+        t.sort(axis=1)
+        dup = np.zeros_like(t, dtype=bool)
+        dup[:, 1:] = t[:, 1:] == t[:, :-1]
+        if dup.any():
+            t[dup] = rng.integers(0, v, int(dup.sum()))
+        src = np.repeat(new, m)
+        dst = t.ravel()
+        eu.append(src)
+        ev.append(dst)
+        pool.append(np.concatenate([src, dst]))
+        pool_len += 2 * len(src)
+        v += bs
+    eu = np.concatenate(eu)
+    ev = np.concatenate(ev)
+    if log:
+        log(f"barabasi_albert: grown {n} vertices, {len(eu)} undirected edges")
+    created = np.bincount(eu, minlength=n)
+    # incident edges per vertex (both ends), then ceil(log2 E_i) kept per vertex
+    ends_v = np.concatenate([eu, ev])
+    other = np.concatenate([ev, eu])
+    order = np.lexsort((rng.random(len(ends_v)), ends_v))  # random order within each vertex
+    ends_v, other = ends_v[order], other[order]
+    deg = np.bincount(ends_v, minlength=n)
+    first = np.concatenate([[0], np.cumsum(deg)[:-1]])
+    rank = np.arange(len(ends_v)) - first[ends_v]
+    kept = np.minimum(np.ceil(np.log2(np.maximum(created, 1))).astype(np.int64), deg)
+    sel = rank < kept[ends_v]
+    g = csr_from_edges(n, ends_v[sel], other[sel])
+    g.meta.update(dict(kind="barabasi_albert", m=m, m0=m0, seed=seed))
+    return g
+
+
 def _zipf_truncated(rng, size, a, dmax):
     k = np.arange(1, dmax + 1, dtype=np.float64)
     cdf = np.cumsum(k ** (-a))
@@ -453,6 +522,9 @@ CONFIGS = {
     "c5_web_20m": dict(kind="web_like", n=20_000_000, m=200_000_000, seed=5001,
                        giant_frac=0.50, cac_frac=0.25, dangling_frac=0.08, zipf_a=2.1,
                        n_levels=60, scc_median=12, cac_median=8),
+    # the B-A workloads: about one and about five edges per vertex
+    "ba_1m_e1": dict(kind="barabasi_albert", n=1_000_000, m=2, seed=6001),
+    "ba_1m_e5": dict(kind="barabasi_albert", n=1_000_000, m=24, seed=6002),
 }
 
 
@@ -465,6 +537,8 @@ def config_graph(name: str, seed: int | None = None, **override) -> Graph:
         s = seed
     if kind == "small_plain":
         g = small_plain(seed=s, **cfg)
+    elif kind == "barabasi_albert":
+        g = barabasi_albert(cfg.pop("n"), cfg.pop("m"), s, **cfg)
     else:
         n = cfg.pop("n")
         m = cfg.pop("m")
