@@ -86,6 +86,7 @@ struct SolveParams {
   double* wr0;   // [n] R_0 of the guess
   double* wx;    // [n] c R_0 / outdeg
   double* wres;  // [n] r_0 = W' + c A^T R_0 - R_0
+  float4* wfeat; // [n] gang SCC rows: the four features of the guess
   // starting guess of gang SCCs: per-workgroup partial norms of the first
   // plain term, of r_0 and max |r_0| (slot layout of gpart), then per SCC
   // the decision (1 kept, 0 not, -1 none), ||r_0||_1 and max |r_0|
@@ -1716,7 +1717,6 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
           p.wprime[v] = wp;
           if constexpr (sizeof(YT) == 8) yw[v] = c * wp * p.inv64[v];
           else yw[v] = (YT)(c * wp * (double)p.inv32[v]);
-          if (p.gmlp) p.wx[v] = c * wp * p.inv64[v];
           part += wp;
         }
       }
@@ -1877,25 +1877,23 @@ __global__ __launch_bounds__(kThreads) void k_gang_warm(SolveParams p, int gang,
       double np1 = 0.0;
       for (int ra = w0; ra < w1; ra += 64) {
         const int nr = w1 - ra < 64 ? w1 - ra : 64;
-        const double p1 = wave_tile_gather<RPW, double, false>(p, ptr, p.int_src, p.wx, ra, nr, &s_tile[wave]);
+        // the first plain term, gathered from term 0 (c W' / outdeg, written by
+        // launch k = 0 in the precision of the terms); the features are FP32
+        const double p1 = (double)wave_tile_gather<RPW, YT, false>(p, ptr, p.int_src, (const YT*)p.y0, ra, nr,
+                                                                   &s_tile[wave]);
         const int v = ra + lane;
         const bool act = lane < nr && sC > 0.0;
         float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
         if (act) {
           const double wpv = p.wprime[v];
           np1 += fabs(p1);
-          const double indeg = (double)((p.bnd_ptr[v + 1] - p.bnd_ptr[v]) + (ptr[v + 1] - ptr[v]));
-          f0 = (float)log1p(indeg);
-          f1 = (float)log1p(rint(1.0 / p.inv64[v]));
-          f2 = (float)log1p((wpv - p.W[p.perm[v]]) / sC);
-          f3 = (float)log1p((wpv + p1) / sC);
+          const uint32_t indeg = (p.bnd_ptr[v + 1] - p.bnd_ptr[v]) + (ptr[v + 1] - ptr[v]);
+          f0 = log1pf((float)indeg);
+          f1 = log1pf(rintf(1.0f / p.inv32[v]));
+          f2 = log1pf((float)((wpv - p.W[p.perm[v]]) / sC));
+          f3 = log1pf((float)((wpv + p1) / sC));
         }
-        const float y = mlp_forward64(*p.gmlp, f0, f1, f2, f3);
-        if (lane < nr) {
-          const double r0 = act ? sC * exp((double)y) : 0.0;
-          p.wr0[v] = r0;
-          p.wres[v] = c * r0 * p.inv64[v];
-        }
+        if (lane < nr) p.wfeat[v] = make_float4(f0, f1, f2, f3);
       }
       np1 = block_sum(np1, s_red);
       if (threadIdx.x == 0) p.gwp1[slot] = np1;
@@ -1940,6 +1938,36 @@ __global__ __launch_bounds__(kThreads) void k_gang_warm(SolveParams p, int gang,
         p.gws[si] = keep ? 1 : 0;
         p.gwn[si] = nr0;
         p.gwm[si] = mr0;
+      }
+    }
+  }
+}
+
+// The network of the gang SCCs' starting guess, between steps 0 and 1 of
+// k_gang_warm: R_0 = s_C exp(y) from the features step 0 stored, and
+// c R_0 / outdeg for the residual.  A kernel of its own: without the gather
+// and its tiles it keeps few registers, so many wavefronts share each SIMD
+// while the network's matrix-core and GELU work runs.
+__global__ __launch_bounds__(kThreads) void k_gang_warm_net(SolveParams p, int gang) {
+  __shared__ double s_red[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const GangDesc gd = p.gangs[gang];
+  const GangCtx g = gang_ctx(p, gd);
+  for (int si = g.s_lo; si < g.s_hi; ++si) {
+    const GangScc sc = p.gscc[si];
+    const int a = sc.vbeg > g.r0 ? sc.vbeg : g.r0, z = sc.vend < g.r1 ? sc.vend : g.r1;
+    double tot, mx;
+    gang_total(p, sc, 0, s_red, &tot, &mx);  // ||W'_C||_1 from term 0's partials
+    const double sC = tot / (double)(sc.vend - sc.vbeg);
+    for (int ra = a + 64 * wave; ra < z; ra += kThreads) {  // wave-uniform trip count
+      const int v = ra + lane;
+      const bool act = v < z && sC > 0.0;
+      const float4 f = act ? p.wfeat[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float y = mlp_forward64(*p.gmlp, f.x, f.y, f.z, f.w);
+      if (v < z) {
+        const double r0 = act ? sC * exp((double)y) : 0.0;
+        p.wr0[v] = r0;
+        p.wres[v] = p.c * r0 * p.inv64[v];
       }
     }
   }
@@ -2537,6 +2565,13 @@ static int64_t term_bound(const pr_solve_opts& o, double c, double sumW) {
   return (int64_t)k;
 }
 
+// the features of the guess (float4 per vertex) follow the other scratch of
+// warm_buf, on a 16-byte boundary
+static size_t warm_feat_off(const Levels& lv) {
+  const size_t off = 3 * (size_t)lv.n + 3 * (size_t)lv.n_gslots + 2 * (size_t)lv.n_gscc;
+  return (off + 1) & ~(size_t)1;
+}
+
 int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_solve_opts& o,
                      hipStream_t s, pr_solve_stats* st) {
   int dev;
@@ -2606,7 +2641,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
       return PR_EINVAL;
     }
     if (!lv.warm_buf) {
-      PR_TRY(dalloc(&lv.warm_buf, 3 * (size_t)lv.n + 3 * (size_t)lv.n_gslots + 2 * (size_t)lv.n_gscc));
+      PR_TRY(dalloc(&lv.warm_buf, warm_feat_off(lv) + 2 * (size_t)lv.n));
       PR_TRY(dalloc(&lv.warm_gws, std::max<int64_t>(lv.n_gscc, 1)));
     }
     p.gmlp = m->packed;
@@ -2620,6 +2655,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     p.gwn = p.gwm0 + lv.n_gslots;
     p.gwm = p.gwn + lv.n_gscc;
     p.gws = lv.warm_gws;
+    p.wfeat = reinterpret_cast<float4*>(lv.warm_buf + warm_feat_off(lv));
   }
   if (o.trace == 1) {  // timeline of the segment items (tests / profiling)
     if (!lv.trace) {
@@ -2717,6 +2753,10 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
         for (int step = 0; step < 3; ++step) {
           hipLaunchKernelGGL(wk, dim3(lv.ggrid), dim3(kThreads), 0, s, p, gang, step);
           PR_TRY(mark(1));
+          if (step == 0) {
+            hipLaunchKernelGGL(k_gang_warm_net, dim3(lv.ggrid), dim3(kThreads), 0, s, p, gang);
+            PR_TRY(mark(1));
+          }
         }
       }
     }
