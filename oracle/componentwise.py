@@ -32,7 +32,7 @@ from .partition import partition_theorem
 
 def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e-6,
                         tol=None, max_iter=1_000_000, return_stats=False, warm=None, warm_fn=None,
-                        direct_max=0):
+                        direct_max=0, loops=False):
     """Componentwise R^(3).
 
     Stop rule per SCC C (one term added per iteration, k >= 1):
@@ -49,6 +49,13 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
     e.g. to plant a perfect or a useless guess.  The stats then also hold, per component, the accept flag
     (1 kept, 0 fell back, -1 not an SCC).
 
+    loops: keep self-loops in A (the general definition; the partition does
+    not change, a loop being a cycle of one vertex only).  A one-vertex
+    component then has R_v = W'_v / (1 - c a_vv), and in the CAC sweep a
+    vertex's collected rank is divided by (1 - c a_vv) before it is passed
+    on (the loop's own share comes back to it); SCC series use A_CC with its
+    diagonal.
+
     direct_max: SCCs of at most this many vertices are solved directly,
     (I - c A_CC^T) R_C = W'_C with a dense LAPACK solve: the paper's choice
     for small SCCs in the per-component method dispatch of Sec. 4.3 (zero
@@ -64,8 +71,9 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
     ctype = part["comp_type"]
     csize = part["comp_size"].astype(np.int64)
     vlevel = clevel[comp]
-    AT = transition_T_csr(n, row_ptr, col)
-    deg = out_degree(n, row_ptr, col)
+    AT = transition_T_csr(n, row_ptr, col, loops)
+    deg = out_degree(n, row_ptr, col, loops)
+    a_diag = AT.diagonal() if loops else np.zeros(n)
     nbr_ptr, nbr = row_ptr, col  # out-edges for the CAC sweep
     R = np.zeros(n, dtype=np.float64)
     iters = np.zeros(len(csize), dtype=np.int64)
@@ -99,11 +107,11 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
         R[V] = 0.0
         cV = comp[V]
         single = (csize[cV] == 1)
-        R[V[single]] = Wp[single]
+        R[V[single]] = Wp[single] / (1.0 - c * a_diag[V[single]])
         # CACs of two or more vertices: in-degree countdown sweep
         cac_mask = (ctype[cV] == 0) & ~single
         if np.any(cac_mask):
-            _cac_sweep(V[cac_mask], Wp[cac_mask], comp, c, deg, nbr_ptr, nbr, R)
+            _cac_sweep(V[cac_mask], Wp[cac_mask], comp, c, deg, nbr_ptr, nbr, R, a_diag)
         # SCCs: small ones solved directly when asked, the rest by the power
         # series per component
         scc_mask = ctype[cV] == 1
@@ -120,10 +128,11 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
     return R
 
 
-def _cac_sweep(Vc, Wp, comp, c, deg, nbr_ptr, nbr, R):
-    """Sec. 4.3.1 with loops ignored: v.degree = in-degree inside v's CAC,
+def _cac_sweep(Vc, Wp, comp, c, deg, nbr_ptr, nbr, R, a_diag=None):
+    """Sec. 4.3.1: v.degree = in-degree inside v's CAC (loops not counted),
     v.rank = W'_v; a vertex is dequeued only after all its in-edges inside the
-    CAC have delivered rank, and then pushes c*rank/outdeg along each out-edge
+    CAC have delivered rank; its rank is then final (divided by 1 - c a_vv
+    when it has a loop) and it pushes c*rank/outdeg along each out-edge
     inside the CAC.  Every vertex and edge is used once."""
     member = {int(v): i for i, v in enumerate(Vc)}
     rank = Wp.astype(np.float64).copy()
@@ -141,6 +150,8 @@ def _cac_sweep(Vc, Wp, comp, c, deg, nbr_ptr, nbr, R):
             while q:
                 j = q.popleft()
                 w = int(Vc[j])
+                if a_diag is not None and a_diag[w] != 0.0:
+                    rank[j] /= 1.0 - c * a_diag[w]
                 for e in range(int(nbr_ptr[w]), int(nbr_ptr[w + 1])):
                     u = int(nbr[e])
                     if u == w or comp[u] != comp[w] or u not in member:

@@ -3,10 +3,12 @@
 Test infrastructure only (see the package docstring).
 
 Conventions (Def. 3.4): A is the adjacency matrix with every non-zero row
-scaled to sum to one.  Self-loops are ignored, as in the experiments of
-Sec. 5.2; a repeated edge counts with its multiplicity (the paper assumes
-simple graphs, Sec. 3, so this only matters for inputs that are not).
-Dangling vertices have a zero row.
+scaled to sum to one.  Self-loops are ignored by default, as in the
+experiments of Sec. 5.2; with loops=True they stay in A (a vertex with a loop
+has a_vv > 0 and the loop counts in its out-degree), the general definition.
+A repeated edge counts with its multiplicity (the paper assumes simple
+graphs, Sec. 3, so this only matters for inputs that are not).  Dangling
+vertices have a zero row.
 """
 from __future__ import annotations
 
@@ -14,22 +16,22 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def out_degree(n, row_ptr, col):
-    """Out-degree without self-loops, duplicates counted."""
+def out_degree(n, row_ptr, col, loops=False):
+    """Out-degree, duplicates counted; self-loops only with loops=True."""
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
     src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
-    keep = src != col
+    keep = (src != col) | loops
     return np.bincount(src[keep], minlength=n).astype(np.int64)
 
 
-def transition_dense(n, row_ptr, col):
-    """Dense A of Def. 3.4 (row-normalised, loops dropped)."""
+def transition_dense(n, row_ptr, col, loops=False):
+    """Dense A of Def. 3.4 (row-normalised; loops dropped unless loops=True)."""
     A = np.zeros((n, n), dtype=np.float64)
     for u in range(n):
         for e in range(int(row_ptr[u]), int(row_ptr[u + 1])):
             v = int(col[e])
-            if v != u:
+            if v != u or loops:
                 A[u, v] += 1.0
     s = A.sum(axis=1)
     nz = s > 0
@@ -37,22 +39,23 @@ def transition_dense(n, row_ptr, col):
     return A
 
 
-def transition_T_csr(n, row_ptr, col):
-    """A^T as a scipy CSR matrix: row v holds 1/outdeg(u) for every edge u->v."""
+def transition_T_csr(n, row_ptr, col, loops=False):
+    """A^T as a scipy CSR matrix: row v holds 1/outdeg(u) for every edge u->v
+    (self-loops only with loops=True)."""
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
     src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
-    keep = src != col
+    keep = (src != col) | loops
     src, dst = src[keep], col[keep]
     deg = np.bincount(src, minlength=n).astype(np.float64)
     val = 1.0 / deg[src]
     return sp.csr_matrix((val, (dst, src)), shape=(n, n))
 
 
-def pagerank_dense(n, row_ptr, col, c, W):
+def pagerank_dense(n, row_ptr, col, c, W, loops=False):
     """R^(3) as the solution of (I - c A^T) R = W (Sec. 4.3, third method;
     equivalent to Def. 3.5).  LAPACK via numpy; for small n only."""
-    A = transition_dense(n, row_ptr, col)
+    A = transition_dense(n, row_ptr, col, loops)
     return np.linalg.solve(np.eye(n) - c * A.T, np.asarray(W, dtype=np.float64))
 
 
@@ -110,7 +113,7 @@ def pagerank_random_walks(n, row_ptr, col, c, W, walks_per_unit, seed):
 
 
 def pagerank_power_series(n, row_ptr, col, c, W, *, stop="cert", eps=1e-6, tol=None,
-                          max_iter=1_000_000, AT=None):
+                          max_iter=1_000_000, AT=None, loops=False):
     """The power series of Sec. 4.3.2 on the whole graph (the paper's baseline,
     "method 1" of Sec. 5.2):  P_0 = W,  P_{k+1} = c A^T P_k,  R = sum_k P_k.
 
@@ -124,7 +127,7 @@ def pagerank_power_series(n, row_ptr, col, c, W, *, stop="cert", eps=1e-6, tol=N
     Returns (R, iterations, ||P_K||_1).
     """
     if AT is None:
-        AT = transition_T_csr(n, row_ptr, col)
+        AT = transition_T_csr(n, row_ptr, col, loops)
     W = np.asarray(W, dtype=np.float64)
     R = W.copy()
     p = W.copy()
@@ -149,13 +152,13 @@ def pagerank_power_series(n, row_ptr, col, c, W, *, stop="cert", eps=1e-6, tol=N
     return R, k, last
 
 
-def residual_bound(n, row_ptr, col, c, W, R, AT=None):
+def residual_bound(n, row_ptr, col, c, W, R, AT=None, loops=False):
     """Certificate of any candidate R (Sec. 4.4): the residual r = W - (I - c A^T) R
     satisfies R* - R = (I - c A^T)^{-1} r, and the column sums of c A^T are at
     most c, so ||R* - R||_1 <= ||r||_1 / (1 - c).  Returns that bound divided
     by ||R||_1 (a relative 1-norm error bound) and A^T for reuse."""
     if AT is None:
-        AT = transition_T_csr(n, row_ptr, col)
+        AT = transition_T_csr(n, row_ptr, col, loops)
     R = np.asarray(R, dtype=np.float64)
     r = np.asarray(W, dtype=np.float64) - R + c * (AT @ R)
     return float(np.abs(r).sum() / ((1.0 - c) * np.abs(R).sum())), AT

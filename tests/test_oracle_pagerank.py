@@ -283,3 +283,67 @@ def test_direct_planted_sign_mistake_is_caught():
     AT = PR.transition_dense(m, g.row_ptr, g.col).T
     wrong = np.linalg.solve(np.eye(m) + C * AT, np.ones(m))
     assert not np.allclose(wrong, 1.0 / (1.0 - C), rtol=1e-6)
+
+
+# ------------------------------------------------- self-loops (general A)
+
+def _loopy(n, edges):
+    return csr_from_edges(n, [a for a, _ in edges], [b for _, b in edges], drop_loops=False)
+
+
+def test_loops_closed_forms():
+    """Def. 3.4 with a_vv > 0: a lone vertex with a loop has R = w/(1-c); a
+    loop plus one edge to a sink gives R_0 = w/(1-c/2) and R_1 = w + c R_0/2;
+    the same loop in the middle of a chain (a CAC) scales only its vertex."""
+    g = _loopy(1, [(0, 0)])
+    R = CW.componentwise_solve(1, g.row_ptr, g.col, C, np.ones(1), loops=True)
+    assert np.allclose(R, 1.0 / (1.0 - C), rtol=1e-15)
+    g = _loopy(2, [(0, 0), (0, 1)])
+    R = CW.componentwise_solve(2, g.row_ptr, g.col, C, np.ones(2), loops=True)
+    r0 = 1.0 / (1.0 - C / 2)
+    assert np.allclose(R, [r0, 1.0 + C * r0 / 2], rtol=1e-15)
+    g = _loopy(3, [(0, 1), (1, 1), (1, 2)])
+    R = CW.componentwise_solve(3, g.row_ptr, g.col, C, np.ones(3), loops=True)
+    r1 = (1.0 + C) / (1.0 - C / 2)
+    assert np.allclose(R, [1.0, r1, 1.0 + C * r1 / 2], rtol=1e-15)
+    # the default (loops ignored) differs: the loop is dropped from A and outdeg
+    R0 = CW.componentwise_solve(3, g.row_ptr, g.col, C, np.ones(3))
+    assert np.allclose(R0, [1.0, 1.0 + C, 1.0 + C * (1.0 + C)], rtol=1e-15)
+
+
+loop_lists = st.integers(min_value=1, max_value=30).flatmap(
+    lambda n: st.tuples(st.just(n), st.lists(
+        st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=3 * n),
+        st.lists(st.integers(0, n - 1), max_size=n)))
+
+
+@settings(max_examples=80, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(loop_lists, st.floats(0.05, 0.99))
+def test_property_loops_componentwise_equals_dense(nel, c):
+    """Random graphs with self-loops: the componentwise solve (CAC sweep with
+    the loop factor, SCC series with the diagonal, direct small SCCs too)
+    equals the dense solve of (I - c A^T) R = W with the loops in A."""
+    n, edges, loops = nel
+    g = _loopy(n, edges + [(v, v) for v in loops])
+    W = np.linspace(0.5, 1.5, n)
+    Rd = PR.pagerank_dense(g.n, g.row_ptr, g.col, c, W, loops=True)
+    Rc = CW.componentwise_solve(g.n, g.row_ptr, g.col, c, W, eps=1e-15, loops=True)
+    assert np.allclose(Rc, Rd, rtol=1e-9, atol=0)
+    Rx = CW.componentwise_solve(g.n, g.row_ptr, g.col, c, W, eps=1e-15, loops=True, direct_max=8)
+    assert np.allclose(Rx, Rd, rtol=1e-9, atol=0)
+
+
+def test_loops_planted_missing_factor_is_caught():
+    """The CAC sweep run without its loop factor (a_diag omitted) on a chain
+    with a looped middle vertex must miss the dense solve."""
+    g = _loopy(3, [(0, 1), (1, 1), (1, 2)])
+    W = np.ones(3)
+    Rd = PR.pagerank_dense(3, g.row_ptr, g.col, C, W, loops=True)
+    deg = PR.out_degree(3, g.row_ptr, g.col, loops=True)
+    R = np.zeros(3)
+    CW._cac_sweep(np.arange(3), W.copy(), np.zeros(3, dtype=np.int64), C, deg, g.row_ptr, g.col, R)
+    assert not np.allclose(R, Rd, rtol=1e-6)
+    R2 = np.zeros(3)
+    AT = PR.transition_T_csr(3, g.row_ptr, g.col, loops=True)
+    CW._cac_sweep(np.arange(3), W.copy(), np.zeros(3, dtype=np.int64), C, deg, g.row_ptr, g.col, R2, AT.diagonal())
+    assert np.allclose(R2, Rd, rtol=1e-14)
