@@ -8,9 +8,10 @@
  *        (I - c A^T) R = W                                          (Sec. 4.3)
  *
  * where A is the adjacency matrix of the input graph with every non-zero row
- * scaled to sum to one (Def. 3.4).  Self-loops are ignored everywhere, as in
- * the experiments (Sec. 5.2); a repeated edge counts with its multiplicity
- * in A and in the out-degree.
+ * scaled to sum to one (Def. 3.4).  Self-loops are ignored by default, as in
+ * the experiments (Sec. 5.2), or kept in A with the build option keep_loops
+ * (the general definition); the partition never depends on them.  A
+ * repeated edge counts with its multiplicity in A and in the out-degree.
  *
  * Conventions for every entry point
  *  - A graph is CSR over out-edges: row_ptr[n+1] (int64, row_ptr[0] == 0,
@@ -109,7 +110,13 @@ typedef struct pr_build_opts {
      the environment variable PR_AUTOTUNE_CACHE (read and appended to).
      The choice is reported by pr_levels_get_info. */
   int32_t autotune;
-  int32_t reserved[7];
+  /* 1 = keep self-loops in A (the general Def. 3.4: a loop counts in its
+     vertex's out-degree; an SCC's series uses the diagonal; a one-vertex or
+     CAC vertex's collected rank is divided by 1 - c a_vv, Sec. 4.3 and
+     4.3.1).  0 (default) = ignore them, as in the paper's experiments.  The
+     partition does not depend on loops. */
+  int32_t keep_loops;
+  int32_t reserved[6];
 } pr_build_opts;
 
 void pr_default_build_opts(pr_build_opts* o);
@@ -137,7 +144,7 @@ typedef struct pr_levels_info {
   int64_t n_scc, n_cac, n_singleton;  /* components by kind */
   int64_t v_scc, v_cac, v_singleton;  /* vertices by kind of component */
   int64_t m_scc_internal;   /* edges inside SCCs (iterated) */
-  int64_t m_cac_internal;   /* edges inside CACs (used once) */
+  int64_t m_cac_internal;   /* edges inside CACs, one-vertex components' kept loops included (used once) */
   int64_t m_between;        /* edges between components (used once) */
   int64_t n_items;          /* work items of the persistent segment kernels */
   int64_t n_gangs, n_gang_scc; /* gang phases, SCCs iterated in gang phases */

@@ -30,7 +30,8 @@ PR_PREC_FP64 = 1
 
 class BuildOpts(C.Structure):
     _fields_ = [("small_cutoff", C.c_int32), ("team_edges", C.c_int32), ("rows_per_wave", C.c_int32),
-                ("build_plain", C.c_int32), ("autotune", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("build_plain", C.c_int32), ("autotune", C.c_int32), ("keep_loops", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class SolveOpts(C.Structure):

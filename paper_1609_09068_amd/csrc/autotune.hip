@@ -75,6 +75,7 @@ int32_t autotune_levels(Levels& lv, hipStream_t s) {
   for (const char* q = prop.gcnArchName; *q; ++q) key = mix(key, (uint64_t)(unsigned char)*q);
   for (const char* q = pr_version(); *q; ++q) key = mix(key, (uint64_t)(unsigned char)*q);
   key = mix(key, lv.full_ptr ? 1u : 0u);
+  key = mix(key, lv.opts.keep_loops ? 2u : 0u);
   Choice best{lv.opts.rows_per_wave, lv.opts.small_cutoff, lv.opts.team_edges};
   bool have = false;
   if (lv.opts.autotune == 1) {

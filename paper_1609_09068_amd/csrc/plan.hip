@@ -92,12 +92,12 @@ __global__ void k_perm_inverse(const uint32_t* perm, int64_t n, int32_t* perm_ou
 
 // out-degree without self-loops, in plan order, and its reciprocals
 __global__ void k_degrees(const int64_t* row_ptr, const int32_t* col, const int32_t* perm, int64_t n,
-                          uint32_t* odeg, float* inv32, double* inv64) {
+                          int32_t keep_loops, uint32_t* odeg, float* inv32, double* inv64) {
   int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   const int32_t u = perm[i];
   uint32_t d = 0;
-  for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) d += (col[e] != u);
+  for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) d += (col[e] != u || keep_loops);
   odeg[i] = d;
   inv64[i] = d ? 1.0 / (double)d : 0.0;
   inv32[i] = d ? (float)(1.0 / (double)d) : 0.0f;
@@ -105,15 +105,15 @@ __global__ void k_degrees(const int64_t* row_ptr, const int32_t* col, const int3
 
 // edges in plan-source order: key = plan destination, value = plan source
 __global__ void k_emit_edges(const int64_t* row_ptr, const int32_t* col, const int32_t* perm,
-                             const int32_t* iperm, const uint32_t* optr, int64_t n, uint32_t* dkey,
-                             uint32_t* sval) {
+                             const int32_t* iperm, const uint32_t* optr, int64_t n, int32_t keep_loops,
+                             uint32_t* dkey, uint32_t* sval) {
   int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   const int32_t u = perm[i];
   uint32_t pos = optr[i];
   for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
     const int32_t w = col[e];
-    if (w == u) continue;
+    if (w == u && !keep_loops) continue;
     dkey[pos] = (uint32_t)iperm[w];
     sval[pos] = (uint32_t)i;
     ++pos;
@@ -273,7 +273,8 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
   PR_TRY(scr.get(sizeof(uint32_t) * (n + 1), (void**)&optr));
   PR_TRY(dalloc(&lv.inv_deg32, n));
   PR_TRY(dalloc(&lv.inv_deg64, n));
-  if (n) k_degrees<<<nblk(n), kB, 0, s>>>(d_rp, d_col, lv.perm, n, odeg, lv.inv_deg32, lv.inv_deg64);
+  if (n)
+    k_degrees<<<nblk(n), kB, 0, s>>>(d_rp, d_col, lv.perm, n, opts.keep_loops, odeg, lv.inv_deg32, lv.inv_deg64);
   PR_TRY(scan_u32(odeg, optr, n, s));
   uint32_t m32 = 0;
   PR_HIP_CHECK(hipMemcpyAsync(&m32, optr + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -286,7 +287,7 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
   PR_TRY(scr.get(sizeof(uint32_t) * m, (void**)&dkey));
   PR_TRY(scr.get(sizeof(uint32_t) * m, (void**)&sval));
   PR_TRY(scr.get(sizeof(uint32_t) * n, (void**)&rcnt));
-  if (n) k_emit_edges<<<nblk(n), kB, 0, s>>>(d_rp, d_col, lv.perm, iperm, optr, n, dkey, sval);
+  if (n) k_emit_edges<<<nblk(n), kB, 0, s>>>(d_rp, d_col, lv.perm, iperm, optr, n, opts.keep_loops, dkey, sval);
   PR_TRY(radix_sort_pairs(dkey, sval, m, bit_length((uint64_t)std::max<int64_t>(n - 1, 0)), s));
   uint32_t* fptr;
   PR_TRY(scr.get(sizeof(uint32_t) * (n + 1), (void**)&fptr));
@@ -372,6 +373,7 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
     } else {
       I.n_singleton++;
       I.v_singleton += sz;
+      I.m_cac_internal += h_cint[r];  // self-loops of a one-vertex component (keep_loops)
     }
     // sanity: plan order must be level-descending
     if (r > 0 && lv.h_comp_level[r] > lv.h_comp_level[r - 1]) {

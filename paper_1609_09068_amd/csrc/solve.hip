@@ -707,13 +707,16 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
             const uint4 s4 = sS[q];
             const uint32_t w4[4] = {s4.x, s4.y, s4.z, s4.w};
             double xs[4];
+            int nl = 0;  // self-loops (a plan built with keep_loops)
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
               const uint32_t w = w4[m];
-              xs[m] = (uint32_t)m >= n ? 0.0
-                      : (w & kExt)     ? ld_x(p.x, (int)(w & ~kExt))
-                      : (int)w == prev ? xprev
-                                       : ld_lx((int)w);
+              const bool self = (uint32_t)m < n && w == (uint32_t)loc;
+              nl += self ? 1 : 0;
+              xs[m] = ((uint32_t)m >= n || self) ? 0.0
+                      : (w & kExt)              ? ld_x(p.x, (int)(w & ~kExt))
+                      : (int)w == prev          ? xprev
+                                                : ld_lx((int)w);
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -722,15 +725,23 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
                 r += xs[m];
               }
             }
+            // the loop's share returns to the vertex: R = (W' + sources) / (1 - c a_vv)
+            if (nl) r /= 1.0 - (double)nl * c8[j];
           } else if (kind == 3u) {
             const uint32_t l0 = p.int_ptr[vbeg + loc], l1 = p.int_ptr[vbeg + loc + 1];
+            int nl = 0;
             for (uint32_t e = l0; e < l1 && ok; ++e) {
               const int u = p.int_src[e];
               if (!inside(u)) continue;
+              if (u - vbeg == loc) {
+                ++nl;
+                continue;
+              }
               const double xv = u - vbeg == prev ? xprev : ld_lx(u - vbeg);
               if (xv < 0.0) ok = false;
               else r += xv;
             }
+            if (nl) r /= 1.0 - (double)nl * c8[j];
           }
           if (!ok) {
             stop = true;
