@@ -32,7 +32,7 @@ from .partition import partition_theorem
 
 def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e-6,
                         tol=None, max_iter=1_000_000, return_stats=False, warm=None, warm_fn=None,
-                        direct_max=0, loops=False):
+                        direct_max=0, loops=False, tail=False):
     """Componentwise R^(3).
 
     Stop rule per SCC C (one term added per iteration, k >= 1):
@@ -55,6 +55,16 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
     vertex's collected rank is divided by (1 - c a_vv) before it is passed
     on (the loop's own share comes back to it); SCC series use A_CC with its
     diagonal.
+
+    tail: with the CERT rule, an SCC may also stop early on a geometric
+    estimate of the rest of its series.  After term P_{k+1} with
+    rho = ||P_k||_1 / ||P_{k-1}||_1 < 1, the candidate
+    R' = P_0 + ... + P_k + rho/(1-rho) P_k has the residual
+    W' - (I - c A_CC^T) R' = (P_{k+1} - rho P_k) / (1 - rho), so
+    ||R' - R*_C||_1 <= ||P_{k+1} - rho P_k||_1 / ((1-rho)(1-c)); the SCC stops
+    with R' when that is at most eps ||W'_C||_1 (the CERT rule's own bound).
+    The plain test is tried first.  Its last-term norm is then the residual
+    norm divided by c, so the certificate's c/(1-c) factor gives the bound.
 
     direct_max: SCCs of at most this many vertices are solved directly,
     (I - c A_CC^T) R_C = W'_C with a dense LAPACK solve: the paper's choice
@@ -122,7 +132,7 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
             scc_mask = scc_mask & ~dmask
         if np.any(scc_mask):
             Vs = V[scc_mask]
-            _scc_series(Vs, Wp[scc_mask], comp, c, AT, R, iters, last, stop, eps, tol, max_iter, feat)
+            _scc_series(Vs, Wp[scc_mask], comp, c, AT, R, iters, last, stop, eps, tol, max_iter, feat, tail)
     if return_stats:
         return R, dict(iters=iters, last=last, wprime=wprime, accepted=accepted)
     return R
@@ -177,7 +187,7 @@ def _scc_direct(Vd, Wp, comp, c, AT, R):
         R[idx] = np.linalg.solve(M, Wp[m])
 
 
-def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter, feat=None):
+def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter, feat=None, tail=False):
     """Power series of Sec. 4.3.2 on each SCC of one level.
 
     With a starting guess (feat), a component whose guess passes the residual
@@ -238,15 +248,34 @@ def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter, f
         iters[uniq] = it
         last[uniq] = lastn
         return
+    use_tail = tail and stop == "cert" and feat is None
+    norm_prev = wnorm.copy()            # ||P_k||_1 (k = 0: W'_C)
+    norm_prev2 = np.full(nc, np.nan)    # ||P_{k-1}||_1, unknown before P_1
     while np.any(active) and k < max_iter:
-        p = c * (sub @ p)
-        p[~active[local]] = 0.0
-        acc += p
+        q = c * (sub @ p)
+        q[~active[local]] = 0.0
         k += 1
         it[active] = k
-        pn = np.bincount(local, weights=np.abs(p), minlength=nc)
-        lastn[active] = pn[active]
-        done = stop_test(p)
+        qn = np.bincount(local, weights=np.abs(q), minlength=nc)
+        done = stop_test(q)
+        acc_new = acc + q
+        if use_tail:
+            rho = norm_prev / norm_prev2
+            ok_rho = np.isfinite(rho) & (rho > 0.0) & (rho < 1.0)
+            rho_s = np.where(ok_rho, rho, 0.0)
+            d = np.bincount(local, weights=np.abs(q - rho_s[local] * p), minlength=nc)
+            res = np.where(ok_rho, d / np.where(ok_rho, 1.0 - rho_s, 1.0), np.inf)
+            tail_stop = active & ~done & ok_rho & (res <= eps * (1.0 - c) * wnorm)
+            if np.any(tail_stop):
+                ts = tail_stop[local]
+                f = rho_s / np.where(ok_rho, 1.0 - rho_s, 1.0)
+                acc_new = np.where(ts, acc + f[local] * p, acc_new)
+                qn = np.where(tail_stop, res / c, qn)
+                done = done | tail_stop
+        acc = acc_new
+        lastn[active] = qn[active]
+        norm_prev2, norm_prev = norm_prev, qn
+        p = q
         active &= ~done
     R[Vs] = acc
     iters[uniq] = it

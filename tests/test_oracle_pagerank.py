@@ -347,3 +347,55 @@ def test_loops_planted_missing_factor_is_caught():
     AT = PR.transition_T_csr(3, g.row_ptr, g.col, loops=True)
     CW._cac_sweep(np.arange(3), W.copy(), np.zeros(3, dtype=np.int64), C, deg, g.row_ptr, g.col, R2, AT.diagonal())
     assert np.allclose(R2, Rd, rtol=1e-14)
+
+
+# ------------------------------- geometric tail estimate of an SCC series
+
+@pytest.mark.parametrize("m", [3, 8])
+def test_tail_estimate_exact_on_a_cycle(m):
+    """On a bare cycle with W = 1 every term is c^k W, so the tail estimate
+    is exact: the SCC stops after two terms with R = 1/(1-c), where the plain
+    rule needs about log(eps (1-c)) / log(c) terms."""
+    g = _g(m, [(i, (i + 1) % m) for i in range(m)])
+    R, st = CW.componentwise_solve(m, g.row_ptr, g.col, C, np.ones(m), eps=1e-10, tail=True, return_stats=True)
+    assert np.allclose(R, 1.0 / (1.0 - C), rtol=1e-14, atol=0)
+    assert st["iters"].max() == 2
+    _, st0 = CW.componentwise_solve(m, g.row_ptr, g.col, C, np.ones(m), eps=1e-10, return_stats=True)
+    assert st0["iters"].max() == math.ceil(math.log(1e-10 * (1 - C)) / math.log(C))
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("eps", [1e-4, 1e-8])
+def test_tail_estimate_meets_the_bound(seed, eps):
+    """Random graphs with SCCs: the relative 1-norm error against the dense
+    solve stays below eps, and no SCC takes more terms than the plain rule."""
+    g = random_digraph(300, 900, seed + 900)
+    W = np.random.default_rng(seed).uniform(0.5, 1.5, g.n)
+    Rd = PR.pagerank_dense(g.n, g.row_ptr, g.col, C, W)
+    R, st = CW.componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=eps, tail=True, return_stats=True)
+    _, st0 = CW.componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=eps, return_stats=True)
+    assert np.abs(R - Rd).sum() / np.abs(Rd).sum() <= eps
+    assert np.all(st["iters"] <= st0["iters"]) and st["iters"].sum() < st0["iters"].sum()
+    # the certificate c/(1-c) sum(last) bounds the actual error
+    assert np.abs(R - Rd).sum() <= C / (1 - C) * st["last"].sum() * (1 + 1e-9)
+
+
+def test_tail_planted_wrong_candidate_is_caught():
+    """Adding the tail on the newest term (rho/(1-rho) P_{k+1}) instead of on
+    P_k breaks the residual identity: on a cycle with unequal weights the
+    wrong candidate misses the dense solve by far more than eps."""
+    m = 5
+    g = _g(m, [(i, (i + 1) % m) for i in range(m)] + [(0, 2)])
+    W = np.linspace(0.5, 1.5, m)
+    Rd = PR.pagerank_dense(m, g.row_ptr, g.col, C, W)
+    AT = PR.transition_T_csr(m, g.row_ptr, g.col)
+    p0 = W.copy()
+    p1 = C * (AT @ p0)
+    p2 = C * (AT @ p1)
+    rho = np.abs(p1).sum() / np.abs(p0).sum()
+    right = p0 + p1 + rho / (1 - rho) * p1
+    wrong = p0 + p1 + p2 + rho / (1 - rho) * p2
+    r_right = W - right + C * (AT @ right)
+    assert np.allclose(r_right, (p2 - rho * p1) / (1 - rho), atol=1e-12)  # the identity the rule uses
+    r_wrong = W - wrong + C * (AT @ wrong)
+    assert not np.allclose(r_wrong, (p2 - rho * p1) / (1 - rho), atol=1e-6)
