@@ -260,7 +260,8 @@ def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter, f
         done = stop_test(q)
         acc_new = acc + q
         if use_tail:
-            rho = norm_prev / norm_prev2
+            with np.errstate(invalid="ignore", divide="ignore"):
+                rho = norm_prev / norm_prev2
             ok_rho = np.isfinite(rho) & (rho > 0.0) & (rho < 1.0)
             rho_s = np.where(ok_rho, rho, 0.0)
             d = np.bincount(local, weights=np.abs(q - rho_s[local] * p), minlength=nc)

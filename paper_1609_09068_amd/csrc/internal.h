@@ -148,6 +148,8 @@ struct Levels {
   double* gpart = nullptr;        // [2 * n_gslots] partial 1-norms of the last two terms
   double* gpmx = nullptr;         // [2 * n_gslots] partial max-norms
   double* gwsum = nullptr;        // [n_gscc + 1] ||W'_C||_1 of each gang SCC
+  double* gpdiff = nullptr;       // [2 * n_gslots] partial 1-norms of P_k - rho P_{k-1} (tail estimate)
+  double* gnhist = nullptr;       // [3 * n_gscc] ||P_{k-1}||_1 of each gang SCC, written by launch k at k % 3
   GangHub* ghubs = nullptr;       // hub rows of all gangs
   GangPiece* gpieces = nullptr;   // hub pieces, grouped by workgroup within a gang
   int32_t* gpiece_ptr = nullptr;  // per gang: grid+1 offsets into gpieces
@@ -156,7 +158,8 @@ struct Levels {
   std::vector<int32_t> h_gang_nhub;  // hubs per gang (host)
   std::vector<int32_t> h_gang_rank;  // component ranks of the componentwise gang SCCs (host)
   std::vector<std::pair<int32_t, int32_t>> h_gang_sccs;  // per gang: its range in the GangScc table
-  std::vector<int64_t> h_gang_hint;  // per gang: most terms any solve of this plan needed (0: none yet)
+  std::vector<int64_t> h_gang_hint;  // per gang and tail mode (index tail * n_gangs + gang): most terms any
+                                     // solve of this plan needed (0: none yet)
   int64_t n_ghubs = 0, n_gpieces = 0;
   int32_t* gdone = nullptr;       // [n_gscc + 1] iterations when converged, -1 while running
   std::vector<uint32_t> h_int_ptr, h_full_ptr;

@@ -65,6 +65,7 @@ struct SolveParams {
   int32_t plain;
   int32_t n_items;  // items of the segment being run
   int32_t direct_max;  // SCCs of a wavefront with at most this many vertices are solved directly
+  int32_t tail;        // segment SCC series may stop on the certified geometric tail estimate
   double c, eps, tol;
   int64_t max_iter;
   const double* W;
@@ -113,6 +114,8 @@ struct SolveParams {
   double* gpart;
   double* gpmx;
   double* gwsum;
+  double* gpdiff;
+  double* gnhist;
   int32_t* gdone;
   const GangHub* ghubs;
   const GangPiece* gpieces;
@@ -245,6 +248,25 @@ __device__ inline void block_sum_max(double v, double m, double* red, int parity
   __syncthreads();
   *sum = (r[0] + r[1]) + (r[2] + r[3]);
   *mx = fmax(fmax(r[4], r[5]), fmax(r[6], r[7]));
+}
+
+// the same with a second sum (red holds 24 doubles)
+__device__ inline void block_sum2_max(double v, double d, double m, double* red, int parity, double* sum,
+                                      double* dsum, double* mx) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  d = wave_sum(d);
+  m = wave_max(m);
+  double* r = red + 12 * parity;
+  if (lane == 0) {
+    r[wave] = v;
+    r[4 + wave] = m;
+    r[8 + wave] = d;
+  }
+  __syncthreads();
+  *sum = (r[0] + r[1]) + (r[2] + r[3]);
+  *mx = fmax(fmax(r[4], r[5]), fmax(r[6], r[7]));
+  *dsum = (r[8] + r[9]) + (r[10] + r[11]);
 }
 
 __device__ inline double block_sum(double v, double* lds) {
@@ -895,7 +917,7 @@ __device__ WarmOut warm_preamble(const SolveParams& p, int vbeg, int nv, double 
 // (one-byte local source ids, two-byte row offsets) when they fit, so every
 // term touches only LDS and registers (R stays in registers, four rows per
 // lane).
-template <typename YT, bool WARM>
+template <typename YT, bool WARM, bool TAIL = false>
 __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned long long* wst, WaveTile* tile) {
   const int lane = threadIdx.x & 63;
   const int vbeg = p.comp_vbeg[rank];
@@ -1042,6 +1064,10 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
     const double inv64 = act ? p.inv64[vbeg + lane] : 0.0;
     const bool cert = p.stop == PR_STOP_CERT_L1;
     double R0 = Rj[0];
+    // certified tail estimate (no starting guess): the previous term and the
+    // norms of the last two terms
+    const bool tail = TAIL && p.tail && cert;
+    double svp = R0, nprev = wsum, nprev2 = -1.0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     while (k < p.max_iter) {
       ++k;
@@ -1087,6 +1113,21 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
           conv = true;
           break;
         }
+        if (tail) {
+          const double rho = nprev2 > 0.0 ? nprev / nprev2 : -1.0;
+          if (rho > 0.0 && rho < 1.0) {
+            const double res = wave_sum(act ? fabs((double)sv - rho * svp) : 0.0) / (1.0 - rho);
+            if (res <= thresh) {  // R' = R - P_k + rho/(1-rho) P_{k-1}
+              R0 += rho / (1.0 - rho) * svp - (double)sv;
+              last = res / p.c;
+              conv = true;
+              break;
+            }
+          }
+          nprev2 = nprev;
+          nprev = norm;
+          svp = (double)sv;
+        }
       } else {
         const double mx = wave_max(sd);
         last = wave_sum(sd);
@@ -1099,10 +1140,19 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
     Rj[0] = R0;
   } else if (!skip) {
     conv = false;
+    // tail estimate: a row's terms are read back from the term buffers
+    const bool tail = TAIL && p.tail;
+    double nprev = wsum, nprev2 = -1.0;
+    auto scale = [&](int j, int i) -> double {  // the factor between P and the term buffer
+      if constexpr (sizeof(YT) == 8) return (double)cy * p.inv64[vbeg + i];
+      else return (double)cy * (double)inv[j];
+    };
     while (k < p.max_iter) {
       ++k;
       part = 0.0;
-      double pm = 0.0;
+      double pm = 0.0, dd = 0.0;
+      const double rho = (tail && nprev2 > 0.0) ? nprev / nprev2 : -1.0;
+      const bool rho_ok = rho > 0.0 && rho < 1.0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int i = lane + 64 * j;
@@ -1127,6 +1177,7 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
           }
           const YT s = s0 + s1;
           Rj[j] += (double)s;
+          if (rho_ok) dd += fabs((double)s - rho * (double)ya[i] / scale(j, i));
           if constexpr (sizeof(YT) == 8) yb[i] = cy * s * p.inv64[vbeg + i];
           else yb[i] = cy * s * inv[j];
           part += fabs((double)s);
@@ -1144,6 +1195,21 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
         conv = true;
         break;
       }
+      if (rho_ok) {
+        const double res = wave_sum(dd) / (1.0 - rho);
+        if (res <= thresh) {  // R' = R - P_k + rho/(1-rho) P_{k-1}; ya: P_k, yb: P_{k-1}
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int i = lane + 64 * j;
+            if (i < nv) Rj[j] += (rho / (1.0 - rho) * (double)yb[i] - (double)ya[i]) / scale(j, i);
+          }
+          last = res / p.c;
+          conv = true;
+          break;
+        }
+      }
+      nprev2 = nprev;
+      nprev = norm;
     }
   }
 #pragma unroll
@@ -1162,7 +1228,7 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
 // (two-byte local sources), 1/outdeg, R and both term vectors live in LDS
 // during the iteration; otherwise the vectors stay in global memory, touched
 // only by this workgroup.
-template <typename YT, int RPW, bool WARM>
+template <typename YT, int RPW, bool WARM, bool TAIL = false>
 __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, int rank, double* red, unsigned long long* wst, WaveTile* tiles,
                            unsigned char* raw, size_t raw_bytes) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1271,10 +1337,15 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
     const uint4* gs = p.mslot_src + sb;
     YT* la = l0;
     YT* lb = l1;
+    // certified tail estimate as in the register path below
+    const bool tail = TAIL && p.tail;
+    double nprev = wsum, nprev2 = -1.0;
     if (!skip) {
       conv = false;
       while (k < p.max_iter) {
         ++k;
+        const double rho = (tail && nprev2 > 0.0) ? nprev / nprev2 : -1.0;
+        const bool rho_ok = rho > 0.0 && rho < 1.0;
         // (A) slot sums, four slots' ids in flight per thread
         for (uint32_t base = threadIdx.x; base < nslot; base += 4 * kThreads) {
           uint4 w[4];
@@ -1297,7 +1368,7 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
         }
         __syncthreads();
         // (B) row sums
-        double part = 0.0, pm = 0.0;
+        double part = 0.0, pm = 0.0, dpart = 0.0;
         for (int rb = wave * 64; rb < nv; rb += kThreads) {
           const int r = rb + lane;
           const uint32_t f0 = r < nv ? lfs[r] : 0u, f1 = r < nv ? lfs[r + 1] : 0u;
@@ -1329,10 +1400,13 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
             lb[r] = cy * sv * linv[r];
             part += fabs((double)sv);
             pm = fmax(pm, fabs((double)sv));
+            if (rho_ok) dpart += fabs((double)sv - rho * (double)la[r] / ((double)cy * (double)linv[r]));
           }
         }
-        double norm, mx;
-        block_sum_max(part, pm, red, (int)(k & 1), &norm, &mx);  // the barrier also publishes lb
+        double norm, mx, dsum = 0.0;
+        // the barrier also publishes lb
+        if (tail) block_sum2_max(part, dpart, pm, red, (int)(k & 1), &norm, &dsum, &mx);
+        else block_sum_max(part, pm, red, (int)(k & 1), &norm, &mx);
         last = norm;
         YT* tt = la;
         la = lb;
@@ -1341,6 +1415,17 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
           conv = true;
           break;
         }
+        if (rho_ok && dsum / (1.0 - rho) <= thresh) {  // lb: P_{k-1}, la: P_k; a thread's rows only
+          for (int r = threadIdx.x; r < nv; r += kThreads) {
+            const double sc = (double)cy * (double)linv[r];
+            lR[r] += rho / (1.0 - rho) * ((double)lb[r] / sc) - (double)la[r] / sc;
+          }
+          last = dsum / (1.0 - rho) / p.c;
+          conv = true;
+          break;
+        }
+        nprev2 = nprev;
+        nprev = norm;
       }
     }
     for (int q = threadIdx.x; q < nv; q += kThreads) {
@@ -1383,10 +1468,17 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
     __syncthreads();
     YT* la = l0;
     YT* lb = l1;
+    // certified tail estimate (no starting guess): the norms of the last two
+    // terms; a row's terms are read back from the term buffers, which hold
+    // c P_k / outdeg (a relative difference of one FP32 rounding)
+    const bool tail = TAIL && p.tail;
+    double nprev = wsum, nprev2 = -1.0;
     if (!skip) {
       conv = false;
       while (k < p.max_iter) {
         ++k;
+        const double rho = (tail && nprev2 > 0.0) ? nprev / nprev2 : -1.0;
+        const bool rho_ok = rho > 0.0 && rho < 1.0;
         // (A) slot sums
 #pragma unroll
         for (int j = 0; j < kSPT; ++j) {
@@ -1400,7 +1492,7 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
         }
         __syncthreads();
         // (B) row sums
-        double part = 0.0, pm = 0.0;
+        double part = 0.0, pm = 0.0, dpart = 0.0;
 #pragma unroll
         for (int j = 0; j < kRPT; ++j) {
           if (kThreads * j + wave * 64 < nv) {  // wave-uniform
@@ -1434,11 +1526,14 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
               lb[r] = cy * sv * ir[j];
               part += fabs((double)sv);
               pm = fmax(pm, fabs((double)sv));
+              if (rho_ok) dpart += fabs((double)sv - rho * (double)la[r] / ((double)cy * (double)ir[j]));
             }
           }
         }
-        double norm, mx;
-        block_sum_max(part, pm, red, (int)(k & 1), &norm, &mx);  // the barrier also publishes lb
+        double norm, mx, dsum = 0.0;
+        // the barrier also publishes lb
+        if (tail) block_sum2_max(part, dpart, pm, red, (int)(k & 1), &norm, &dsum, &mx);
+        else block_sum_max(part, pm, red, (int)(k & 1), &norm, &mx);
         last = norm;
         YT* tt = la;
         la = lb;
@@ -1447,6 +1542,21 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
           conv = true;
           break;
         }
+        if (rho_ok && dsum / (1.0 - rho) <= thresh) {  // R' = R - P_k + rho/(1-rho) P_{k-1}
+#pragma unroll
+          for (int j = 0; j < kRPT; ++j) {
+            const int r = threadIdx.x + kThreads * j;
+            if (r < nv) {
+              const double sc = (double)cy * (double)ir[j];
+              Rr[j] += rho / (1.0 - rho) * ((double)lb[r] / sc) - (double)la[r] / sc;  // lb: P_{k-1}, la: P_k
+            }
+          }
+          last = dsum / (1.0 - rho) / p.c;
+          conv = true;
+          break;
+        }
+        nprev2 = nprev;
+        nprev = norm;
       }
     }
 #pragma unroll
@@ -1458,26 +1568,36 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
       }
     }
   } else {
+    // certified tail estimate as in the register path above
+    const bool tail = TAIL && p.tail;
+    double nprev = wsum, nprev2 = -1.0;
     if (!skip) {
       conv = false;
       while (k < p.max_iter) {
         ++k;
+        const double rho = (tail && nprev2 > 0.0) ? nprev / nprev2 : -1.0;
+        const bool rho_ok = rho > 0.0 && rho < 1.0;
         part = 0.0;
-        double pm = 0.0;
+        double pm = 0.0, dpart = 0.0;
         for (int ra = w0; ra < w1; ra += 64) {
           const int nr = w1 - ra < 64 ? w1 - ra : 64;
           const YT s = wave_tile_gather<RPW, YT, false>(p, ptr, src, ya, ra, nr, tile);
           if (lane < nr) {
             const int v = ra + lane;
+            YT iv;
+            if constexpr (sizeof(YT) == 8) iv = p.inv64[v];
+            else iv = p.inv32[v];
             p.R[v] += (double)s;
-            if constexpr (sizeof(YT) == 8) yb[v] = cy * s * p.inv64[v];
-            else yb[v] = cy * s * p.inv32[v];
+            if (rho_ok) dpart += fabs((double)s - rho * (double)ya[v] / ((double)cy * (double)iv));
+            yb[v] = cy * s * iv;
             part += fabs((double)s);
             pm = fmax(pm, fabs((double)s));
           }
         }
-        double norm, mx;
-        block_sum_max(part, pm, red, (int)(k & 1), &norm, &mx);  // the barrier also publishes yb
+        double norm, mx, dsum = 0.0;
+        // the barrier also publishes yb
+        if (tail) block_sum2_max(part, dpart, pm, red, (int)(k & 1), &norm, &dsum, &mx);
+        else block_sum_max(part, pm, red, (int)(k & 1), &norm, &mx);
         last = norm;
         YT* tt = ya;
         ya = yb;
@@ -1486,6 +1606,20 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
           conv = true;
           break;
         }
+        if (rho_ok && dsum / (1.0 - rho) <= thresh) {  // yb: P_{k-1}, ya: P_k; a lane's own rows
+          for (int v = w0 + lane; v < w1; v += 64) {
+            double iv;
+            if constexpr (sizeof(YT) == 8) iv = p.inv64[v];
+            else iv = (double)p.inv32[v];
+            const double sc = (double)cy * iv;
+            p.R[v] += rho / (1.0 - rho) * ((double)yb[v] / sc) - (double)ya[v] / sc;
+          }
+          last = dsum / (1.0 - rho) / p.c;
+          conv = true;
+          break;
+        }
+        nprev2 = nprev;
+        nprev = norm;
       }
     }
     for (int v = w0 + lane; v < w1; v += 64) {
@@ -1526,9 +1660,9 @@ static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + kThrea
 // whatever the number of resident workgroups: an item only waits for items
 // handed out before it, and those are held by running workgroups; the
 // lowest unfinished item has nothing left to wait for.
-template <typename YT, int RPW, bool WARM>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ? 1 : 3))) void k_segment(SolveParams p) {
-  __shared__ double s_red[16];
+template <typename YT, int RPW, bool WARM, bool TAIL = false>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((WARM || RPW == 1) ? 1 : ((TAIL || RPW < 16) ? 2 : 3)))) void k_segment(SolveParams p) {
+  __shared__ double s_red[24];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kSegLds];
   __shared__ unsigned long long s_stats[kWgStats];
   WaveTile* tiles = reinterpret_cast<WaveTile*>(s_raw);
@@ -1562,10 +1696,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ?
     } else if (it.kind == ITEM_SMALL) {
       const int r = it.a + wave;
       YT* ybuf = reinterpret_cast<YT*>(second) + (size_t)wave * 2 * kSmallMax;
-      if (r < it.b) run_small<YT, WARM>(p, r, ybuf, s_stats, &tiles[wave]);
+      if (r < it.b) run_small<YT, WARM, TAIL>(p, r, ybuf, s_stats, &tiles[wave]);
       slot = S_T_SMALL;
     } else {
-      run_medium<YT, RPW, WARM>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
+      run_medium<YT, RPW, WARM, TAIL>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
       slot = S_T_MEDIUM;
     }
     __syncthreads();
@@ -1618,19 +1752,23 @@ __device__ inline GangCtx gang_ctx(const SolveParams& p, const GangDesc& gd) {
   return g;
 }
 
-// deterministic sum (and max) of an SCC's partials from launch `parity`
+// deterministic sum (and max) of an SCC's partials from launch `parity`;
+// with `dtot`, also the sum of its tail-estimate partials
 __device__ inline void gang_total(const SolveParams& p, const GangScc& sc, int parity, double* red, double* tot,
-                                  double* mx) {
+                                  double* mx, double* dtot = nullptr) {
   const int cnt = sc.nslot;
-  const double* pp = p.gpart + (size_t)parity * p.n_gslots + sc.pbase;
-  const double* pm = p.gpmx + (size_t)parity * p.n_gslots + sc.pbase;
-  double s = 0.0, m = 0.0;
+  const size_t off = (size_t)parity * p.n_gslots + sc.pbase;
+  const double* pp = p.gpart + off;
+  const double* pm = p.gpmx + off;
+  double s = 0.0, m = 0.0, d = 0.0;
   for (int j = threadIdx.x; j < cnt; j += kThreads) {
     s += pp[j];
     m = fmax(m, pm[j]);
+    if (dtot) d += p.gpdiff[off + j];
   }
   *tot = block_sum(s, red);
   *mx = block_max(m, red);
+  if (dtot) *dtot = block_sum(d, red);
 }
 
 __device__ inline void gang_finalise(const SolveParams& p, const GangScc& sc, const GangCtx& g, int64_t iters,
@@ -1715,7 +1853,7 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
     };
     const int w0 = wave == 0 ? a : find_row(tot_w * wave / kWaves);
     const int w1 = wave == kWaves - 1 ? z : find_row(tot_w * (wave + 1) / kWaves);
-    double part = 0.0, pm = 0.0;
+    double part = 0.0, pm = 0.0, dpart = 0.0, rho_k = -1.0;
     if (k == 0) {
       for (int ra = w0; ra < w1; ra += 64) {
         const int nr = w1 - ra < 64 ? w1 - ra : 64;
@@ -1732,8 +1870,8 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
         }
       }
     } else {
-      double tot, mx;
-      gang_total(p, sc, par_r, s_red, &tot, &mx);
+      double tot, mx, dtot = 0.0;
+      gang_total(p, sc, par_r, s_red, &tot, &mx, p.tail ? &dtot : nullptr);
       double wsum;
       if (k == 1) {
         wsum = tot;
@@ -1753,11 +1891,36 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
       } else {
         stop = stop_now(p, tot, mx, thresh);
       }
+      // certified tail estimate (no starting guess): gnhist slot j % 3 holds
+      // ||P_{j-1}||_1 from launch j; rho_t belongs to the difference term k-1
+      // carries, rho_k to the one this launch forms for term k
+      const YT cy = (YT)c;
+      double rho_t = -1.0;
+      if (p.tail) {
+        double* hist = p.gnhist + 3 * (size_t)si;
+        if (blockIdx.x == sc.wg_first && threadIdx.x == 0) hist[k % 3] = tot;
+        if (k >= 2 && hist[(k - 1) % 3] > 0.0) rho_k = tot / hist[(k - 1) % 3];
+        if (k >= 3 && hist[(k - 2) % 3] > 0.0) rho_t = hist[(k - 1) % 3] / hist[(k - 2) % 3];
+        if (!stop && rho_t > 0.0 && rho_t < 1.0 && dtot / (1.0 - rho_t) <= thresh) {
+          // R' = R - P_{k-1} + rho/(1-rho) P_{k-2}: the terms come back from
+          // the term buffers (c P / outdeg), each row by the thread that
+          // finalises it
+          for (int v = a + (int)threadIdx.x; v < z; v += kThreads) {
+            double iv;
+            if constexpr (sizeof(YT) == 8) iv = p.inv64[v];
+            else iv = (double)p.inv32[v];
+            const double sc_v = (double)cy * iv;
+            p.R[v] += rho_t / (1.0 - rho_t) * ((double)yw[v] / sc_v) - (double)yr[v] / sc_v;
+          }
+          last = dtot / (1.0 - rho_t) / c;
+          stop = true;
+        }
+      }
       if (stop || final_launch) {
         gang_finalise(p, sc, g, k - 1, last, stop, s_stats);
         continue;
       }
-      const YT cy = (YT)c;
+      const bool rho_ok = rho_k > 0.0 && rho_k < 1.0;
       int hidx = first_hub(p, gd, w0);  // hub rows are summed in pieces below
       int ra = w0;
       while (ra < w1) {
@@ -1773,9 +1936,12 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
         const YT sv = wave_tile_gather<RPW, YT, false>(p, ptr, p.int_src, yr, ra, nr, &s_tile[wave]);
         if (lane < nr) {
           const int v = ra + lane;
+          YT iv;
+          if constexpr (sizeof(YT) == 8) iv = p.inv64[v];
+          else iv = p.inv32[v];
           p.R[v] += (double)sv;
-          if constexpr (sizeof(YT) == 8) yw[v] = cy * sv * p.inv64[v];
-          else yw[v] = cy * sv * p.inv32[v];
+          if (rho_ok) dpart += fabs((double)sv - rho_k * (double)yr[v] / ((double)cy * (double)iv));
+          yw[v] = cy * sv * iv;
           part += fabs((double)sv);
           pm = fmax(pm, fabs((double)sv));
         }
@@ -1784,10 +1950,12 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
     }
     part = block_sum(part, s_red);
     pm = block_max(pm, s_red);
+    if (p.tail) dpart = block_sum(dpart, s_red);
     if (threadIdx.x == 0) {
       const size_t slot = (size_t)par_w * p.n_gslots + sc.pbase + (blockIdx.x - sc.wg_first);
       p.gpart[slot] = part;
       p.gpmx[slot] = pm;
+      if (p.tail) p.gpdiff[slot] = dpart;
     }
   }
   // pieces of hub rows assigned to this workgroup (terms k >= 1); a piece
@@ -1831,18 +1999,28 @@ __global__ __launch_bounds__(kThreads) void k_gang_hubs(SolveParams p, int gang,
   if (k == 0) {
     p.gpart[slot] = 0.0;
     p.gpmx[slot] = 0.0;
+    if (p.tail) p.gpdiff[slot] = 0.0;
     return;
   }
   if (p.gdone[hb.scc] >= 0) return;  // its SCC stopped in launch k
   YT s = 0;
   for (int q = hb.p0; q < hb.p1; ++q) s += (YT)p.gpiece_part[p.ghub_pieces[q]];
   YT* yw = (YT*)((k & 1) ? p.y1 : p.y0);
+  const YT* yr = (const YT*)((k & 1) ? p.y0 : p.y1);
   const int v = hb.row;
+  YT iv;
+  if constexpr (sizeof(YT) == 8) iv = p.inv64[v];
+  else iv = p.inv32[v];
+  const YT cy = (YT)p.c;
   p.R[v] += (double)s;
-  if constexpr (sizeof(YT) == 8) yw[v] = (YT)p.c * s * p.inv64[v];
-  else yw[v] = (YT)p.c * s * p.inv32[v];
+  yw[v] = cy * s * iv;
   p.gpart[slot] = fabs((double)s);
   p.gpmx[slot] = fabs((double)s);
+  if (p.tail) {  // the same rho_k as launch k (gnhist, see k_gang)
+    const double* hist = p.gnhist + 3 * (size_t)hb.scc;
+    const double rho = (k >= 2 && hist[(k - 1) % 3] > 0.0) ? hist[k % 3] / hist[(k - 1) % 3] : -1.0;
+    p.gpdiff[slot] = (rho > 0.0 && rho < 1.0) ? fabs((double)s - rho * (double)yr[v] / ((double)cy * (double)iv)) : 0.0;
+  }
 }
 
 // Starting guess for the SCCs of a gang (Sec. 4.3.2 series started from a
@@ -2087,13 +2265,21 @@ using SegFn = void (*)(SolveParams);
 using GangFn = void (*)(SolveParams, int, int, int);
 
 template <typename YT>
-SegFn seg_kernel(int rpw, bool warm) {
+SegFn seg_kernel(int rpw, bool warm, bool tail) {
   if (warm) {
     switch (rpw) {
       case 64: return k_segment<YT, 64, true>;
       case 16: return k_segment<YT, 16, true>;
       case 4: return k_segment<YT, 4, true>;
       default: return k_segment<YT, 1, true>;
+    }
+  }
+  if (tail) {
+    switch (rpw) {
+      case 64: return k_segment<YT, 64, false, true>;
+      case 16: return k_segment<YT, 16, false, true>;
+      case 4: return k_segment<YT, 4, false, true>;
+      default: return k_segment<YT, 1, false, true>;
     }
   }
   switch (rpw) {
@@ -2129,8 +2315,8 @@ WarmGangFn gang_warm_kernel(int rpw) {
 WarmGangFn pick_gang_warm(int precision, int rpw) {
   return precision == PR_PREC_FP64 ? gang_warm_kernel<double>(rpw) : gang_warm_kernel<float>(rpw);
 }
-SegFn pick_segment(int precision, int rpw, bool warm = false) {
-  return precision == PR_PREC_FP64 ? seg_kernel<double>(rpw, warm) : seg_kernel<float>(rpw, warm);
+SegFn pick_segment(int precision, int rpw, bool warm = false, bool tail = false) {
+  return precision == PR_PREC_FP64 ? seg_kernel<double>(rpw, warm, tail) : seg_kernel<float>(rpw, warm, tail);
 }
 GangFn pick_gang(int precision, int rpw) {
   return precision == PR_PREC_FP64 ? gang_kernel<double>(rpw) : gang_kernel<float>(rpw);
@@ -2424,10 +2610,10 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
     lv.h_gang_nhub.push_back(gd.h1 - gd.h0);
     lv.h_gang_sccs.push_back({gd.s0, gd.s1});
   }
-  lv.h_gang_hint.assign(T.gangs.size(), 0);
+  lv.h_gang_hint.assign(2 * T.gangs.size(), 0);
   lv.phases = phases;
   // device copies
-  void* old[] = {lv.items, lv.gangs, lv.gsccs, lv.gbounds, lv.gpart, lv.gpmx, lv.gwsum, lv.gdone, lv.wgstats,
+  void* old[] = {lv.items, lv.gangs, lv.gsccs, lv.gbounds, lv.gpart, lv.gpmx, lv.gwsum, lv.gdone, lv.wgstats, lv.gpdiff, lv.gnhist,
                  lv.trace, lv.seg_heads, lv.ghubs, lv.gpieces, lv.gpiece_ptr, lv.gpiece_part, lv.ghub_pieces,
                  lv.warm_buf, lv.warm_gws, lv.mslot_ptr, lv.mslot_src};
   for (void* q : old)
@@ -2443,6 +2629,8 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   lv.gpart = nullptr;
   lv.gpmx = nullptr;
   lv.gwsum = nullptr;
+  lv.gpdiff = nullptr;
+  lv.gnhist = nullptr;
   lv.gdone = nullptr;
   lv.wgstats = nullptr;
   lv.trace = nullptr;
@@ -2508,6 +2696,8 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   PR_TRY(dalloc(&lv.gpart, 2 * (size_t)T.slots));
   PR_TRY(dalloc(&lv.gpmx, 2 * (size_t)T.slots));
   PR_TRY(dalloc(&lv.gwsum, T.sccs.size()));
+  PR_TRY(dalloc(&lv.gpdiff, 2 * (size_t)T.slots));
+  PR_TRY(dalloc(&lv.gnhist, 3 * T.sccs.size()));
   PR_TRY(dalloc(&lv.gdone, T.sccs.size()));
   PR_TRY(dalloc(&lv.wgstats, (size_t)lv.sgrid * kWgStats));
   PR_TRY(dalloc(&lv.seg_heads, std::max<size_t>(phases.size(), 1)));
@@ -2617,6 +2807,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.int_src = plain ? lv.full_src : lv.int_src;
   p.vpath = lv.vpath;
   p.direct_max = plain ? 0 : o.small_direct;
+  p.tail = (!plain && o.tail_estimate && o.stop == PR_STOP_CERT_L1) ? 1 : 0;
   p.mslot_ptr = lv.mslot_ptr;
   p.mslot_src = lv.mslot_src;
   p.inv32 = lv.inv_deg32;
@@ -2637,6 +2828,8 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.gpart = lv.gpart;
   p.gpmx = lv.gpmx;
   p.gwsum = lv.gwsum;
+  p.gpdiff = lv.gpdiff;
+  p.gnhist = lv.gnhist;
   p.gdone = lv.gdone;
   p.ghubs = lv.ghubs;
   p.gpieces = lv.gpieces;
@@ -2700,11 +2893,12 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   double sumW = 0.0;
   for (int i = 0; i < kRedBlocks; ++i) sumW += wparts[2 * i];
   const int64_t kb = term_bound(o, c, sumW);
-  const SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave, p.mlp != nullptr);
-  // the variant with the starting guess needs more registers: size its grid
-  // to what stays resident
+  if (p.mlp) p.tail = 0;  // the tail estimate is not used with a starting guess
+  const SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave, p.mlp != nullptr, p.tail != 0);
+  // the variants with the starting guess or the tail estimate need more
+  // registers: size their grid to what stays resident
   unsigned seg_grid = (unsigned)lv.grid;
-  if (p.mlp) {
+  if (p.mlp || p.tail) {
     int occ = 0, cus = 0;
     PR_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)seg, kThreads, 0));
     PR_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, lv.device));
@@ -2738,8 +2932,9 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   // plus a margin instead of the worst case; a solve whose gang reaches the
   // shorter bound without its stop rule is run again with the worst case, so
   // results never depend on the bound.
+  auto hint_at = [&](int gang) -> size_t { return (size_t)(p.tail ? 1 : 0) * lv.h_gang_sccs.size() + gang; };
   auto budget = [&](int gang) -> int64_t {
-    const int64_t h = lv.h_gang_hint[gang];
+    const int64_t h = lv.h_gang_hint[hint_at(gang)];
     return h > 0 ? std::min(kb, h + std::max<int64_t>(4, h / 4)) : kb;
   };
   std::vector<int> gangs_run;
@@ -2816,6 +3011,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     key = mix64(key, (uint64_t)kb);
     key = mix64(key, (uint64_t)(o.stop * 16 + o.precision * 4 + o.method));
     key = mix64(key, (uint64_t)o.small_direct);
+    key = mix64(key, (uint64_t)o.tail_estimate);
     key = mix64(key, (uint64_t)(uintptr_t)p.mlp);
     key = mix64(key, (uint64_t)(uintptr_t)p.gmlp);
     for (int gg : gangs_run) key = mix64(key, (uint64_t)budget(gg));
@@ -2881,10 +3077,10 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
       for (int32_t si = lv.h_gang_sccs[gg].first; si < lv.h_gang_sccs[gg].second; ++si)
         need = std::max<int64_t>(need, gd[si]);
       if (budget(gg) < kb && need >= budget(gg)) {
-        lv.h_gang_hint[gg] = 0;
+        lv.h_gang_hint[hint_at(gg)] = 0;
         cut = true;
       } else {
-        lv.h_gang_hint[gg] = std::max(lv.h_gang_hint[gg], need);
+        lv.h_gang_hint[hint_at(gg)] = std::max(lv.h_gang_hint[hint_at(gg)], need);
       }
     }
     if (cut) return solve_levels(lv, c, W, R, o, s, st);

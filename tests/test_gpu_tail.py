@@ -1,0 +1,118 @@
+"""GPU parity of the certified geometric tail estimate of SCC series (solve
+option tail_estimate) against the oracle's same rule and the dense solve."""
+import sys
+
+import numpy as np
+import pytest
+
+from graphgen import config_graph, csr_from_edges, random_digraph, scc_blocks
+from oracle.componentwise import componentwise_solve
+from oracle.pagerank import pagerank_dense, pagerank_power_series
+from oracle.partition import partition_theorem
+
+pytestmark = pytest.mark.gpu
+C = 0.85
+
+
+def _say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def prm():
+    import torch
+
+    import paper_1609_09068_amd as pr
+
+    assert torch.cuda.is_available()
+    return pr, torch
+
+
+def _run(prm, g, W, build, **opts):
+    pr, torch = prm
+    part = pr.pr_partition(g.row_ptr, g.col)
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col, **build)
+    Wd = torch.tensor(W, dtype=torch.float64, device="cuda")
+    Rd = torch.empty_like(Wd)
+    rc, st = pr.pr_solve(lv, C, Wd, Rd, **opts)
+    torch.cuda.synchronize()
+    return Rd.cpu().numpy(), rc, st, lv
+
+
+def test_cycle_stops_after_two_terms(prm):
+    m = 8
+    g = csr_from_edges(m, np.arange(m), (np.arange(m) + 1) % m)
+    for small in (64, 1):  # a wavefront, then a workgroup
+        _say("tail cycle small_cutoff", small)
+        R, rc, st, _ = _run(prm, g, np.ones(m), dict(small_cutoff=small), eps=1e-10, precision=1, tail_estimate=1)
+        assert rc == 0 and st["iters_max"] == 2
+        assert np.allclose(R, 1.0 / (1.0 - C), rtol=1e-13, atol=0)
+
+
+def _hub_graph(seed):
+    """A random digraph whose vertex 0 has more than 2048 in-edges (a gang
+    sums such a row in pieces) and lies in the giant SCC."""
+    g = random_digraph(3000, 9000, seed)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    s2 = np.concatenate([src, np.arange(1, g.n), [0] * 50])
+    d2 = np.concatenate([g.col, np.zeros(g.n - 1, np.int64), np.arange(1, 51)])
+    return csr_from_edges(g.n, s2, d2)
+
+
+# (small_cutoff, team_edges): wavefront and workgroup SCCs in a segment, the
+# large-component LDS path (team_edges above every SCC), and gangs (hub rows
+# included)
+@pytest.mark.parametrize("small,team", [(64, 1 << 30), (8, 1 << 30), (8, 256)])
+@pytest.mark.parametrize("seed", range(3))
+def test_fp64_matches_oracle_rule(prm, small, team, seed):
+    """Per-SCC term counts equal the oracle's tail rule (FP64) but for a
+    rounding tie, the result is within eps of the dense solve, and fewer terms
+    than the plain rule are taken."""
+    graphs = [scc_blocks(seed + 20, nblocks=40, max_size=60), random_digraph(2000, 6000, seed + 40)]
+    if team < 1 << 30:
+        graphs.append(_hub_graph(seed + 60))
+    for g in graphs:
+        W = np.random.default_rng(seed).uniform(0.5, 1.5, g.n)
+        _say("tail fp64 seed", seed, "small", small, "team", team, "n", g.n)
+        build = dict(small_cutoff=small, team_edges=team)
+        R, rc, st, lv = _run(prm, g, W, build, eps=1e-9, precision=1, tail_estimate=1)
+        _, _, st0, _ = _run(prm, g, W, build, eps=1e-9, precision=1)
+        assert rc == 0
+        Ro, sto = componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=1e-9, tail=True, return_stats=True)
+        part = partition_theorem(g.n, g.row_ptr, g.col)
+        scc = part["comp_type"] == 1
+        it = lv.debug("iters", n_comp=part["n_comp"])
+        d = np.abs(it[scc].astype(np.int64) - sto["iters"][scc])
+        assert d.max() <= 1 and np.count_nonzero(d) <= 2, (it[scc][d > 0], sto["iters"][scc][d > 0])
+        big = np.argmax(part["comp_size"][scc])
+        assert it[scc][big] == sto["iters"][scc][big]
+        Rd = pagerank_dense(g.n, g.row_ptr, g.col, C, W) if g.n <= 2500 else None
+        if Rd is not None:
+            assert np.abs(R - Rd).sum() / Rd.sum() <= 1e-9
+        assert np.abs(R - Ro).sum() / Ro.sum() <= 2e-9
+        assert st["iters_sum"] < st0["iters_sum"]
+        assert st["cert_rel"] <= 1e-9
+
+
+@pytest.mark.parametrize("team", [65536, 512])
+def test_config1_mixed_and_replay(prm, team):
+    pr, torch = prm
+    g = config_graph("c1_small")
+    W = np.ones(g.n)
+    ref, _, _ = pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-14)
+    part = pr.pr_partition(g.row_ptr, g.col)
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col, team_edges=team)
+    Wd = torch.tensor(W, device="cuda")
+    Re = torch.empty_like(Wd)
+    _say("tail c1 mixed team", team)
+    rc, st = pr.pr_solve(lv, C, Wd, Re, eps=1e-6, tail_estimate=1)
+    eager = Re.cpu().numpy()
+    assert rc == 0 and np.abs(eager - ref).sum() / ref.sum() <= 1e-6 and st["cert_rel"] <= 1e-6
+    Rg = torch.empty_like(Wd)
+    for rep in range(3):
+        _say("tail replay", rep)
+        Rg.fill_(-1.0)
+        rc, _ = pr.pr_solve(lv, C, Wd, Rg, eps=1e-6, tail_estimate=1, use_graph=1)
+        assert rc == 0 and np.array_equal(Rg.cpu().numpy(), eager)
+    with pytest.raises(pr.PRError):
+        pr.pr_solve(lv, C, Wd, Rg, tail_estimate=2)
