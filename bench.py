@@ -224,19 +224,21 @@ def run_tol_sweep(args, pr, torch, g, lv, info, W, R, t_part, t_build):
     rows = []
     AT = None
     for eps in (1e-2, 1e-4, 1e-6, 1e-8, 1e-10):
-        for meth, direct in ((0, 0), (0, 24), (1, 0)):
+        for meth, direct, tail in ((0, 0, 0), (0, 24, 0), (0, 0, 1), (1, 0, 0)):
             prec = 0 if eps >= 1e-6 else 1  # FP32 terms cannot certify below about 1e-7
             for _ in range(2):
-                pr.pr_solve(lv, args.c, W, R, method=meth, precision=prec, eps=eps, use_graph=1, small_direct=direct)
+                pr.pr_solve(lv, args.c, W, R, method=meth, precision=prec, eps=eps, use_graph=1, small_direct=direct,
+                            tail_estimate=tail)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(args.steps):
                 rc, st = pr.pr_solve(lv, args.c, W, R, method=meth, precision=prec, eps=eps, use_graph=1,
-                                     small_direct=direct)
+                                     small_direct=direct, tail_estimate=tail)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) / args.steps * 1e3
             bound, AT = residual_bound(g, args.c, R.cpu().numpy(), AT)
-            name = "plain" if meth == 1 else ("componentwise" + ("+small_direct" if direct else ""))
+            name = "plain" if meth == 1 else ("componentwise" + ("+small_direct" if direct else "")
+                                              + ("+tail_estimate" if tail else ""))
             row = {"eps": eps, "method": name,
                    "precision": "mixed" if prec == 0 else "fp64", "ms": round(ms, 3),
                    "terms_max": st["iters_max"], "edge_iters": st["edge_iters"], "cert_rel": st["cert_rel"],
@@ -391,6 +393,11 @@ def main():
     run(0, Rdir, 1, small_direct=24, **wopt)
     t_dir, st_dir = run(0, Rdir, args.steps, small_direct=24, **wopt)
     log(f"componentwise with small SCCs solved directly: {t_dir / args.steps * 1e3:.3f} ms/step")
+    # the SCC series stopped on the certified geometric tail estimate (plain start)
+    Rtl = torch.empty_like(W)
+    run(0, Rtl, 1, tail_estimate=1)
+    t_tl, st_tl = run(0, Rtl, args.steps, tail_estimate=1)
+    log(f"componentwise with the tail estimate: {t_tl / args.steps * 1e3:.3f} ms/step")
     # per-kernel durations: the same solves, eager, an event pair around every
     # launch on the solve stream (the events add a little host time per launch)
     t_ecw, st_ecw = run(0, R, args.steps, use_graph=0, kernel_timing=1, **wopt)
@@ -438,6 +445,7 @@ def main():
         acc = {"componentwise": float(np.abs(Rc - ref).sum() / ref.sum()),
                "componentwise_plain_start": float(np.abs(Rn.cpu().numpy() - ref).sum() / ref.sum()),
                "componentwise_small_direct": float(np.abs(Rdir.cpu().numpy() - ref).sum() / ref.sum()),
+               "componentwise_tail_estimate": float(np.abs(Rtl.cpu().numpy() - ref).sum() / ref.sum()),
                "plain": float(np.abs(Rpl - ref).sum() / ref.sum()),
                "cert_componentwise": s["cert_rel"], "cert_plain": sp["cert_rel"],
                "reference": f"oracle plain power series, FP64, eps 1e-12 ({kref} terms)"}
@@ -446,7 +454,9 @@ def main():
         b2, _ = residual_bound(g, args.c, Rn.cpu().numpy(), AT)
         b3, _ = residual_bound(g, args.c, Rp.cpu().numpy(), AT)
         b4, _ = residual_bound(g, args.c, Rdir.cpu().numpy(), AT)
+        b5, _ = residual_bound(g, args.c, Rtl.cpu().numpy(), AT)
         acc = {"componentwise": b1, "componentwise_plain_start": b2, "plain": b3, "componentwise_small_direct": b4,
+               "componentwise_tail_estimate": b5,
                "cert_componentwise": s["cert_rel"], "cert_plain": sp["cert_rel"],
                "reference": "bound from the oracle's FP64 residual ||W - (I - cA^T)R||_1 / ((1-c)||R||_1)"}
 
@@ -501,6 +511,7 @@ def main():
         "time_to_1e-6_ms": {"componentwise": round(ms_cw, 4), "plain": round(ms_pl, 4),
                             "componentwise_plain_start": round(t_cn / args.steps * 1e3, 4),
                             "componentwise_small_direct": round(t_dir / args.steps * 1e3, 4),
+                            "componentwise_tail_estimate": round(t_tl / args.steps * 1e3, 4),
                             "componentwise_device_eager": round(mcw["kernel_ms"], 4),
                             "plain_device_eager": round(mpl["kernel_ms"], 4),
                             "componentwise_eager_with_launch_events": round(t_ecw / args.steps * 1e3, 4),
@@ -512,7 +523,10 @@ def main():
                        "componentwise_terms_sum": s["iters_sum"], "plain_start_terms_sum": st_cn[-1]["iters_sum"],
                        "edge_iters_cw": s["edge_iters"], "edge_iters_cw_plain_start": st_cn[-1]["edge_iters"],
                        "edge_iters_plain": sp["edge_iters"],
-                       "componentwise_small_direct_terms_sum": st_dir[-1]["iters_sum"]},
+                       "componentwise_small_direct_terms_sum": st_dir[-1]["iters_sum"],
+                       "componentwise_tail_estimate_terms_sum": st_tl[-1]["iters_sum"],
+                       "componentwise_tail_estimate_max": st_tl[-1]["iters_max"],
+                       "edge_iters_cw_tail_estimate": st_tl[-1]["edge_iters"]},
         "starting_guess": None if net is None else {
             "network": os.path.relpath(args.warm_net, ROOT), "kept": s["ws_accepted"], "fell_back": s["ws_rejected"],
             "fallback_rate": round(s["ws_rejected"] / max(s["ws_accepted"] + s["ws_rejected"], 1), 4)},
