@@ -65,6 +65,9 @@ def componentwise_solve(n, row_ptr, col, c, W, *, part=None, stop="cert", eps=1e
     with R' when that is at most eps ||W'_C||_1 (the CERT rule's own bound).
     The plain test is tried first.  Its last-term norm is then the residual
     norm divided by c, so the certificate's c/(1-c) factor gives the bound.
+    With a starting guess the same rule runs on the residual series r_k of a
+    kept guess (rho from the second new term on: nothing precedes r_0) and
+    on the plain series of one that fell back.
 
     direct_max: SCCs of at most this many vertices are solved directly,
     (I - c A_CC^T) R_C = W'_C with a dense LAPACK solve: the paper's choice
@@ -205,7 +208,6 @@ def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter, f
     active = wnorm > 0 if stop == "cert" else np.ones(nc, dtype=bool)
     it = np.zeros(nc, dtype=np.int64)
     lastn = wnorm.copy()
-    k = 0
 
     def stop_test(pv):
         if stop == "cert":
@@ -235,27 +237,18 @@ def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter, f
         active = live.copy()
         active &= ~stop_test(p)
         p[~active[local]] = 0.0
-        while np.any(active) and int(it[active].max()) < max_iter:
-            p = c * (sub @ p)
-            p[~active[local]] = 0.0
-            acc += p
-            it[active] += 1
-            pn = np.bincount(local, weights=np.abs(p), minlength=nc)
-            lastn[active] = pn[active]
-            active &= ~stop_test(p)
-            active &= it < max_iter
-        R[Vs] = acc
-        iters[uniq] = it
-        last[uniq] = lastn
-        return
-    use_tail = tail and stop == "cert" and feat is None
-    norm_prev = wnorm.copy()            # ||P_k||_1 (k = 0: W'_C)
-    norm_prev2 = np.full(nc, np.nan)    # ||P_{k-1}||_1, unknown before P_1
-    while np.any(active) and k < max_iter:
+        # the series continues from the current term p: r_0 (nothing before
+        # it in this series) or P_1 (after P_0 = W'_C)
+        norm_prev = lastn.copy()
+        norm_prev2 = np.where(keep, np.nan, wnorm)
+    else:
+        norm_prev = wnorm.copy()            # ||P_k||_1 (k = 0: W'_C)
+        norm_prev2 = np.full(nc, np.nan)    # ||P_{k-1}||_1, unknown before P_1
+    use_tail = tail and stop == "cert"
+    while np.any(active) and int(it[active].max()) < max_iter:
         q = c * (sub @ p)
         q[~active[local]] = 0.0
-        k += 1
-        it[active] = k
+        it[active] += 1
         qn = np.bincount(local, weights=np.abs(q), minlength=nc)
         done = stop_test(q)
         acc_new = acc + q
@@ -278,6 +271,7 @@ def _scc_series(Vs, Wp, comp, c, AT, R, iters, last, stop, eps, tol, max_iter, f
         norm_prev2, norm_prev = norm_prev, qn
         p = q
         active &= ~done
+        active &= it < max_iter
     R[Vs] = acc
     iters[uniq] = it
     last[uniq] = lastn

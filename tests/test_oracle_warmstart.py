@@ -179,3 +179,82 @@ def test_bf16_bound_covers_emulated_rounding():
     bound = ws.forward_bf16_bound(th, X)
     assert np.all(err <= bound)
     assert err.max() > 0.0
+
+
+# ------------------------- the geometric tail estimate after a starting guess
+
+def test_tail_with_useless_guess_is_the_plain_start_tail():
+    """A guess that always falls back leaves the plain series, so the tail
+    rule must act exactly as without a guess (its rho starts from W'_C)."""
+    n, rp, col = _graph_with_sccs(15)
+    c = 0.85
+    W = np.random.default_rng(15).uniform(0.5, 1.5, n)
+    R0, st0 = componentwise_solve(n, rp, col, c, W, eps=1e-9, tail=True, return_stats=True)
+
+    def huge(F, Vs, s):
+        return np.full(len(Vs), 40.0)
+
+    R, st = componentwise_solve(n, rp, col, c, W, eps=1e-9, tail=True, return_stats=True, warm_fn=huge)
+    scc = st["accepted"] >= 0
+    assert (st["accepted"][scc] == 0).all()
+    np.testing.assert_array_equal(st["iters"], st0["iters"])
+    np.testing.assert_allclose(R, R0, rtol=1e-13)
+
+
+@pytest.mark.parametrize("m", [4, 7])
+def test_tail_with_kept_guess_on_a_cycle(m):
+    """Bare cycle, W = 1, guess R_0 = 0.5/(1-c) on every vertex: r_0 = 0.5
+    and r_k = 0.5 c^k, all uniform.  The guess is kept (0.5 < c), no ratio
+    exists before the second new term, and there the estimate is exact: two
+    new terms, R = 1/(1-c)."""
+    rp = np.arange(m + 1)
+    col = (np.arange(m) + 1) % m
+    c = 0.85
+
+    def half(F, Vs, s):
+        return np.log(0.5 / (1.0 - c) / s)
+
+    R, st = componentwise_solve(m, rp, col, c, np.ones(m), eps=1e-12, tail=True, return_stats=True, warm_fn=half)
+    assert st["accepted"].max() == 1
+    assert st["iters"].max() == 2
+    np.testing.assert_allclose(R, 1.0 / (1.0 - c), rtol=1e-14)
+
+
+@pytest.mark.parametrize("seed", [16, 17])
+def test_tail_with_noisy_guess_meets_the_bound(seed):
+    """Guesses within 5% of the answer (mostly kept): the result is within
+    eps of the dense solve, no SCC takes more terms than without the rule,
+    and each SCC's residual is at most c times its last-term norm (equal for
+    a tail stop: the rule's residual identity)."""
+    from graphgen import scc_blocks
+
+    g = scc_blocks(seed, nblocks=30, max_size=40)
+    n, rp, col = g.n, g.row_ptr, g.col
+    c = 0.85
+    eps = 1e-8
+    W = np.random.default_rng(seed).uniform(0.5, 1.5, n)
+    exact = pagerank_dense(n, rp, col, c, W)
+    noise = np.random.default_rng(seed + 1).uniform(-0.05, 0.05, n)
+
+    def noisy(F, Vs, s):
+        return np.log(exact[Vs] * (1.0 + noise[Vs]) / s)
+
+    R, st = componentwise_solve(n, rp, col, c, W, eps=eps, tail=True, return_stats=True, warm_fn=noisy)
+    _, st0 = componentwise_solve(n, rp, col, c, W, eps=eps, return_stats=True, warm_fn=noisy)
+    scc = st["accepted"] >= 0
+    assert (st["accepted"][scc] == 1).sum() > scc.sum() // 2
+    assert np.abs(R - exact).sum() / exact.sum() <= eps
+    assert np.all(st["iters"] <= st0["iters"]) and st["iters"].sum() < st0["iters"].sum()
+    from oracle.partition import partition_theorem
+    from oracle.pagerank import transition_T_csr
+
+    part = partition_theorem(n, rp, col)
+    AT = transition_T_csr(n, rp, col).toarray()
+    n_eq = 0
+    for C_ in np.nonzero(scc)[0]:
+        v = np.nonzero(part["comp"] == C_)[0]
+        res = np.abs(st["wprime"][v] - R[v] + c * AT[np.ix_(v, v)] @ R[v]).sum()
+        slack = 1e-14 * len(v) * np.abs(R[v]).max()  # rounding of the residual itself
+        assert res <= c * st["last"][C_] * (1 + 1e-8) + slack
+        n_eq += bool(abs(res - c * st["last"][C_]) <= slack)
+    assert n_eq > 0  # some SCCs did stop on the estimate
