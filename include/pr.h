@@ -190,13 +190,15 @@ typedef struct pr_solve_opts {
                            matrix is column diagonally dominant), the paper's choice for small
                            SCCs in the per-component method dispatch of Sec. 4.3.  Such an SCC
                            counts zero terms; its FP64 residual enters the certificate. */
-  int32_t tail_estimate;/* 1 = with PR_STOP_CERT_L1, an SCC iterated in a segment (by a wavefront or
-                           one workgroup) may also stop on a geometric estimate of the rest of its
-                           series: after term P_{k+1}, with rho = ||P_k||/||P_{k-1}|| < 1, it takes
+  int32_t tail_estimate;/* 1 = with PR_STOP_CERT_L1, every iterated SCC may also stop on a geometric
+                           estimate of the rest of its series (Sec. 4.3.2 series, Sec. 4.4 error):
+                           after term P_{k+1}, with rho = ||P_k||/||P_{k-1}|| < 1, it takes
                            R' = P_0 + ... + P_k + rho/(1-rho) P_k once ||P_{k+1} - rho P_k||_1 /
                            ((1-rho)(1-c)) <= eps ||W'_C||_1, which bounds ||R' - R*_C||_1 exactly as
                            the plain rule does (the residual of R' is (P_{k+1} - rho P_k)/(1-rho)).
-                           Not used with a starting guess nor in gang phases.  Default 0. */
+                           The plain test is tried first.  After a kept starting guess the rule
+                           runs on the residual series r_0, r_1, ... (rho from r_2 on).  Not
+                           combined with warm_scope = 1 (PR_EINVAL).  Default 0. */
   int32_t reserved[3];
 } pr_solve_opts;
 

@@ -1891,14 +1891,15 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
       } else {
         stop = stop_now(p, tot, mx, thresh);
       }
-      // certified tail estimate (no starting guess): gnhist slot j % 3 holds
-      // ||P_{j-1}||_1 from launch j; rho_t belongs to the difference term k-1
-      // carries, rho_k to the one this launch forms for term k
+      // certified tail estimate: gnhist slot j % 3 holds ||P_{j-1}||_1 from
+      // launch j (P_0 = r_0 after a kept guess); rho_t belongs to the
+      // difference term k-1 carries, rho_k to the one this launch forms
       const YT cy = (YT)c;
       double rho_t = -1.0;
       if (p.tail) {
         double* hist = p.gnhist + 3 * (size_t)si;
-        if (blockIdx.x == sc.wg_first && threadIdx.x == 0) hist[k % 3] = tot;
+        // launch 1: the first term's norm, r_0's for a kept starting guess
+        if (blockIdx.x == sc.wg_first && threadIdx.x == 0) hist[k % 3] = last;
         if (k >= 2 && hist[(k - 1) % 3] > 0.0) rho_k = tot / hist[(k - 1) % 3];
         if (k >= 3 && hist[(k - 2) % 3] > 0.0) rho_t = hist[(k - 1) % 3] / hist[(k - 2) % 3];
         if (!stop && rho_t > 0.0 && rho_t < 1.0 && dtot / (1.0 - rho_t) <= thresh) {
@@ -2893,7 +2894,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   double sumW = 0.0;
   for (int i = 0; i < kRedBlocks; ++i) sumW += wparts[2 * i];
   const int64_t kb = term_bound(o, c, sumW);
-  if (p.mlp) p.tail = 0;  // the tail estimate is not used with a starting guess
+  if (p.mlp) p.tail = 0;  // (refused at the boundary) the guessing segment variants do not carry the rule
   const SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave, p.mlp != nullptr, p.tail != 0);
   // the variants with the starting guess or the tail estimate need more
   // registers: size their grid to what stays resident

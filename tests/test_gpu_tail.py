@@ -116,3 +116,75 @@ def test_config1_mixed_and_replay(prm, team):
         assert rc == 0 and np.array_equal(Rg.cpu().numpy(), eager)
     with pytest.raises(pr.PRError):
         pr.pr_solve(lv, C, Wd, Rg, tail_estimate=2)
+
+
+def _const_net(pr, b3):
+    """A network whose output is b3 on every row (zero weights): the same
+    guess R_0 = s exp(b3) on the GPU and in the oracle."""
+    net = pr.Mlp.create(6)
+    th = np.zeros(4545, dtype=np.float32)
+    th[-1] = b3
+    net.set_params(th)
+    return net
+
+
+def test_gang_rejected_guess_with_tail_is_the_plain_start_tail(prm):
+    """Every SCC on the gang path with a guess that always falls back: the
+    tail rule must act exactly as without a guess, bit for bit."""
+    pr, torch = prm
+    from graphgen import small_plain
+
+    g = small_plain(seed=1)
+    W = np.random.default_rng(3).uniform(0.5, 2.0, g.n)
+    build = dict(small_cutoff=1, team_edges=1)
+    _say("tail + rejected guess, gangs")
+    R0, rc0, st0, lv0 = _run(prm, g, W, build, eps=1e-10, precision=1, tail_estimate=1)
+    R1, rc1, st1, lv1 = _run(prm, g, W, build, eps=1e-10, precision=1, tail_estimate=1,
+                             warm_start=_const_net(pr, 40.0))
+    assert rc0 == 0 and rc1 == 0
+    assert st1["ws_accepted"] == 0 and st1["ws_rejected"] == st1["n_iterated"] > 0
+    np.testing.assert_array_equal(R1, R0)
+    assert st1["iters_sum"] == st0["iters_sum"]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_gang_kept_guess_with_tail_matches_oracle(prm, precision):
+    """Every SCC on the gang path, constant guess kept for most SCCs: the
+    per-SCC term counts follow the oracle's rule (r_0 first, rho from r_2 on)
+    but for rounding ties (FP64 terms), the result is within eps, and the
+    rule saves terms over the guess alone."""
+    pr, torch = prm
+    from graphgen import small_plain
+
+    g = small_plain(seed=1)
+    W = np.random.default_rng(3).uniform(0.5, 2.0, g.n)
+    eps = 1e-10 if precision == 1 else 1e-6
+    ref, _, _ = pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-13)
+    build = dict(small_cutoff=1, team_edges=1)
+    net = _const_net(pr, 0.5)
+    _say("tail + kept guess, gangs, precision", precision)
+    R, rc, st, lv = _run(prm, g, W, build, eps=eps, precision=precision, tail_estimate=1, warm_start=net)
+    _, _, st0, _ = _run(prm, g, W, build, eps=eps, precision=precision, warm_start=net)
+    assert rc == 0
+    assert np.abs(R - ref).sum() / ref.sum() <= eps
+    assert st["ws_accepted"] == st0["ws_accepted"] > st["n_iterated"] // 2
+    assert st["iters_sum"] < st0["iters_sum"]
+    if precision == 1:
+        _, sto = componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=eps, tail=True, return_stats=True,
+                                     warm_fn=lambda F, Vs, s: np.full(len(Vs), 0.5))
+        part = partition_theorem(g.n, g.row_ptr, g.col)
+        scc = part["comp_type"] == 1
+        assert abs(st["ws_accepted"] - int((sto["accepted"] == 1).sum())) <= 2
+        it = lv.debug("iters", n_comp=part["n_comp"])
+        d = np.abs(it[scc].astype(np.int64) - sto["iters"][scc])
+        assert d.max() <= 1 and np.count_nonzero(d) <= 4, (it[scc][d > 0], sto["iters"][scc][d > 0])
+
+
+def test_tail_with_guess_on_every_scc_is_refused(prm):
+    pr, torch = prm
+    g = csr_from_edges(3, np.array([0, 1, 2]), np.array([1, 2, 0]))
+    part = pr.pr_partition(g.row_ptr, g.col)
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col)
+    Wd = torch.ones(3, dtype=torch.float64, device="cuda")
+    with pytest.raises(pr.PRError):
+        pr.pr_solve(lv, C, Wd, torch.empty_like(Wd), tail_estimate=1, warm_start=_const_net(pr, 0.5), warm_scope=1)
