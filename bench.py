@@ -2,11 +2,12 @@
 
 One step = one pr_solve of the componentwise method (Sec. 4.3: boundary
 mass, one-vertex components, CAC sweeps, SCC power series started from the
-learned guess where it passes the residual test, output) on the web-like
-graph of 1M vertices / 10M edges, with the plan resident on the device.  The
-same solve from the plain start and the plain whole-graph power series
-(Sec. 5.2, method 1) are timed the same way beside it.  All stop on the
-1-norm certificate at 1e-6.
+learned guess where it passes the residual test and stopped on the 1-norm
+certificate or on the certified geometric tail estimate, output) on the
+web-like graph of 1M vertices / 10M edges, with the plan resident on the
+device.  The same solve without the tail estimate, from the plain start, with
+small SCCs solved directly, and the plain whole-graph power series (Sec. 5.2,
+method 1) are timed the same way beside it.  All are certified to 1e-6.
 
 Prints ONE JSON line.  --gpus N > 1 is refused (single-GPU build).
 """
@@ -286,6 +287,8 @@ def main():
                     help="committed counter summary that supplies roofline.traffic "
                          "(default: profiles/hbm_traffic_<config>.json)")
     ap.add_argument("--no-warm", action="store_true", help="no starting guess in the headline step")
+    ap.add_argument("--tail-estimate", type=int, default=1, choices=[0, 1],
+                    help="headline step stops each SCC series on the certified geometric tail estimate")
     ap.add_argument("--warm-net", default=os.path.join(ROOT, "paper_1609_09068_amd", "data", "warm_web.prmlp"))
     ap.add_argument("--only", choices=["componentwise", "plain"],
                     help="run one method only (counter runs: one kernel family per method)")
@@ -364,7 +367,8 @@ def main():
         if meth == 0 and not args.no_warm and os.path.exists(args.warm_net):
             net = pr.Mlp.load_file(args.warm_net)
         for _ in range(args.warmup + args.steps):  # eager launches: one profiler record per kernel
-            run(meth, R, 1, use_graph=0, **(dict(warm_start=net) if net is not None else {}))
+            run(meth, R, 1, use_graph=0, **(dict(warm_start=net) if net is not None else {}),
+                **(dict(tail_estimate=args.tail_estimate) if meth == 0 else {}))
         if args.calib_copy_mb:
             calib_copy(torch, args.calib_copy_mb)
         log(f"{args.only}: {args.warmup + args.steps} solves done")
@@ -375,15 +379,21 @@ def main():
             raise SystemExit(f"bench.py: trained network {args.warm_net} missing (use --no-warm)")
         net = pr.Mlp.load_file(args.warm_net)
     wopt = dict(warm_start=net) if net is not None else {}
+    hopt = dict(wopt, tail_estimate=args.tail_estimate)  # the headline step
     Rn = torch.empty_like(W)
     for _ in range(args.warmup):
-        run(0, R, 1, **wopt)
+        run(0, R, 1, **hopt)
         run(0, Rn, 1)
         run(1, Rp, 1)
     mode = "hipGraph replay" if args.graph else "eager launches"
     log(f"warmup done; timing {args.steps} solves of each ({mode})")
-    t_cw, st_cw = run(0, R, args.steps, **wopt)
-    log(f"componentwise{' + starting guess' if net else ''}: {t_cw / args.steps * 1e3:.3f} ms/step")
+    t_cw, st_cw = run(0, R, args.steps, **hopt)
+    log(f"componentwise{' + starting guess' if net else ''}{' + tail estimate' if args.tail_estimate else ''}: "
+        f"{t_cw / args.steps * 1e3:.3f} ms/step")
+    Rg = torch.empty_like(W)
+    run(0, Rg, 1, **wopt)
+    t_cg, st_cg = run(0, Rg, args.steps, **wopt)
+    log(f"componentwise{' + starting guess' if net else ''}, plain stop rule: {t_cg / args.steps * 1e3:.3f} ms/step")
     t_cn, st_cn = run(0, Rn, args.steps)
     log(f"componentwise, plain start: {t_cn / args.steps * 1e3:.3f} ms/step")
     t_pl, st_pl = run(1, Rp, args.steps)
@@ -397,10 +407,10 @@ def main():
     Rtl = torch.empty_like(W)
     run(0, Rtl, 1, tail_estimate=1)
     t_tl, st_tl = run(0, Rtl, args.steps, tail_estimate=1)
-    log(f"componentwise with the tail estimate: {t_tl / args.steps * 1e3:.3f} ms/step")
+    log(f"componentwise, plain start, tail estimate: {t_tl / args.steps * 1e3:.3f} ms/step")
     # per-kernel durations: the same solves, eager, an event pair around every
     # launch on the solve stream (the events add a little host time per launch)
-    t_ecw, st_ecw = run(0, R, args.steps, use_graph=0, kernel_timing=1, **wopt)
+    t_ecw, st_ecw = run(0, R, args.steps, use_graph=0, kernel_timing=1, **hopt)
     t_epl, st_epl = run(1, Rp, args.steps, use_graph=0, kernel_timing=1)
     log(f"eager with launch events: componentwise {t_ecw / args.steps * 1e3:.3f} ms/step, "
         f"plain {t_epl / args.steps * 1e3:.3f} ms/step")
@@ -445,7 +455,8 @@ def main():
         acc = {"componentwise": float(np.abs(Rc - ref).sum() / ref.sum()),
                "componentwise_plain_start": float(np.abs(Rn.cpu().numpy() - ref).sum() / ref.sum()),
                "componentwise_small_direct": float(np.abs(Rdir.cpu().numpy() - ref).sum() / ref.sum()),
-               "componentwise_tail_estimate": float(np.abs(Rtl.cpu().numpy() - ref).sum() / ref.sum()),
+               "componentwise_plain_start_tail_estimate": float(np.abs(Rtl.cpu().numpy() - ref).sum() / ref.sum()),
+               "componentwise_guess_plain_stop": float(np.abs(Rg.cpu().numpy() - ref).sum() / ref.sum()),
                "plain": float(np.abs(Rpl - ref).sum() / ref.sum()),
                "cert_componentwise": s["cert_rel"], "cert_plain": sp["cert_rel"],
                "reference": f"oracle plain power series, FP64, eps 1e-12 ({kref} terms)"}
@@ -455,8 +466,9 @@ def main():
         b3, _ = residual_bound(g, args.c, Rp.cpu().numpy(), AT)
         b4, _ = residual_bound(g, args.c, Rdir.cpu().numpy(), AT)
         b5, _ = residual_bound(g, args.c, Rtl.cpu().numpy(), AT)
+        b6, _ = residual_bound(g, args.c, Rg.cpu().numpy(), AT)
         acc = {"componentwise": b1, "componentwise_plain_start": b2, "plain": b3, "componentwise_small_direct": b4,
-               "componentwise_tail_estimate": b5,
+               "componentwise_plain_start_tail_estimate": b5, "componentwise_guess_plain_stop": b6,
                "cert_componentwise": s["cert_rel"], "cert_plain": sp["cert_rel"],
                "reference": "bound from the oracle's FP64 residual ||W - (I - cA^T)R||_1 / ((1-c)||R||_1)"}
 
@@ -469,7 +481,7 @@ def main():
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
             Ro, sto = componentwise_solve(g.n, g.row_ptr, g.col, args.c, np.ones(g.n), eps=args.eps,
-                                          return_stats=True)
+                                          return_stats=True, tail=bool(args.tail_estimate))
             t_or = time.perf_counter() - t0
         part_d = part.as_dict()
         scc = part_d["comp_type"] == 1
@@ -480,7 +492,8 @@ def main():
         e_iter_or = float(np.sum(sto["iters"][scc] * e_int[scc])) + (info["m_between"] + info["m_cac_internal"])
         cpu = {"value": round(e_iter_or / t_or / 1e9, 5), "unit": "GEdge-iter/s", "cores": 1, "kind": "oracle",
                "sample": f"the whole {args.config} solve: serial componentwise oracle (numpy/scipy, FP64, "
-                         f"1 thread), eps {args.eps}, {t_or:.2f} s",
+                         f"1 thread, plain start{', tail estimate' if args.tail_estimate else ''}), "
+                         f"eps {args.eps}, {t_or:.2f} s",
                "time_to_1e-6_ms": round(t_or * 1e3, 1), "host_cores_available": len(os.sched_getaffinity(0))}
         log(f"cpu oracle {t_or:.2f}s")
 
@@ -500,18 +513,21 @@ def main():
         "config": {"workload": f"{args.config}: {'Barabasi-Albert' if 'ba_' in args.config else 'web-like'} "
                                f"graph n={g.n} m={g.m}, c={args.c}, "
                                f"1-norm certificate eps={args.eps}, W=1, componentwise solve"
-                               f"{' with the learned starting guess' if net is not None else ''}, plan resident",
+                               f"{' with the learned starting guess' if net is not None else ''}"
+                               f"{' and the tail-estimate stop' if args.tail_estimate else ''}, plan resident",
                    "n": g.n, "m": g.m, "levels": info["n_levels"], "components": info["n_comp"],
                    "scc": info["n_scc"], "scc_vertices": info["v_scc"], "m_scc_internal": info["m_scc_internal"],
                    "m_between": info["m_between"], "m_cac_internal": info["m_cac_internal"],
                    "gang_vertices": info["v_gang"], "rows_per_wave": info["rows_per_wave"],
                    "small_cutoff": info["small_cutoff"], "team_edges": info["team_edges"],
                    "grid_wgs": info["grid_wgs"], "hipgraph": bool(args.graph),
+                   "tail_estimate": bool(args.tail_estimate),
                    "autotuned": bool(bopts.get("autotune", 0))},
         "time_to_1e-6_ms": {"componentwise": round(ms_cw, 4), "plain": round(ms_pl, 4),
                             "componentwise_plain_start": round(t_cn / args.steps * 1e3, 4),
                             "componentwise_small_direct": round(t_dir / args.steps * 1e3, 4),
-                            "componentwise_tail_estimate": round(t_tl / args.steps * 1e3, 4),
+                            "componentwise_plain_start_tail_estimate": round(t_tl / args.steps * 1e3, 4),
+                            "componentwise_guess_plain_stop": round(t_cg / args.steps * 1e3, 4),
                             "componentwise_device_eager": round(mcw["kernel_ms"], 4),
                             "plain_device_eager": round(mpl["kernel_ms"], 4),
                             "componentwise_eager_with_launch_events": round(t_ecw / args.steps * 1e3, 4),
@@ -524,9 +540,10 @@ def main():
                        "edge_iters_cw": s["edge_iters"], "edge_iters_cw_plain_start": st_cn[-1]["edge_iters"],
                        "edge_iters_plain": sp["edge_iters"],
                        "componentwise_small_direct_terms_sum": st_dir[-1]["iters_sum"],
-                       "componentwise_tail_estimate_terms_sum": st_tl[-1]["iters_sum"],
-                       "componentwise_tail_estimate_max": st_tl[-1]["iters_max"],
-                       "edge_iters_cw_tail_estimate": st_tl[-1]["edge_iters"]},
+                       "plain_start_tail_estimate_terms_sum": st_tl[-1]["iters_sum"],
+                       "guess_plain_stop_terms_sum": st_cg[-1]["iters_sum"],
+                       "edge_iters_cw_plain_start_tail_estimate": st_tl[-1]["edge_iters"],
+                       "edge_iters_cw_guess_plain_stop": st_cg[-1]["edge_iters"]},
         "starting_guess": None if net is None else {
             "network": os.path.relpath(args.warm_net, ROOT), "kept": s["ws_accepted"], "fell_back": s["ws_rejected"],
             "fallback_rate": round(s["ws_rejected"] / max(s["ws_accepted"] + s["ws_rejected"], 1), 4)},
