@@ -1753,9 +1753,9 @@ __device__ inline GangCtx gang_ctx(const SolveParams& p, const GangDesc& gd) {
 }
 
 // deterministic sum (and max) of an SCC's partials from launch `parity`;
-// with `dtot`, also the sum of its tail-estimate partials
+// with `want_d`, also the sum of its tail-estimate partials (else 0)
 __device__ inline void gang_total(const SolveParams& p, const GangScc& sc, int parity, double* red, double* tot,
-                                  double* mx, double* dtot = nullptr) {
+                                  double* mx, bool want_d, double& dtot) {
   const int cnt = sc.nslot;
   const size_t off = (size_t)parity * p.n_gslots + sc.pbase;
   const double* pp = p.gpart + off;
@@ -1764,11 +1764,11 @@ __device__ inline void gang_total(const SolveParams& p, const GangScc& sc, int p
   for (int j = threadIdx.x; j < cnt; j += kThreads) {
     s += pp[j];
     m = fmax(m, pm[j]);
-    if (dtot) d += p.gpdiff[off + j];
+    if (want_d) d += p.gpdiff[off + j];
   }
   *tot = block_sum(s, red);
   *mx = block_max(m, red);
-  if (dtot) *dtot = block_sum(d, red);
+  dtot = want_d ? block_sum(d, red) : 0.0;
 }
 
 __device__ inline void gang_finalise(const SolveParams& p, const GangScc& sc, const GangCtx& g, int64_t iters,
@@ -1871,7 +1871,7 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
       }
     } else {
       double tot, mx, dtot = 0.0;
-      gang_total(p, sc, par_r, s_red, &tot, &mx, p.tail ? &dtot : nullptr);
+      gang_total(p, sc, par_r, s_red, &tot, &mx, p.tail != 0, dtot);
       double wsum;
       if (k == 1) {
         wsum = tot;
@@ -2061,8 +2061,8 @@ __global__ __launch_bounds__(kThreads) void k_gang_warm(SolveParams p, int gang,
     const int w1 = wave == kWaves - 1 ? z : find_row(tot_w * (wave + 1) / kWaves);
     const size_t slot = (size_t)sc.pbase + (blockIdx.x - sc.wg_first);
     if (step == 0) {
-      double tot, mx;
-      gang_total(p, sc, 0, s_red, &tot, &mx);  // ||W'_C||_1 from term 0's partials
+      double tot, mx, dnone;
+      gang_total(p, sc, 0, s_red, &tot, &mx, false, dnone);  // ||W'_C||_1 from term 0's partials
       const double sC = tot / (double)(sc.vend - sc.vbeg);
       double np1 = 0.0;
       for (int ra = w0; ra < w1; ra += 64) {
@@ -2146,8 +2146,8 @@ __global__ __launch_bounds__(kThreads) void k_gang_warm_net(SolveParams p, int g
   for (int si = g.s_lo; si < g.s_hi; ++si) {
     const GangScc sc = p.gscc[si];
     const int a = sc.vbeg > g.r0 ? sc.vbeg : g.r0, z = sc.vend < g.r1 ? sc.vend : g.r1;
-    double tot, mx;
-    gang_total(p, sc, 0, s_red, &tot, &mx);  // ||W'_C||_1 from term 0's partials
+    double tot, mx, dnone;
+    gang_total(p, sc, 0, s_red, &tot, &mx, false, dnone);  // ||W'_C||_1 from term 0's partials
     const double sC = tot / (double)(sc.vend - sc.vbeg);
     for (int ra = a + 64 * wave; ra < z; ra += kThreads) {  // wave-uniform trip count
       const int v = ra + lane;
