@@ -1,5 +1,6 @@
 """GPU parity of the certified geometric tail estimate of SCC series (solve
 option tail_estimate) against the oracle's same rule and the dense solve."""
+import itertools
 import sys
 
 import numpy as np
@@ -191,11 +192,12 @@ def test_tail_with_guess_on_every_scc_is_refused(prm):
 
 
 def test_web_1m_in_the_timed_launch_shape(prm):
-    """The 1M-vertex / 10M-edge web-like graph in the launch shape the
-    benchmark's autotuner picked (rows per wave 64, small cutoff 16, gang
-    threshold 16384 edges), hipGraph replay, mixed precision, eps 1e-6: the
-    trained starting guess with the tail estimate, and the plain start with
-    it, both within 1e-6 of the oracle's FP64 series, certificates included."""
+    """The 1M-vertex / 10M-edge web-like graph in the launch shapes the
+    benchmark's autotuner picks (rows per wave 64, small cutoff 16, gang
+    threshold 16384 or 65536 edges), hipGraph replay, mixed precision, eps
+    1e-6: the trained starting guess with the tail estimate, and the plain
+    start with it, both within 1e-6 of the oracle's FP64 series, certificates
+    included."""
     import os
 
     pr, torch = prm
@@ -203,14 +205,14 @@ def test_web_1m_in_the_timed_launch_shape(prm):
     W = np.ones(g.n)
     ref, _, _ = pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-12)
     part = pr.pr_partition(g.row_ptr, g.col)
-    lv = pr.pr_build_levels(part, g.row_ptr, g.col, rows_per_wave=64, small_cutoff=16, team_edges=16384)
     path = os.path.join(os.path.dirname(pr.__file__), "data", "warm_web.prmlp")
     net = pr.Mlp.load_file(path)
     Wd = torch.tensor(W, device="cuda")
-    for opts in (dict(warm_start=net), {}):
-        R = torch.empty_like(Wd)
-        for rep in range(2):
-            _say("web 1m timed shape", sorted(opts), "replay", rep)
+    R = torch.empty_like(Wd)
+    for team in (16384, 65536):
+        lv = pr.pr_build_levels(part, g.row_ptr, g.col, rows_per_wave=64, small_cutoff=16, team_edges=team)
+        for opts, rep in itertools.product((dict(warm_start=net), {}), range(2)):
+            _say("web 1m timed shape team", team, sorted(opts), "replay", rep)
             R.fill_(-1.0)
             rc, st = pr.pr_solve(lv, C, Wd, R, eps=1e-6, precision=0, tail_estimate=1, use_graph=1, **opts)
             assert rc == 0
