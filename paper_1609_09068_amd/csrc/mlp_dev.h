@@ -74,7 +74,7 @@ __device__ inline float gelu_grad(float x) {
 // Forward pass of one block of 16 rows.  xb: the B operand of the features
 // (lanes 0..15 hold the four features of row l, other lanes zero).  Returns
 // the output of row l % 16 on lanes 0..15 (other lanes: unspecified).
-__device__ inline float mlp_forward16(const MlpPacked& w, bf16x4 xb) {
+__device__ __attribute__((always_inline)) inline float mlp_forward16(const MlpPacked& w, bf16x4 xb) {
   const int lane = threadIdx.x & 63;
   const int hb = 4 * (lane >> 4);  // first hidden unit of this lane within a tile
   bf16x4 h1[4];
@@ -106,7 +106,7 @@ __device__ inline float mlp_forward16(const MlpPacked& w, bf16x4 xb) {
 // lane's row; inactive lanes pass anything).  Returns the lane's output.
 // The weights are read from memory (L1/L2) for each block rather than held
 // in registers, so a kernel that embeds this keeps its register budget.
-__device__ inline float mlp_forward64(const MlpPacked& w, float f0, float f1, float f2, float f3) {
+__device__ __attribute__((always_inline)) inline float mlp_forward64(const MlpPacked& w, float f0, float f1, float f2, float f3) {
   const int lane = threadIdx.x & 63;
   float out = 0.f;
 #pragma unroll 1

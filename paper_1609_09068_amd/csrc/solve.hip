@@ -390,7 +390,7 @@ struct WaveTile {
 };
 
 template <int RPW, typename VT, bool WAIT_X>
-__device__ VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const int32_t* src, const VT* val,
+__device__ __attribute__((always_inline)) VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const int32_t* src, const VT* val,
                                int ra, int nr, WaveTile* t) {
   constexpr int LPR = 64 / RPW;
   const int lane = threadIdx.x & 63;
@@ -848,7 +848,7 @@ struct WarmOut {
 };
 
 template <int G>
-__device__ WarmOut warm_preamble(const SolveParams& p, int vbeg, int nv, double wsum, double* red) {
+__device__ __attribute__((always_inline)) WarmOut warm_preamble(const SolveParams& p, int vbeg, int nv, double wsum, double* red) {
   const int tid = G == 64 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
   auto gsum = [&](double v) { return G == 64 ? wave_sum(v) : block_sum(v, red); };
   auto gmax = [&](double v) { return G == 64 ? wave_max(v) : block_max(v, red); };
@@ -1661,7 +1661,7 @@ static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + kThrea
 // handed out before it, and those are held by running workgroups; the
 // lowest unfinished item has nothing left to wait for.
 template <typename YT, int RPW, bool WARM, bool TAIL = false>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((WARM || RPW == 1) ? 1 : ((TAIL || RPW < 16) ? 2 : 3)))) void k_segment(SolveParams p) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ? 1 : ((TAIL || RPW < 16) ? 2 : 3)))) void k_segment(SolveParams p) {
   __shared__ double s_red[24];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kSegLds];
   __shared__ unsigned long long s_stats[kWgStats];
