@@ -218,6 +218,14 @@ __device__ inline T wave_sum(T v) {
   v = row16_sum(v);
   return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
 }
+// two wavefront sums at once (independent chains, each in wave_sum's order)
+template <typename T>
+__device__ inline void wave_sum2(T a, T b, T& sa, T& sb) {
+  a = row16_sum(a);
+  b = row16_sum(b);
+  sa = (readlane(a, 0) + readlane(a, 16)) + (readlane(a, 32) + readlane(a, 48));
+  sb = (readlane(b, 0) + readlane(b, 16)) + (readlane(b, 32) + readlane(b, 48));
+}
 template <typename T>
 __device__ inline T wave_max(T v) {
   v = row16_max(v);
@@ -1071,6 +1079,10 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     while (k < p.max_iter) {
       ++k;
+      // the tail estimate's ratio is known before the term (its division
+      // overlaps the gathers)
+      const double rho = (tail && nprev2 > 0.0) ? nprev / nprev2 : -1.0;
+      const bool rho_ok = rho > 0.0 && rho < 1.0;
       // all gathers issued before any is used (one LDS wait); unused slots
       // read the zero pad
       YT g[16];
@@ -1107,23 +1119,21 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
       ya = yb;
       yb = t;
       if (cert) {
-        const double norm = wave_sum(sd);
+        double norm, dsum = 0.0;  // both sums in one pass
+        if (rho_ok) wave_sum2(sd, act ? fabs((double)sv - rho * svp) : 0.0, norm, dsum);
+        else norm = wave_sum(sd);
         last = norm;
         if (norm <= thresh) {
           conv = true;
           break;
         }
+        if (rho_ok && dsum <= thresh * (1.0 - rho)) {  // R' = R - P_k + rho/(1-rho) P_{k-1}
+          R0 += rho / (1.0 - rho) * svp - (double)sv;
+          last = dsum / (1.0 - rho) / p.c;
+          conv = true;
+          break;
+        }
         if (tail) {
-          const double rho = nprev2 > 0.0 ? nprev / nprev2 : -1.0;
-          if (rho > 0.0 && rho < 1.0) {
-            const double res = wave_sum(act ? fabs((double)sv - rho * svp) : 0.0) / (1.0 - rho);
-            if (res <= thresh) {  // R' = R - P_k + rho/(1-rho) P_{k-1}
-              R0 += rho / (1.0 - rho) * svp - (double)sv;
-              last = res / p.c;
-              conv = true;
-              break;
-            }
-          }
           nprev2 = nprev;
           nprev = norm;
           svp = (double)sv;
@@ -1185,7 +1195,9 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      const double norm = wave_sum(part);
+      double norm, dsum = 0.0;
+      if (rho_ok) wave_sum2(part, dd, norm, dsum);
+      else norm = wave_sum(part);
       const double mx = wave_max(pm);
       last = norm;
       YT* t = ya;
@@ -1195,18 +1207,16 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
         conv = true;
         break;
       }
-      if (rho_ok) {
-        const double res = wave_sum(dd) / (1.0 - rho);
-        if (res <= thresh) {  // R' = R - P_k + rho/(1-rho) P_{k-1}; ya: P_k, yb: P_{k-1}
+      if (rho_ok && dsum <= thresh * (1.0 - rho)) {
+        // R' = R - P_k + rho/(1-rho) P_{k-1}; ya: P_k, yb: P_{k-1}
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int i = lane + 64 * j;
-            if (i < nv) Rj[j] += (rho / (1.0 - rho) * (double)yb[i] - (double)ya[i]) / scale(j, i);
-          }
-          last = res / p.c;
-          conv = true;
-          break;
+        for (int j = 0; j < 4; ++j) {
+          const int i = lane + 64 * j;
+          if (i < nv) Rj[j] += (rho / (1.0 - rho) * (double)yb[i] - (double)ya[i]) / scale(j, i);
         }
+        last = dsum / (1.0 - rho) / p.c;
+        conv = true;
+        break;
       }
       nprev2 = nprev;
       nprev = norm;
@@ -1415,7 +1425,7 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
           conv = true;
           break;
         }
-        if (rho_ok && dsum / (1.0 - rho) <= thresh) {  // lb: P_{k-1}, la: P_k; a thread's rows only
+        if (rho_ok && dsum <= thresh * (1.0 - rho)) {  // lb: P_{k-1}, la: P_k; a thread's rows only
           for (int r = threadIdx.x; r < nv; r += kThreads) {
             const double sc = (double)cy * (double)linv[r];
             lR[r] += rho / (1.0 - rho) * ((double)lb[r] / sc) - (double)la[r] / sc;
@@ -1542,7 +1552,7 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
           conv = true;
           break;
         }
-        if (rho_ok && dsum / (1.0 - rho) <= thresh) {  // R' = R - P_k + rho/(1-rho) P_{k-1}
+        if (rho_ok && dsum <= thresh * (1.0 - rho)) {  // R' = R - P_k + rho/(1-rho) P_{k-1}
 #pragma unroll
           for (int j = 0; j < kRPT; ++j) {
             const int r = threadIdx.x + kThreads * j;
@@ -1606,7 +1616,7 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
           conv = true;
           break;
         }
-        if (rho_ok && dsum / (1.0 - rho) <= thresh) {  // yb: P_{k-1}, ya: P_k; a lane's own rows
+        if (rho_ok && dsum <= thresh * (1.0 - rho)) {  // yb: P_{k-1}, ya: P_k; a lane's own rows
           for (int v = w0 + lane; v < w1; v += 64) {
             double iv;
             if constexpr (sizeof(YT) == 8) iv = p.inv64[v];
@@ -1902,7 +1912,7 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
         if (blockIdx.x == sc.wg_first && threadIdx.x == 0) hist[k % 3] = last;
         if (k >= 2 && hist[(k - 1) % 3] > 0.0) rho_k = tot / hist[(k - 1) % 3];
         if (k >= 3 && hist[(k - 2) % 3] > 0.0) rho_t = hist[(k - 1) % 3] / hist[(k - 2) % 3];
-        if (!stop && rho_t > 0.0 && rho_t < 1.0 && dtot / (1.0 - rho_t) <= thresh) {
+        if (!stop && rho_t > 0.0 && rho_t < 1.0 && dtot <= thresh * (1.0 - rho_t)) {
           // R' = R - P_{k-1} + rho/(1-rho) P_{k-2}: the terms come back from
           // the term buffers (c P / outdeg), each row by the thread that
           // finalises it
