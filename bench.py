@@ -303,7 +303,7 @@ def main():
     if args.traffic is None:
         args.traffic = os.path.join(ROOT, "profiles", f"hbm_traffic_{args.config}.json")
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
