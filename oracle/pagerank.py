@@ -59,6 +59,24 @@ def pagerank_dense(n, row_ptr, col, c, W, loops=False):
     return np.linalg.solve(np.eye(n) - c * A.T, np.asarray(W, dtype=np.float64))
 
 
+def pagerank_dense_weighted(n, row_ptr, col, weight, c, W, loops=False):
+    """R^(3) of Def. 3.4/3.5 for a weighted graph (a Markov chain's
+    transition weights): a_uv = w_uv / sum_x w_ux over the out-edges of u
+    (repeated edges add their weights; loops dropped unless loops=True),
+    then the dense solve (I - c A^T) R = W."""
+    weight = np.asarray(weight, dtype=np.float64)
+    A = np.zeros((n, n), dtype=np.float64)
+    for u in range(n):
+        for e in range(int(row_ptr[u]), int(row_ptr[u + 1])):
+            v = int(col[e])
+            if v != u or loops:
+                A[u, v] += weight[e]
+    s = A.sum(axis=1)
+    nz = s > 0
+    A[nz] /= s[nz, None]
+    return np.linalg.solve(np.eye(n) - c * A.T, np.asarray(W, dtype=np.float64))
+
+
 def pagerank_r1(n, row_ptr, col, c, w):
     """R^(1) of Def. 3.4: the eigenvector of M = c(A + g w^T)^T + (1-c) w e^T
     for eigenvalue one, scaled to unit 1-norm (numpy eigen-solver)."""
