@@ -11,7 +11,10 @@
  * scaled to sum to one (Def. 3.4).  Self-loops are ignored by default, as in
  * the experiments (Sec. 5.2), or kept in A with the build option keep_loops
  * (the general definition); the partition never depends on them.  A
- * repeated edge counts with its multiplicity in A and in the out-degree.
+ * repeated edge counts with its multiplicity in A and in the out-degree, so
+ * a weighted graph with integer weights (a Markov chain's transition
+ * weights, a_uv = w_uv / sum_x w_ux) is passed exactly by repeating an edge
+ * of weight k k times.
  *
  * Conventions for every entry point
  *  - A graph is CSR over out-edges: row_ptr[n+1] (int64, row_ptr[0] == 0,

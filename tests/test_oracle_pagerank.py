@@ -399,3 +399,59 @@ def test_tail_planted_wrong_candidate_is_caught():
     assert np.allclose(r_right, (p2 - rho * p1) / (1 - rho), atol=1e-12)  # the identity the rule uses
     r_wrong = W - wrong + C * (AT @ wrong)
     assert not np.allclose(r_wrong, (p2 - rho * p1) / (1 - rho), atol=1e-6)
+
+
+# ------------------------------------------- weighted graphs (Markov chains)
+
+def test_weighted_closed_form():
+    """0 -> 1 (weight 3), 0 -> 2 (weight 1), 1 -> 0, 2 a sink; W = 1:
+    R_0 = 1 + c R_1, R_1 = 1 + (3/4) c R_0, R_2 = 1 + (1/4) c R_0, so
+    R_0 = (1 + c) / (1 - 3c^2/4)."""
+    rp = np.array([0, 2, 3, 3])
+    col = np.array([1, 2, 0])
+    w = np.array([3.0, 1.0, 1.0])
+    R = PR.pagerank_dense_weighted(3, rp, col, w, C, np.ones(3))
+    r0 = (1 + C) / (1 - 0.75 * C * C)
+    np.testing.assert_allclose(R, [r0, 1 + 0.75 * C * r0, 1 + 0.25 * C * r0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_unit_weights_are_the_unweighted_definition(seed):
+    g = random_digraph(60, 240, seed + 70, loops=True, duplicates=True)
+    W = np.random.default_rng(seed).uniform(0.5, 1.5, g.n)
+    for loops in (False, True):
+        np.testing.assert_allclose(PR.pagerank_dense_weighted(g.n, g.row_ptr, g.col, np.ones(g.m), C, W, loops),
+                                   PR.pagerank_dense(g.n, g.row_ptr, g.col, C, W, loops), rtol=1e-13)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_integer_weights_as_parallel_edges(seed):
+    """An edge of integer weight k passed as k parallel edges (the library's
+    input form for weighted graphs) gives the weighted definition, through
+    the componentwise oracle and the plain series alike."""
+    from paper_1609_09068_amd.weights import expand_integer_weights
+
+    g = random_digraph(300, 1000, seed + 80)
+    w = np.random.default_rng(seed).integers(1, 6, g.m)
+    W = np.random.default_rng(seed + 1).uniform(0.5, 1.5, g.n)
+    Rw = PR.pagerank_dense_weighted(g.n, g.row_ptr, g.col, w, C, W)
+    rp2, col2 = expand_integer_weights(g.row_ptr, g.col, w)
+    assert rp2[-1] == w.sum()
+    R = CW.componentwise_solve(g.n, rp2, col2, C, W, eps=1e-13)
+    np.testing.assert_allclose(R, Rw, rtol=1e-11)
+    Rp, _, _ = PR.pagerank_power_series(g.n, rp2, col2, C, W, eps=1e-13)
+    np.testing.assert_allclose(Rp, Rw, rtol=1e-11)
+    # a planted mistake: ignoring the weights is far off
+    assert not np.allclose(CW.componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=1e-13), Rw, rtol=1e-3)
+
+
+def test_weight_expansion_validates_and_drops_zero_weights():
+    from paper_1609_09068_amd.weights import expand_integer_weights
+
+    rp = np.array([0, 2, 3, 3])
+    col = np.array([1, 2, 0])
+    rp2, col2 = expand_integer_weights(rp, col, [2, 0, 3])
+    assert rp2.tolist() == [0, 2, 5, 5] and col2.tolist() == [1, 1, 0, 0, 0]
+    for bad in ([1.5, 1, 1], [1, -1, 1], [1, 1]):
+        with pytest.raises(ValueError):
+            expand_integer_weights(rp, col, bad)
