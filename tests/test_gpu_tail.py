@@ -219,3 +219,45 @@ def test_web_1m_in_the_timed_launch_shape(prm):
             err = np.abs(R.cpu().numpy() - ref).sum() / ref.sum()
             assert err <= 1e-6 and st["cert_rel"] <= 1e-6, (err, st["cert_rel"])
             assert st["n_not_converged"] == 0
+
+
+def test_tail_is_inert_under_the_papers_stop_rule(prm):
+    """The estimate certifies against the 1-norm rule only: with the paper's
+    max-norm rule the solve is bit for bit the one without it."""
+    pr, torch = prm
+    g = scc_blocks(31, nblocks=40, max_size=60)
+    W = np.random.default_rng(31).uniform(0.5, 1.5, g.n)
+    for team in (1 << 30, 256):
+        build = dict(small_cutoff=8, team_edges=team)
+        _say("tail under PAPER rule, team", team)
+        R0, rc0, st0, _ = _run(prm, g, W, build, stop=pr.PR_STOP_PAPER_MAXABS, tol=1e-9, precision=1)
+        R1, rc1, st1, _ = _run(prm, g, W, build, stop=pr.PR_STOP_PAPER_MAXABS, tol=1e-9, precision=1,
+                               tail_estimate=1)
+        assert rc0 == 0 and rc1 == 0
+        np.testing.assert_array_equal(R1, R0)
+        assert st1["iters_sum"] == st0["iters_sum"]
+
+
+def test_tail_with_zero_mass_sccs(prm):
+    """SCCs that receive no mass (W = 0 on them and on everything above
+    them) skip the series; the rest match the oracle's tail rule."""
+    pr, torch = prm
+    g = scc_blocks(32, nblocks=40, max_size=60)
+    part = partition_theorem(g.n, g.row_ptr, g.col)
+    rng = np.random.default_rng(32)
+    W = rng.uniform(0.5, 1.5, g.n)
+    vlevel = part["comp_level"][part["comp"]]
+    W[vlevel >= np.percentile(vlevel, 60)] = 0.0  # the upper levels carry no mass
+    for team in (1 << 30, 256):
+        build = dict(small_cutoff=8, team_edges=team)
+        _say("tail zero-mass SCCs, team", team)
+        R, rc, st, lv = _run(prm, g, W, build, eps=1e-9, precision=1, tail_estimate=1)
+        Ro, sto = componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=1e-9, tail=True, return_stats=True)
+        assert rc == 0
+        np.testing.assert_allclose(R, Ro, rtol=2e-9, atol=1e-300)
+        it = lv.debug("iters", n_comp=part["n_comp"])
+        scc = part["comp_type"] == 1
+        d = np.abs(it[scc].astype(np.int64) - sto["iters"][scc])
+        assert d.max() <= 1 and np.count_nonzero(d) <= 2
+        dead = scc & (sto["iters"] == 0)
+        assert dead.any() and (it[dead] == 0).all()
