@@ -200,8 +200,8 @@ typedef struct pr_solve_opts {
                            ((1-rho)(1-c)) <= eps ||W'_C||_1, which bounds ||R' - R*_C||_1 exactly as
                            the plain rule does (the residual of R' is (P_{k+1} - rho P_k)/(1-rho)).
                            The plain test is tried first.  After a kept starting guess the rule
-                           runs on the residual series r_0, r_1, ... (rho from r_2 on).  Not
-                           combined with warm_scope = 1 (PR_EINVAL).  Default 0. */
+                           runs on the residual series r_0, r_1, ... (rho from r_2 on).
+                           Default 0. */
   int32_t reserved[3];
 } pr_solve_opts;
 

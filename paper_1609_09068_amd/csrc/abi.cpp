@@ -272,10 +272,6 @@ int32_t pr_solve(pr_levels_t* lh, double c, const void* W_dev, void* R_dev, cons
     set_error("tail_estimate = %d, expected 0 or 1", o.tail_estimate);
     return PR_EINVAL;
   }
-  if (o.tail_estimate == 1 && o.warm_start && o.warm_scope == 1) {
-    set_error("tail_estimate = 1 cannot be combined with warm_scope = 1");
-    return PR_EINVAL;
-  }
   if (o.small_direct < 0 || o.small_direct > 24) {
     set_error("small_direct = %d, expected 0..24", o.small_direct);
     return PR_EINVAL;

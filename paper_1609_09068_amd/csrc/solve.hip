@@ -1028,7 +1028,9 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
     Rj[0] = xr;
     last = rr / p.c;  // the certificate adds c / (1 - c) * last
     skip = true;
-  } else if (WARM && !skip) {
+  }
+  double P0 = Rj[0];  // the lane's first term: W' (P_0), or r_0 after a kept guess
+  if (WARM && !skip) {  // (the direct solve above has set skip)
     const WarmOut w = warm_preamble<64>(p, vbeg, nv, wsum, nullptr);
     ws = w.keep ? 1 : 0;
     if (w.keep) {  // start from R_0 + r_0 with the term r_0
@@ -1039,6 +1041,7 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
           const int v = vbeg + i;
           const double r = p.wres[v];
           Rj[j] = p.wr0[v] + r;
+          if (j == 0) P0 = r;
           if constexpr (sizeof(YT) == 8) ya[i] = (YT)(p.c * r * p.inv64[v]);
           else ya[i] = (YT)(p.c * r * (double)inv[j]);
         }
@@ -1072,10 +1075,10 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
     const double inv64 = act ? p.inv64[vbeg + lane] : 0.0;
     const bool cert = p.stop == PR_STOP_CERT_L1;
     double R0 = Rj[0];
-    // certified tail estimate (no starting guess): the previous term and the
+    // certified tail estimate: the previous term (r_0 after a kept guess) and the
     // norms of the last two terms
     const bool tail = TAIL && p.tail && cert;
-    double svp = R0, nprev = wsum, nprev2 = -1.0;
+    double svp = P0, nprev = last, nprev2 = -1.0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     while (k < p.max_iter) {
       ++k;
@@ -1152,7 +1155,7 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
     conv = false;
     // tail estimate: a row's terms are read back from the term buffers
     const bool tail = TAIL && p.tail;
-    double nprev = wsum, nprev2 = -1.0;
+    double nprev = last, nprev2 = -1.0;
     auto scale = [&](int j, int i) -> double {  // the factor between P and the term buffer
       if constexpr (sizeof(YT) == 8) return (double)cy * p.inv64[vbeg + i];
       else return (double)cy * (double)inv[j];
@@ -1349,7 +1352,7 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
     YT* lb = l1;
     // certified tail estimate as in the register path below
     const bool tail = TAIL && p.tail;
-    double nprev = wsum, nprev2 = -1.0;
+    double nprev = last, nprev2 = -1.0;
     if (!skip) {
       conv = false;
       while (k < p.max_iter) {
@@ -1478,11 +1481,11 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
     __syncthreads();
     YT* la = l0;
     YT* lb = l1;
-    // certified tail estimate (no starting guess): the norms of the last two
+    // certified tail estimate (from r_0 after a kept guess): the norms of the last two
     // terms; a row's terms are read back from the term buffers, which hold
     // c P_k / outdeg (a relative difference of one FP32 rounding)
     const bool tail = TAIL && p.tail;
-    double nprev = wsum, nprev2 = -1.0;
+    double nprev = last, nprev2 = -1.0;
     if (!skip) {
       conv = false;
       while (k < p.max_iter) {
@@ -1580,7 +1583,7 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
   } else {
     // certified tail estimate as in the register path above
     const bool tail = TAIL && p.tail;
-    double nprev = wsum, nprev2 = -1.0;
+    double nprev = last, nprev2 = -1.0;
     if (!skip) {
       conv = false;
       while (k < p.max_iter) {
@@ -2277,6 +2280,14 @@ using GangFn = void (*)(SolveParams, int, int, int);
 
 template <typename YT>
 SegFn seg_kernel(int rpw, bool warm, bool tail) {
+  if (warm && tail) {
+    switch (rpw) {
+      case 64: return k_segment<YT, 64, true, true>;
+      case 16: return k_segment<YT, 16, true, true>;
+      case 4: return k_segment<YT, 4, true, true>;
+      default: return k_segment<YT, 1, true, true>;
+    }
+  }
   if (warm) {
     switch (rpw) {
       case 64: return k_segment<YT, 64, true>;
@@ -2904,7 +2915,6 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   double sumW = 0.0;
   for (int i = 0; i < kRedBlocks; ++i) sumW += wparts[2 * i];
   const int64_t kb = term_bound(o, c, sumW);
-  if (p.mlp) p.tail = 0;  // (refused at the boundary) the guessing segment variants do not carry the rule
   const SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave, p.mlp != nullptr, p.tail != 0);
   // the variants with the starting guess or the tail estimate need more
   // registers: size their grid to what stays resident
