@@ -68,10 +68,16 @@ def roofline(fam, info, st, prec, plain, traffic):
     per_launch = b / max(cnt, 1)
     avg_ms = ms / max(cnt, 1)
     ach = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": FAMILIES[fam], "launches_per_solve": cnt, "avg_launch_us": round(avg_ms * 1e3, 3),
-            "alg_bytes_per_launch": int(per_launch)}
+    out = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "kernel": FAMILIES[fam], "launches_per_solve": cnt, "avg_launch_us": round(avg_ms * 1e3, 3),
+           "alg_bytes_per_launch": int(per_launch)}
+    if traffic and avg_ms > 0:
+        # the counted memory-side bytes over the same duration: how close the
+        # kernel runs to the bandwidth limit in the bytes it actually moves
+        out["traffic_gbs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 2)
+        out["traffic_frac"] = round(out["traffic_gbs"] / HBM_PEAK_GBS, 4)
+    return out
 
 
 def load_traffic(path, kernel):
