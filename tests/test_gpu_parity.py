@@ -274,6 +274,36 @@ def test_config2_full_size_mixed(prm, c2, method):
         assert partition_arrays_equal(p.as_dict(), partition_theorem(g.n, g.row_ptr, g.col))
 
 
+def test_config3_full_size(prm):
+    """5M vertices / 49M edges, 300 levels, no giant SCC: the partition is
+    bit-exact with the oracle's, and the benchmark's headline solve (mixed
+    precision, gang starting guess, tail estimate, eps 1e-6) and the plain
+    method both meet the oracle's FP64 residual bound, which holds at any
+    size: ||R - R*||_1 <= ||W - (I - cA^T)R||_1 / (1 - c)."""
+    import os
+
+    from oracle.pagerank import residual_bound
+
+    pr, torch = prm
+    g = config_graph("c3_deep_5m")
+    W = np.ones(g.n)
+    _say("c3 partition")
+    part = pr.pr_partition(g.row_ptr, g.col)
+    assert partition_arrays_equal(part.as_dict(), partition_theorem(g.n, g.row_ptr, g.col))
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col)
+    net = pr.Mlp.load_file(os.path.join(os.path.dirname(pr.__file__), "data", "warm_web.prmlp"))
+    Wd = torch.tensor(W, device="cuda")
+    AT = None
+    for method, opts in ((0, dict(warm_start=net, tail_estimate=1)), (1, {})):
+        _say("c3 full size method", method, sorted(opts))
+        R = torch.empty_like(Wd)
+        rc, st = pr.pr_solve(lv, C, Wd, R, eps=1e-6, precision=0, method=method, use_graph=1, **opts)
+        assert rc == 0 and st["cert_rel"] <= 1e-6 and st["n_not_converged"] == 0
+        bound, AT = residual_bound(g.n, g.row_ptr, g.col, C, W, R.cpu().numpy(), AT)
+        _say("c3 residual bound", bound)
+        assert bound <= 1e-6
+
+
 def test_autotuner_sweeps_caches_and_stays_exact(prm, c1, tmp_path, monkeypatch):
     pr, torch = prm
     g, W, ref = c1
