@@ -199,12 +199,14 @@ def run_study(args, pr, torch, g, lv, info, W, R, t_part, t_build):
     AT = None
     for c in (0.85, 0.99):
         for prec in (0, 1):
-            for meth in (0, 1):
-                name = ("componentwise" if meth == 0 else "plain") + ("/mixed" if prec == 0 else "/fp64")
+            for meth, tail in ((0, 0), (0, 1), (1, 0)):
+                name = (("componentwise" + ("+tail_estimate" if tail else "")) if meth == 0 else "plain") + \
+                       ("/mixed" if prec == 0 else "/fp64")
                 st = None
                 ms = []
                 for rep in range(1 + max(args.steps, 1)):
-                    rc, st = pr.pr_solve(lv, c, W, R, method=meth, precision=prec, eps=args.eps, kernel_timing=1)
+                    rc, st = pr.pr_solve(lv, c, W, R, method=meth, precision=prec, eps=args.eps, kernel_timing=1,
+                                         tail_estimate=tail)
                     if rep:
                         ms.append(st["kernel_ms"])
                 bound, AT = residual_bound(g, c, R.cpu().numpy(), AT)

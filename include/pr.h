@@ -214,7 +214,8 @@ typedef struct pr_solve_stats {
   int64_t n_iterated;   /* SCCs iterated */
   int64_t n_not_converged;
   int64_t ws_accepted, ws_rejected; /* warm start: per-SCC accept / fallback counts */
-  double cert_abs;      /* c/(1-c) * sum_C ||P_{K_C}||_1: bound on ||R* - R||_1 (CERT rule) */
+  double cert_abs;      /* c/(1-c) * sum_C ||P_{K_C}||_1: bound on ||R* - R||_1 (CERT rule; truncation
+                           only, term rounding excluded, see pr_solve) */
   double r_sum;         /* ||R||_1 */
   double cert_rel;      /* cert_abs / r_sum: bound on the relative 1-norm error */
   double time_ms;       /* host wall time of the pr_solve call, weight check included */
@@ -243,6 +244,10 @@ typedef struct pr_solve_stats {
  * rule.  PLAIN runs the power series on the whole graph with the same rule.
  * With PR_STOP_CERT_L1 the relative 1-norm error of R is below eps in exact
  * arithmetic (Sec. 4.4); stats->cert_rel reports the bound for this run.
+ * That bound covers the truncation of the series, not rounding: FP32 terms
+ * (PR_PREC_MIXED) add rounding that the solve amplifies by up to 1/(1-c),
+ * which matters as c approaches 1 (at c = 0.99 it can exceed 1e-6 relative);
+ * use PR_PREC_FP64 there.
  * The call returns after the stream work has completed.
  * Errors: PR_EINVAL (c outside (0,1), eps <= 0, tol <= 0, W negative or not
  * finite, method PLAIN without build_plain), PR_EHIP.
