@@ -455,3 +455,16 @@ def test_weight_expansion_validates_and_drops_zero_weights():
     for bad in ([1.5, 1, 1], [1, -1, 1], [1, 1]):
         with pytest.raises(ValueError):
             expand_integer_weights(rp, col, bad)
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_tail_estimate_inert_under_the_papers_rule(seed):
+    """The estimate certifies against the 1-norm rule only: under the
+    paper's max-norm rule the result and the term counts are unchanged."""
+    g = random_digraph(300, 900, seed + 910)
+    W = np.random.default_rng(seed).uniform(0.5, 1.5, g.n)
+    R0, st0 = CW.componentwise_solve(g.n, g.row_ptr, g.col, C, W, stop="paper", tol=1e-9, return_stats=True)
+    R1, st1 = CW.componentwise_solve(g.n, g.row_ptr, g.col, C, W, stop="paper", tol=1e-9, tail=True,
+                                     return_stats=True)
+    np.testing.assert_array_equal(R1, R0)
+    np.testing.assert_array_equal(st1["iters"], st0["iters"])
