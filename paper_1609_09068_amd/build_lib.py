@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpr.so")
 ARCH = os.environ.get("PR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.cpp", "partition.cpp", "devsort.hip", "plan.hip", "solve.hip", "mlp.hip", "autotune.hip"]
+SOURCES = ["abi.cpp", "partition.cpp", "devsort.hip", "plan.hip", "solve.hip", "seg_f32.hip", "seg_f32_tail.hip",
+           "seg_f64.hip", "seg_f64_tail.hip", "mlp.hip", "autotune.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -29,17 +30,43 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object (in parallel), then link libpr.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = [hipcc] + compile_flags + inc + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        return obj, res
+
+    jobs = int(os.environ.get("PR_BUILD_JOBS", "0")) or min(len(SOURCES), os.cpu_count() or 1, 8)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(compile_one, sources()))
+    failed = False
+    for obj, res in results:
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            failed = True
+        elif verbose and res.stderr.strip():
+            sys.stderr.write(res.stderr[-2000:])
+    if failed:
+        raise RuntimeError("hipcc failed building libpr.so")
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(HERE, "..", "include")] + sources() + ["-o", tmp]
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + [o for o, _ in results] + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libpr.so")
-    if verbose and res.stderr.strip():
-        sys.stderr.write(res.stderr[-4000:])
+        raise RuntimeError("hipcc failed linking libpr.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -126,3 +126,35 @@ def test_config_partitions_bit_exact(name):
     a = pr.pr_partition(g.row_ptr, g.col).as_dict()
     b = partition_theorem(g.n, g.row_ptr, g.col)
     assert partition_arrays_equal(a, b)
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, np.int64).ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, np.int32).ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def test_build_rejects_partition_of_another_graph_differing_in_one_edge():
+    """The plan build checks that the partition belongs to the graph from a
+    fingerprint of every row pointer and column index: a graph with the same
+    n and m that differs in one edge, far from any strided sample point, is
+    refused before any device work (PR_EINVAL)."""
+    lib = _lib.load()
+    g = random_digraph(20_000, 200_000, 7)
+    p = pr.pr_partition(g.row_ptr, g.col)
+    for e in (1, g.m // 4097 + 3, g.m - 2):
+        col = g.col.copy()
+        col[e] = (col[e] + 1) % g.n
+        out = C.c_void_p()
+        rc = lib.pr_build_levels(p.handle, g.n, _i64(g.row_ptr), _i32(col), None, None, C.byref(out))
+        assert rc == _lib.PR_EINVAL, (e, rc)
+        assert b"different graph" in lib.pr_last_error()
+    # moving an edge to the next row keeps m but changes two row pointers
+    rp = g.row_ptr.copy()
+    v = int(np.argmax(np.diff(rp) > 1))
+    rp[v + 1] -= 1
+    out = C.c_void_p()
+    rc = lib.pr_build_levels(p.handle, g.n, _i64(rp), _i32(g.col), None, None, C.byref(out))
+    assert rc == _lib.PR_EINVAL and b"different graph" in lib.pr_last_error()

@@ -40,12 +40,12 @@ def test_source_hash_ignores_comments_only():
         def read(name):
             with open(os.path.join(csrc, name)) as f:
                 text = f.read()
-            return edit(text) if name == "solve.hip" else text
+            return edit(text) if name == "solve_dev.h" else text
         return read
 
     h = bench.source_hash()
     assert bench.source_hash(read_with(lambda t: t + "\n// a comment\n/* and\n another */\n")) == h
-    assert bench.source_hash(read_with(lambda t: t.replace("kThreads", "kThreads ", 1))) == h
+    assert bench.source_hash(read_with(lambda t: t.replace("kThreads = 256", "kThreads  =  256", 1))) == h
     assert bench.source_hash(read_with(lambda t: t + "\nstatic int unused_symbol;\n")) != h
 
 
