@@ -202,7 +202,15 @@ typedef struct pr_solve_opts {
                            The plain test is tried first.  After a kept starting guess the rule
                            runs on the residual series r_0, r_1, ... (rho from r_2 on).
                            Default 0. */
-  int32_t reserved[3];
+  int32_t refine;       /* FP64 residual certificate and refinement (Sec. 4.4): after the solve,
+                           r = W - (I - c A^T) R is formed in FP64 over every edge and
+                           cert_rel = ||r||_1 / ((1-c) ||R||_1), a bound that covers the rounding
+                           of FP32 terms as well as the truncation of the series.  While it exceeds
+                           eps (PR_STOP_CERT_L1 only), a correction solve (I - c A^T) d = r by the
+                           same method, to the looser target 0.25 eps / cert_rel, and R += d.
+                           0 (default) = at most 2 such rounds; k > 0 = at most k; -1 = no residual
+                           pass (cert_rel is then the truncation bound alone). */
+  int32_t reserved[2];
 } pr_solve_opts;
 
 void pr_default_solve_opts(pr_solve_opts* o);
@@ -214,8 +222,8 @@ typedef struct pr_solve_stats {
   int64_t n_iterated;   /* SCCs iterated */
   int64_t n_not_converged;
   int64_t ws_accepted, ws_rejected; /* warm start: per-SCC accept / fallback counts */
-  double cert_abs;      /* c/(1-c) * sum_C ||P_{K_C}||_1: bound on ||R* - R||_1 (CERT rule; truncation
-                           only, term rounding excluded, see pr_solve) */
+  double cert_abs;      /* bound on ||R* - R||_1: ||r||_1 / (1-c) from the FP64 residual r (refine >= 0),
+                           else c/(1-c) * sum_C ||P_{K_C}||_1 (truncation only, see pr_solve) */
   double r_sum;         /* ||R||_1 */
   double cert_rel;      /* cert_abs / r_sum: bound on the relative 1-norm error */
   double time_ms;       /* host wall time of the pr_solve call, weight check included */
@@ -228,7 +236,11 @@ typedef struct pr_solve_stats {
   int64_t kt_count[4];
   int64_t gang_edge_iters; /* with kernel_timing = 1, COMPONENTWISE: the part of edge_iters */
   int64_t gang_vert_iters; /* and vert_iters done by gang launches */
-  int32_t reserved[8];
+  double cert_trunc_rel;   /* the truncation bound c/(1-c) sum_C ||P_{K_C}||_1 / ||R||_1 of the first
+                              solve (rounding excluded) */
+  double res_l1;           /* ||W - (I - c A^T) R||_1 of the returned R in FP64 (0 with refine = -1) */
+  int32_t refine_rounds;   /* correction solves run (their terms and edges are included above) */
+  int32_t reserved[3];
 } pr_solve_stats;
 
 /*
@@ -242,12 +254,18 @@ typedef struct pr_solve_stats {
  * one-vertex components copied, CACs solved exactly in topological order
  * (Sec. 4.3.1), SCCs by the power series (Sec. 4.3.2) with the chosen stop
  * rule.  PLAIN runs the power series on the whole graph with the same rule.
- * With PR_STOP_CERT_L1 the relative 1-norm error of R is below eps in exact
- * arithmetic (Sec. 4.4); stats->cert_rel reports the bound for this run.
- * That bound covers the truncation of the series, not rounding: FP32 terms
- * (PR_PREC_MIXED) add rounding that the solve amplifies by up to 1/(1-c),
- * which matters as c approaches 1 (at c = 0.99 it can exceed 1e-6 relative);
- * use PR_PREC_FP64 there.
+ * With PR_STOP_CERT_L1 the relative 1-norm error of the series is below eps
+ * in exact arithmetic (Sec. 4.4).  FP32 terms (PR_PREC_MIXED) add rounding
+ * that the solve amplifies by up to 1/(1-c), which matters as c approaches 1
+ * (at c = 0.99 it can exceed 1e-6 relative).  So by default (refine = 0)
+ * the solve ends with an FP64 residual pass over every edge:
+ * stats->cert_rel = ||W - (I - c A^T) R||_1 / ((1-c) ||R||_1) bounds the
+ * relative 1-norm error of the returned R, rounding included (up to the
+ * FP64 rounding of the residual itself, about 1e-16 relative), and while it
+ * exceeds eps a correction solve refines R (see pr_solve_opts.refine).  When
+ * the bound still exceeds eps after the allowed rounds the call returns
+ * PR_NOT_CONVERGED.  After a refined solve, pr_levels_debug's per-solve
+ * arrays (W', iterations) hold the last correction solve's values.
  * The call returns after the stream work has completed.
  * Errors: PR_EINVAL (c outside (0,1), eps <= 0, tol <= 0, W negative or not
  * finite, method PLAIN without build_plain), PR_EHIP.

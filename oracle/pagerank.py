@@ -170,6 +170,20 @@ def pagerank_power_series(n, row_ptr, col, c, W, *, stop="cert", eps=1e-6, tol=N
     return R, k, last
 
 
+def residual_rows(n, row_ptr, col, c, W, R, AT=None, loops=False):
+    """Per-row residual r = W - (I - c A^T) R of a candidate R (Sec. 4.4), and
+    the size of the terms each row's residual is formed from,
+    |W| + |R| + c A^T |R| (what its FP64 rounding is relative to).  Returns
+    (r, scale, A^T)."""
+    if AT is None:
+        AT = transition_T_csr(n, row_ptr, col, loops)
+    R = np.asarray(R, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    r = W - R + c * (AT @ R)
+    scale = np.abs(W) + np.abs(R) + c * (AT @ np.abs(R))
+    return r, scale, AT
+
+
 def residual_bound(n, row_ptr, col, c, W, R, AT=None, loops=False):
     """Certificate of any candidate R (Sec. 4.4): the residual r = W - (I - c A^T) R
     satisfies R* - R = (I - c A^T)^{-1} r, and the column sums of c A^T are at

@@ -39,7 +39,7 @@ class SolveOpts(C.Structure):
                 ("use_graph", C.c_int32), ("eps", C.c_double), ("tol", C.c_double),
                 ("max_iter", C.c_int64), ("warm_start", C.c_void_p), ("trace", C.c_int32),
                 ("kernel_timing", C.c_int32), ("warm_scope", C.c_int32), ("small_direct", C.c_int32),
-                ("tail_estimate", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("tail_estimate", C.c_int32), ("refine", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class SolveStats(C.Structure):
@@ -49,7 +49,8 @@ class SolveStats(C.Structure):
                 ("cert_rel", C.c_double), ("time_ms", C.c_double), ("vert_iters", C.c_int64),
                 ("kernel_ms", C.c_double), ("kt_ms", C.c_double * 4), ("kt_count", C.c_int64 * 4),
                 ("gang_edge_iters", C.c_int64), ("gang_vert_iters", C.c_int64),
-                ("reserved", C.c_int32 * 8)]
+                ("cert_trunc_rel", C.c_double), ("res_l1", C.c_double), ("refine_rounds", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "kt_ms", "kt_count")}

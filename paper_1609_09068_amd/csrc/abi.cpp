@@ -272,6 +272,10 @@ int32_t pr_solve(pr_levels_t* lh, double c, const void* W_dev, void* R_dev, cons
     set_error("tail_estimate = %d, expected 0 or 1", o.tail_estimate);
     return PR_EINVAL;
   }
+  if (o.refine < -1 || o.refine > 16) {
+    set_error("refine = %d, expected -1 (no residual pass), 0 (default) or 1..16 rounds", o.refine);
+    return PR_EINVAL;
+  }
   if (o.small_direct < 0 || o.small_direct > 24) {
     set_error("small_direct = %d, expected 0..24", o.small_direct);
     return PR_EINVAL;

@@ -182,10 +182,23 @@ struct Levels {
   double* lastnorm = nullptr;     // [K] by rank
   unsigned long long* counters = nullptr;  // [16] queue head, stats
   double* red = nullptr;          // [64] reduction scratch
-  // hipGraph cache
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
-  uint64_t graph_key = 0;
+  // captured launch sequences by key (solve options, buffers, gang budgets),
+  // least recently used dropped beyond kGraphCache entries
+  struct GraphEntry {
+    uint64_t key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+  };
+  static constexpr size_t kGraphCache = 8;
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  void drop_graphs();
+  // FP64 residual certificate: per-workgroup partial sums; refinement: the
+  // residual in the caller's order and the correction (allocated on first use)
+  double* res_part = nullptr;
+  double* res_w = nullptr;
+  double* res_d = nullptr;
   std::vector<hipEvent_t> kev;  // per-launch timing events (kernel_timing)
   double* warm_buf = nullptr;   // starting-guess scratch (allocated on first use)
   int32_t* warm_gws = nullptr;  // [n_gscc] per gang SCC: guess kept / not / none

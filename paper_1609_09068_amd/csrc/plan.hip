@@ -181,14 +181,21 @@ int32_t dalloc(T** p, size_t count) {
 }  // namespace
 
 
+void Levels::drop_graphs() {
+  for (GraphEntry& g : graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  graphs.clear();
+}
+
 Levels::~Levels() {
   void* ps[] = {perm, comp_vbeg, comp_rank_of_id, comp_id_of_rank, bnd_ptr, bnd_src, int_ptr, int_src,
                 full_ptr, full_src, inv_deg32, inv_deg64, items, gangs, gsccs, gbounds, gpart, gpmx, gpdiff, gnhist,
                 gwsum, gdone, x, R, wprime, y0, y1, iters, lastnorm, counters, red, wgstats, trace,
                 seg_heads, ghubs, gpieces, gpiece_ptr, gpiece_part, ghub_pieces, warm_buf, warm_gws, vpath,
-                mslot_ptr, mslot_src};
-  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-  if (graph) (void)hipGraphDestroy(graph);
+                mslot_ptr, mslot_src, res_part, res_w, res_d};
+  drop_graphs();
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (hipEvent_t e : kev) (void)hipEventDestroy(e);
   for (void* p : ps)

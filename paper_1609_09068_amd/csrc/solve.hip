@@ -478,6 +478,7 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
     PR_TRY(dalloc(&lv.lastnorm, std::max<int64_t>(K, 1)));
     PR_TRY(dalloc(&lv.counters, C_COUNT));
     PR_TRY(dalloc(&lv.red, 2 * kRedBlocks + 8));
+    PR_TRY(dalloc(&lv.res_part, 2 * kResBlocks + 8));
   }
   PR_HIP_CHECK(hipStreamSynchronize(s));
   pr_levels_info& I = lv.info;
@@ -500,11 +501,7 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   I.team_edges = lv.opts.team_edges;
   I.grid_wgs = lv.sgrid;
   // a new schedule invalidates a captured graph
-  if (lv.graph_exec) (void)hipGraphExecDestroy(lv.graph_exec);
-  if (lv.graph) (void)hipGraphDestroy(lv.graph);
-  lv.graph_exec = nullptr;
-  lv.graph = nullptr;
-  lv.graph_key = 0;
+  lv.drop_graphs();
   // the uploads above read host vectors that end with this function
   PR_HIP_CHECK(hipStreamSynchronize(s));
   return PR_OK;
@@ -539,8 +536,41 @@ static size_t warm_feat_off(const Levels& lv) {
   return (off + 1) & ~(size_t)1;
 }
 
-int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_solve_opts& o,
-                     hipStream_t s, pr_solve_stats* st) {
+// the kernels' view of the plan for the FP64 residual: every edge once, in
+// the between-component and inside-component rows, whatever the method
+static SolveParams residual_params(const Levels& lv, double c, const double* W) {
+  SolveParams q{};
+  q.n = (int32_t)lv.n;
+  q.c = c;
+  q.W = W;
+  q.perm = lv.perm;
+  q.bnd_ptr = lv.bnd_ptr;
+  q.bnd_src = lv.bnd_src;
+  q.int_ptr = lv.int_ptr;
+  q.int_src = lv.int_src;
+  q.inv64 = lv.inv_deg64;
+  return q;
+}
+
+static unsigned residual_grid(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kResBlocks, (n + kThreads - 1) / kThreads));
+}
+
+// r = W - (I - c A^T) R in FP64 (R in the caller's order): sum |r| and sum
+// |R| to out[0..1], and r itself in the caller's order to rw when not null
+static void launch_residual(const Levels& lv, double c, const double* W, const double* R, double* rw, double* out,
+                            hipStream_t s) {
+  const unsigned g = residual_grid(lv.n);
+  k_res_prep<<<g, kThreads, 0, s>>>(R, lv.perm, lv.inv_deg64, lv.n, lv.R, lv.x);
+  k_residual<<<g, kThreads, 0, s>>>(residual_params(lv, c, W), lv.R, lv.x, rw, lv.res_part);
+  k_res_sum<<<1, kThreads, 0, s>>>(lv.res_part, (int)g, out);
+}
+
+// One solve of the method (no refinement).  signed_w: W is a residual (a
+// correction solve).  residual: end with the FP64 residual pass, its sums in
+// lv.red[2..3].
+static int32_t solve_once(Levels& lv, double c, const double* W, double* R, const pr_solve_opts& o,
+                          hipStream_t s, pr_solve_stats* st, bool signed_w, bool residual) {
   int dev;
   PR_HIP_CHECK(hipGetDevice(&dev));
   if (dev != lv.device) {
@@ -574,6 +604,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   p.vpath = lv.vpath;
   p.direct_max = plain ? 0 : o.small_direct;
   p.tail = (!plain && o.tail_estimate && o.stop == PR_STOP_CERT_L1) ? 1 : 0;
+  p.signed_w = signed_w ? 1 : 0;
   p.mslot_ptr = lv.mslot_ptr;
   p.mslot_src = lv.mslot_src;
   p.inv32 = lv.inv_deg32;
@@ -760,6 +791,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     }
     k_reduce1<<<kRedBlocks, kThreads, 0, s>>>(R, lv.n, lv.lastnorm, plain ? 1 : lv.n_comp, lv.red + 8);
     k_reduce2<<<1, kThreads, 0, s>>>(lv.red + 8, lv.red, lv.wgstats, lv.sgrid, lv.counters);
+    if (residual) launch_residual(lv, c, W, R, nullptr, lv.red + 2, s);
     PR_HIP_CHECK(hipGetLastError());
     PR_TRY(mark(3));
     return PR_OK;
@@ -779,12 +811,21 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     key = mix64(key, (uint64_t)o.tail_estimate);
     key = mix64(key, (uint64_t)(uintptr_t)p.mlp);
     key = mix64(key, (uint64_t)(uintptr_t)p.gmlp);
+    key = mix64(key, (uint64_t)(signed_w ? 2 : 0) + (residual ? 1 : 0));
     for (int gg : gangs_run) key = mix64(key, (uint64_t)budget(gg));
-    if (!lv.graph_exec || lv.graph_key != key) {
-      if (lv.graph_exec) (void)hipGraphExecDestroy(lv.graph_exec);
-      if (lv.graph) (void)hipGraphDestroy(lv.graph);
-      lv.graph_exec = nullptr;
-      lv.graph = nullptr;
+    Levels::GraphEntry* ge = nullptr;
+    for (Levels::GraphEntry& e : lv.graphs)
+      if (e.key == key) ge = &e;
+    if (!ge) {
+      if (lv.graphs.size() >= Levels::kGraphCache) {  // drop the least recently used
+        auto old = std::min_element(lv.graphs.begin(), lv.graphs.end(),
+                                    [](const Levels::GraphEntry& a, const Levels::GraphEntry& b) {
+                                      return a.last_use < b.last_use;
+                                    });
+        if (old->exec) (void)hipGraphExecDestroy(old->exec);
+        if (old->graph) (void)hipGraphDestroy(old->graph);
+        lv.graphs.erase(old);
+      }
       if (!lv.cap_stream) PR_HIP_CHECK(hipStreamCreateWithFlags(&lv.cap_stream, hipStreamNonBlocking));
       const hipStream_t caller = s;
       s = lv.cap_stream;
@@ -798,12 +839,19 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
         set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ce));
         return PR_EHIP;
       }
-      lv.graph = g;
-      PR_HIP_CHECK(hipGraphInstantiate(&lv.graph_exec, g, nullptr, nullptr, 0));
-      lv.graph_key = key;
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+        return PR_EHIP;
+      }
+      lv.graphs.push_back({key, g, ex, 0});
+      ge = &lv.graphs.back();
     }
+    ge->last_use = ++lv.graph_clock;
     PR_HIP_CHECK(hipEventRecord(ev0, s));
-    PR_HIP_CHECK(hipGraphLaunch(lv.graph_exec, s));
+    PR_HIP_CHECK(hipGraphLaunch(ge->exec, s));
     PR_HIP_CHECK(hipEventRecord(ev1, s));
   } else {
     PR_HIP_CHECK(hipEventRecord(ev0, s));
@@ -820,7 +868,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     PR_HIP_CHECK(hipEventRecord(ev1, s));
   }
   unsigned long long cnt[C_COUNT];
-  double red[2];
+  double red[4] = {0.0, 0.0, 0.0, 0.0};
   PR_HIP_CHECK(hipMemcpyAsync(cnt, lv.counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
   PR_HIP_CHECK(hipMemcpyAsync(red, lv.red, sizeof(red), hipMemcpyDeviceToHost, s));
   PR_HIP_CHECK(hipStreamSynchronize(s));
@@ -848,7 +896,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
         lv.h_gang_hint[hint_at(gg)] = std::max(lv.h_gang_hint[hint_at(gg)], need);
       }
     }
-    if (cut) return solve_levels(lv, c, W, R, o, s, st);
+    if (cut) return solve_once(lv, c, W, R, o, s, st, signed_w, residual);
   }
   local.edge_iters = (int64_t)cnt[S_EDGE_ITERS] + (plain ? 0 : (lv.info.m_between + lv.info.m_cac_internal));
   local.iters_max = (int64_t)cnt[S_ITERS_MAX];
@@ -860,6 +908,12 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   local.r_sum = red[0];
   local.cert_abs = c / (1.0 - c) * red[1];
   local.cert_rel = red[0] > 0.0 ? local.cert_abs / red[0] : 0.0;
+  local.cert_trunc_rel = local.cert_rel;
+  if (residual) {  // the FP64 residual bound replaces the truncation bound
+    local.res_l1 = red[2];
+    local.cert_abs = red[2] / (1.0 - c);
+    local.cert_rel = red[3] > 0.0 ? local.cert_abs / red[3] : (red[2] > 0.0 ? INFINITY : 0.0);
+  }
   local.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host_t0).count();
   local.kernel_ms = ms;
   local.vert_iters = (int64_t)cnt[S_VERT_ITERS] + (plain ? 0 : (lv.n - lv.info.v_scc));
@@ -879,6 +933,70 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
   }
   if (st) *st = local;
   return local.n_not_converged ? PR_NOT_CONVERGED : PR_OK;
+}
+
+// The solve of pr_solve: one solve of the method, then (refine >= 0) the FP64
+// residual certificate, and while that bound exceeds eps (CERT rule) up to
+// `refine` rounds of iterative refinement: the residual r in the caller's
+// order, a correction solve (I - c A^T) d = r by the same method and
+// precision to the looser target 0.25 eps / cert (its FP32 rounding is
+// relative to d, which is about cert times smaller than R), R += d, and the
+// residual again (Sec. 4.4: ||R - R*||_1 <= ||r||_1 / (1 - c)).
+int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_solve_opts& o,
+                     hipStream_t s, pr_solve_stats* st) {
+  const auto host_t0 = std::chrono::steady_clock::now();
+  const bool residual = o.refine >= 0 && lv.n > 0;
+  pr_solve_stats a{};
+  int32_t rc = solve_once(lv, c, W, R, o, s, &a, false, residual);
+  if (rc < 0) return rc;
+  const int rounds = o.refine == 0 ? 2 : std::max(o.refine, 0);
+  bool refined_to_eps = true;
+  if (residual && o.stop == PR_STOP_CERT_L1) {
+    while (a.cert_rel > o.eps && a.res_l1 > 0.0 && a.refine_rounds < rounds) {
+      if (!lv.res_w) {
+        PR_TRY(dalloc(&lv.res_w, (size_t)lv.n));
+        PR_TRY(dalloc(&lv.res_d, (size_t)lv.n));
+      }
+      launch_residual(lv, c, W, R, lv.res_w, lv.red + 2, s);
+      PR_HIP_CHECK(hipGetLastError());
+      pr_solve_opts oc = o;
+      oc.warm_start = nullptr;
+      oc.trace = 0;
+      oc.refine = -1;
+      oc.eps = std::min(0.5, 0.25 * o.eps / a.cert_rel);
+      pr_solve_stats b{};
+      rc = solve_once(lv, c, lv.res_w, lv.res_d, oc, s, &b, true, false);
+      if (rc < 0) return rc;
+      k_add<<<residual_grid(lv.n), kThreads, 0, s>>>(R, lv.res_d, lv.n);
+      launch_residual(lv, c, W, R, nullptr, lv.red + 2, s);
+      PR_HIP_CHECK(hipGetLastError());
+      double red[4];
+      PR_HIP_CHECK(hipMemcpyAsync(red, lv.red, sizeof(red), hipMemcpyDeviceToHost, s));
+      PR_HIP_CHECK(hipStreamSynchronize(s));
+      a.edge_iters += b.edge_iters;
+      a.vert_iters += b.vert_iters;
+      a.iters_sum += b.iters_sum;
+      a.iters_max = std::max(a.iters_max, b.iters_max);
+      a.n_iterated += b.n_iterated;
+      a.n_not_converged += b.n_not_converged;
+      a.kernel_ms += b.kernel_ms;
+      for (int f = 0; f < 4; ++f) {
+        a.kt_ms[f] += b.kt_ms[f];
+        a.kt_count[f] += b.kt_count[f];
+      }
+      a.gang_edge_iters += b.gang_edge_iters;
+      a.gang_vert_iters += b.gang_vert_iters;
+      a.res_l1 = red[2];
+      a.r_sum = red[3];
+      a.cert_abs = red[2] / (1.0 - c);
+      a.cert_rel = red[3] > 0.0 ? a.cert_abs / red[3] : INFINITY;
+      a.refine_rounds += 1;
+    }
+    refined_to_eps = !(a.cert_rel > o.eps);
+  }
+  a.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host_t0).count();
+  if (st) *st = a;
+  return (a.n_not_converged || !refined_to_eps) ? PR_NOT_CONVERGED : PR_OK;
 }
 
 }  // namespace prlib

@@ -35,6 +35,7 @@ struct SolveParams {
   int32_t n_items;  // items of the segment being run
   int32_t direct_max;  // SCCs of a wavefront with at most this many vertices are solved directly
   int32_t tail;        // segment SCC series may stop on the certified geometric tail estimate
+  int32_t signed_w;    // weights may be negative (the residual that a correction solve takes)
   double c, eps, tol;
   int64_t max_iter;
   const double* W;
@@ -99,6 +100,11 @@ struct SolveParams {
 };
 
 // ------------------------------------------------------------------ helpers
+
+// x holds a quiet NaN until its vertex's rank is final: any other value, of
+// either sign (a correction solve has signed weights), is a published value
+__device__ inline bool x_ok(double v) { return v == v; }
+constexpr double kXPending = __builtin_nan("");
 
 __device__ inline double ld_x(const double* x, int u) {
   return __hip_atomic_load(const_cast<double*>(x) + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -284,7 +290,7 @@ __device__ inline bool lane_partial_x(const SolveParams& p, const int32_t* src, 
   for (; e + 3 * STRIDE < hi; e += 4 * STRIDE) {
     const int32_t s0 = src[e], s1 = src[e + STRIDE], s2 = src[e + 2 * STRIDE], s3 = src[e + 3 * STRIDE];
     const double a0 = ld_x(p.x, s0), a1 = ld_x(p.x, s1), a2 = ld_x(p.x, s2), a3 = ld_x(p.x, s3);
-    ok &= (a0 >= 0.0) & (a1 >= 0.0) & (a2 >= 0.0) & (a3 >= 0.0);
+    ok = ok && x_ok(a0) && x_ok(a1) && x_ok(a2) && x_ok(a3);
     acc += a0;
     acc += a1;
     acc += a2;
@@ -292,7 +298,7 @@ __device__ inline bool lane_partial_x(const SolveParams& p, const int32_t* src, 
   }
   for (; e < hi; e += STRIDE) {
     const double a = ld_x(p.x, src[e]);
-    ok &= (a >= 0.0);
+    ok = ok && x_ok(a);
     acc += a;
   }
   *out = acc;
@@ -395,7 +401,7 @@ __device__ __attribute__((always_inline)) VT wave_tile_gather(const SolveParams&
       for (int j = 0; j < 8; ++j) v[j] = idx[j] >= 0 ? ld_x(p.x, idx[j]) : 0.0;
       bool ok = true;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) ok &= v[j] >= 0.0;
+      for (int j = 0; j < 8; ++j) ok = ok && x_ok(v[j]);
       if (!__all(ok)) {
         // poll one missing source at a time (one address for the whole
         // wavefront), then re-read only the sources still missing
@@ -405,13 +411,13 @@ __device__ __attribute__((always_inline)) VT wave_tile_gather(const SolveParams&
           int want = -1;
 #pragma unroll
           for (int j = 7; j >= 0; --j)
-            if (v[j] < 0.0) want = idx[j];
+            if (!x_ok(v[j])) want = idx[j];
           const unsigned long long m = __ballot(want >= 0);
           if (!m) break;
           const int a = __shfl(want, __ffsll(m) - 1, 64);
           bool late = false;
           unsigned polls = 0;
-          while (ld_x(p.x, a) < 0.0) {
+          while (!x_ok(ld_x(p.x, a))) {
             if ((++polls & 15u) == 0u && timed_out(p, t0)) {
               late = true;
               break;
@@ -421,7 +427,7 @@ __device__ __attribute__((always_inline)) VT wave_tile_gather(const SolveParams&
           if (late) break;
 #pragma unroll
           for (int j = 0; j < 8; ++j)
-            if (v[j] < 0.0) v[j] = ld_x(p.x, idx[j]);
+            if (!x_ok(v[j])) v[j] = ld_x(p.x, idx[j]);
         }
         if (lane == 0) atomicAdd(&t->wst[S_T_WAIT], wall_clock64() - t0);
       }
@@ -487,7 +493,7 @@ __device__ __attribute__((always_inline)) VT wave_tile_gather(const SolveParams&
 //     lane walks each path in order with the x of the previous vertex in a
 //     register: R_v = acc_v + the x of v's CAC sources in edge order, read
 //     from LDS (sources in the item) or from the published x (earlier items)
-//     once final (x < 0 means not yet; the lane then retries in the next
+//     once final (x still NaN means not yet; the lane then retries in the next
 //     round).  A chain costs one multiply-add chain in one lane, and an item
 //     starts walking while the items before it are still being walked.
 // x_v = c R_v / outdeg(v) is published the moment R_v is final when a later
@@ -523,7 +529,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
   const bool pstart = act && (pw & 0x100u);
   const bool early = pw & 0x10000u;  // v has a CAC edge into a later item
   if (act) sQ[pw & 0xffu] = i | (pstart ? 0x10000 : 0);
-  sX[i] = -1.0;  // the LDS still holds the previous item's values
+  sX[i] = kXPending;  // the LDS still holds the previous item's values
   sI[i] = 0u;    // bit 15 marks a position whose entries are written
   const unsigned long long sm = __ballot(pstart);
   if (lane == 0) sWc[wave] = (int32_t)__popcll(sm);
@@ -550,11 +556,11 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
   auto inside = [&](int u) { return u >= vbeg && u < vend; };
   auto wait_x = [&](int u) {
     double xv = ld_x(p.x, u);
-    if (xv < 0.0) {
+    if (!x_ok(xv)) {
       const unsigned long long tw = wall_clock64();
       int nw = 1;
       unsigned polls = 0;
-      while ((xv = ld_x(p.x, u)) < 0.0) {
+      while (!x_ok(xv = ld_x(p.x, u))) {
         if ((++polls & 15u) == 0u && timed_out(p, tw)) return 0.0;
         backoff_sleep(nw);
       }
@@ -592,7 +598,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (u[j] >= 0 && !inside(u[j])) {
-            if (xv[j] < 0.0) xv[j] = wait_x(u[j]);
+            if (!x_ok(xv[j])) xv[j] = wait_x(u[j]);
             acc += xv[j];
           }
         }
@@ -720,7 +726,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
               if ((uint32_t)m < n) {
-                ok = ok && xs[m] >= 0.0;
+                ok = ok && x_ok(xs[m]);
                 r += xs[m];
               }
             }
@@ -737,7 +743,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
                 continue;
               }
               const double xv = u - vbeg == prev ? xprev : ld_lx(u - vbeg);
-              if (xv < 0.0) ok = false;
+              if (!x_ok(xv)) ok = false;
               else r += xv;
             }
             if (nl) r /= 1.0 - (double)nl * c8[j];
@@ -919,7 +925,7 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
       if constexpr (sizeof(YT) == 8) ya[i] = (YT)(p.c * wp * p.inv64[v]);
       else ya[i] = (YT)(p.c * wp * (double)inv[j]);
       p.wprime[v] = wp;
-      part += wp;
+      part += fabs(wp);
     }
   }
   // stage the internal rows in LDS (the tile is free after the gathers)
@@ -1247,7 +1253,7 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
       p.wprime[v] = wp;
       if constexpr (sizeof(YT) == 8) ya[v] = c * wp * p.inv64[v];
       else ya[v] = (YT)(c * wp * (double)p.inv32[v]);
-      part += wp;
+      part += fabs(wp);
     }
   }
   const double wsum = block_sum(part, red);  // also orders the phase-0 writes
@@ -1848,7 +1854,7 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
           p.wprime[v] = wp;
           if constexpr (sizeof(YT) == 8) yw[v] = c * wp * p.inv64[v];
           else yw[v] = (YT)(c * wp * (double)p.inv32[v]);
-          part += wp;
+          part += fabs(wp);
         }
       }
     } else {
@@ -2152,9 +2158,12 @@ __global__ void k_init(SolveParams p, int64_t K, int64_t n_gscc, int64_t n_stats
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = tid; i < p.n; i += stride) {
-    p.x[i] = -1.0;
+    p.x[i] = kXPending;
     const double w = p.W[i];
-    if (!(w >= 0.0) || !(w <= 1.7976931348623157e308)) atomicOr(&p.counters[C_BAD_W], 1ull);
+    // weights are non-negative and finite; a correction solve's weights (a
+    // residual) only finite
+    if (!((p.signed_w ? fabs(w) : w) >= 0.0) || !(fabs(w) <= 1.7976931348623157e308))
+      atomicOr(&p.counters[C_BAD_W], 1ull);
   }
   for (int64_t i = tid; i < K; i += stride) {
     p.iters[i] = 0;
@@ -2232,6 +2241,75 @@ __global__ __launch_bounds__(kThreads) void k_reduce2(const double* part, double
     }
     counters[threadIdx.x] = a;
   }
+}
+
+// ------------------------------------------------------------ FP64 residual
+// The certificate of a finished solve (Sec. 4.4).  With R the computed rank,
+// r = W - (I - c A^T) R is formed in FP64 over every edge of the graph: the
+// plan's between-component rows and inside-component rows together hold
+// each edge once (kept self-loops included, in the inside rows).  Every
+// column of c A^T sums to at most c, so ||R - R*||_1 <= ||r||_1 / (1 - c).
+// Unlike the truncation bound of the series this covers the rounding of the
+// FP32 terms too.
+//   k_res_prep  R in plan order and xr = R / outdeg
+//   k_residual  r per plan row, 64-row wavefront tiles; per-workgroup sums of
+//               |r| and |R|; optionally r in the caller's order (the weights
+//               of a correction solve)
+//   k_res_sum   the workgroup sums added in a fixed order
+constexpr int kResBlocks = 2048;
+__global__ __launch_bounds__(kThreads) void k_res_prep(const double* Rout, const int32_t* perm, const double* inv64,
+                                                       int64_t n, double* Rp, double* xr) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    const double r = Rout[perm[i]];
+    Rp[i] = r;
+    xr[i] = r * inv64[i];
+  }
+}
+__global__ __launch_bounds__(kThreads) void k_residual(SolveParams p, const double* Rp, const double* xr, double* rw,
+                                                       double* part) {
+  __shared__ WaveTile s_tile[kWaves];
+  __shared__ double lds[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double sr = 0.0, sR = 0.0;
+  for (int64_t ra = ((int64_t)blockIdx.x * kWaves + wave) * 64; ra < p.n; ra += (int64_t)gridDim.x * kThreads) {
+    const int nr = p.n - ra < 64 ? (int)(p.n - ra) : 64;
+    const double sb = wave_tile_gather<64, double, false>(p, p.bnd_ptr, p.bnd_src, xr, (int)ra, nr, &s_tile[wave]);
+    const double si = wave_tile_gather<64, double, false>(p, p.int_ptr, p.int_src, xr, (int)ra, nr, &s_tile[wave]);
+    if (lane < nr) {
+      const int v = (int)ra + lane;
+      const int o = p.perm[v];
+      const double R = Rp[v];
+      const double r = p.W[o] - R + p.c * (sb + si);
+      if (rw) rw[o] = r;
+      sr += fabs(r);
+      sR += fabs(R);
+    }
+  }
+  sr = block_sum(sr, lds);
+  sR = block_sum(sR, lds);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sr;
+    part[2 * blockIdx.x + 1] = sR;
+  }
+}
+__global__ __launch_bounds__(kThreads) void k_res_sum(const double* part, int G, double* out) {
+  __shared__ double lds[4];
+  double a = 0.0, b = 0.0;
+  for (int g = threadIdx.x; g < G; g += kThreads) {
+    a += part[2 * g];
+    b += part[2 * g + 1];
+  }
+  a = block_sum(a, lds);
+  b = block_sum(b, lds);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+// R += d (a refinement step)
+__global__ __launch_bounds__(kThreads) void k_add(double* R, const double* d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    R[i] += d[i];
 }
 
 using SegFn = void (*)(SolveParams);

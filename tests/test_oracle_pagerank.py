@@ -468,3 +468,26 @@ def test_tail_estimate_inert_under_the_papers_rule(seed):
                                      return_stats=True)
     np.testing.assert_array_equal(R1, R0)
     np.testing.assert_array_equal(st1["iters"], st0["iters"])
+
+
+def test_residual_rows_of_exact_and_planted_errors():
+    """Pins residual_rows: the dense solution leaves a residual at rounding
+    level, and a planted error e at one vertex v (out-degree d) leaves
+    r_v = -e and r_u = c e / d at each successor u, nothing elsewhere."""
+    g = random_digraph(80, 320, 11)
+    W = np.random.default_rng(3).random(g.n) + 0.5
+    R = PR.pagerank_dense(g.n, g.row_ptr, g.col, C, W)
+    r, scale, _ = PR.residual_rows(g.n, g.row_ptr, g.col, C, W, R)
+    assert np.all(np.abs(r) <= 1e-13 * scale)
+    outdeg = np.diff(g.row_ptr) - np.array([np.sum(g.col[g.row_ptr[u]:g.row_ptr[u + 1]] == u) for u in range(g.n)])
+    v = int(np.argmax(outdeg))
+    succ = [int(u) for u in g.col[g.row_ptr[v]:g.row_ptr[v + 1]] if u != v]
+    e = 0.125
+    R2 = R.copy()
+    R2[v] += e
+    r2, _, _ = PR.residual_rows(g.n, g.row_ptr, g.col, C, W, R2)
+    want = np.zeros(g.n)
+    want[v] -= e
+    for u in succ:
+        want[u] += C * e / outdeg[v]
+    assert np.allclose(r2 - r, want, rtol=0, atol=1e-12)
