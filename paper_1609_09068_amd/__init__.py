@@ -24,6 +24,7 @@ class Partition:
     def __init__(self, handle, n):
         self.handle = handle
         self.n = n
+        _lib.track(self)
         lib = _lib.load()
         k = C.c_int64()
         L = C.c_int32()
@@ -45,9 +46,9 @@ class Partition:
                     comp_size=self.comp_size, n_comp=self.n_comp, n_levels=self.n_levels)
 
     def free(self):
-        if self.handle:
+        if self.handle and not _lib.finalizing():
             _lib.load().pr_free(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -62,6 +63,7 @@ class Levels:
     def __init__(self, handle, n):
         self.handle = handle
         self.n = n
+        _lib.track(self)
 
     def info(self):
         inf = _lib.LevelsInfo()
@@ -100,9 +102,9 @@ class Levels:
         return out
 
     def free(self):
-        if self.handle:
+        if self.handle and not _lib.finalizing():
             _lib.load().pr_free(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -118,6 +120,7 @@ class Mlp:
 
     def __init__(self, handle):
         self.handle = handle
+        _lib.track(self)
 
     @classmethod
     def create(cls, seed=0):
@@ -176,9 +179,9 @@ class Mlp:
         return loss.value
 
     def free(self):
-        if self.handle:
+        if self.handle and not _lib.finalizing():
             _lib.load().pr_free(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:

@@ -77,6 +77,42 @@ EXPORTS = ["pr_partition", "pr_partition_get", "pr_default_build_opts", "pr_buil
            "pr_warm_features"]
 
 _lib = None
+_owners = None
+_finalizing = False
+
+
+def track(owner):
+    """Register an object that owns a library handle, so that it is released
+    at interpreter exit while the HIP runtime is still up."""
+    global _owners
+    import weakref
+
+    if _owners is None:
+        _owners = weakref.WeakSet()
+    _owners.add(owner)
+
+
+def _release_all():
+    """atexit hook: free every live handle (plans and networks first, they
+    hold device memory), then ignore later frees.  Without it a handle whose
+    owner survives to interpreter teardown would call hipFree / hipGraph*Destroy
+    from a finalizer after the runtime (or a profiler's tool library) has shut
+    down."""
+    global _finalizing
+    if _owners is not None:
+        live = list(_owners)
+        for kind in ("Levels", "Mlp", "Partition"):
+            for o in live:
+                if type(o).__name__ == kind:
+                    try:
+                        o.free()
+                    except Exception:
+                        pass
+    _finalizing = True
+
+
+def finalizing():
+    return _finalizing
 
 
 def load():
@@ -88,6 +124,9 @@ def load():
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1609_09068_amd.build_lib` (there is no fallback)")
     lib = C.CDLL(LIB_PATH)
+    import atexit
+
+    atexit.register(_release_all)
     P, I32, I64, U32, VP = C.POINTER, C.c_int32, C.c_int64, C.c_uint32, C.c_void_p
     lib.pr_partition.argtypes = [I64, P(I64), P(I32), U32, P(VP)]
     lib.pr_partition.restype = I32

@@ -876,8 +876,14 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
   PR_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
-  if (cnt[C_ERROR]) {
-    set_error("internal: a dependency wait timed out (flags %llu)", cnt[C_ERROR]);
+  if (cnt[C_ERROR] == 1ull) {
+    set_error("internal: a dependency wait timed out");
+    return PR_EHIP;
+  }
+  if (cnt[C_ERROR] || cnt[C_BAD_W] > 1ull) {
+    // the kernels only OR 1 into these slots: anything else was written by
+    // something that does not own them (a counter-layout error)
+    set_error("internal: counter layout error (error slot %llu, weight slot %llu)", cnt[C_ERROR], cnt[C_BAD_W]);
     return PR_EHIP;
   }
   if (!gangs_run.empty()) {

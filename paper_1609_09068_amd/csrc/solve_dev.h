@@ -27,6 +27,9 @@ enum : int { S_EDGE_ITERS = 0, S_VERT_ITERS = 1, S_ITERS_MAX = 2, S_ITERS_SUM = 
              S_T_GANG = 11, S_T_WAIT = 12, S_T_SEGMENT = 13, S_N_GANG = 14, S_T_MEDIUM_ITER = 15 };
 // global counters: [0, kWgStats) reduced from the workgroup counters, then flags
 enum : int { C_ERROR = 16, C_BAD_W = 17, C_COUNT = 32 };
+// the reduction of the workgroup counters writes slots [0, kWgStats): the
+// flags must lie beyond them
+static_assert(C_ERROR >= kWgStats && C_BAD_W >= kWgStats && C_BAD_W < C_COUNT, "counter layout");
 
 struct SolveParams {
   int32_t n;
