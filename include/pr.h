@@ -337,6 +337,19 @@ int32_t pr_mlp_predict(const pr_mlp_t* mlp, int64_t n, const float* X_dev, float
  * grad_host float[4545] (nullable), *loss = the mean squared error. */
 int32_t pr_mlp_grad(pr_mlp_t* mlp, int64_t n, const float* X_dev, const float* t_dev, float* grad_host,
                     double* loss, void* hip_stream);
+/* pr_mlp_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result, bit for bit, but the
+ * per-wavefront partial gradients live in a static device array of the
+ * library (at most 1024 partial vectors, 17.8 MiB, which covers every batch
+ * size: the gradient kernel runs at most 256 workgroups), not in a buffer the
+ * network allocates on first use.  The call allocates nothing; grad_host and
+ * loss are written as by pr_mlp_grad.  Every call on a device shares that
+ * device's array, so calls that overlap on one GPU (other threads, other
+ * streams) race; each call writes every partial it reads, so no clearing is
+ * needed.  PR_EINVAL if a batch needed more partials than the array holds. */
+int32_t pr_mlp_grad_noalloc(pr_mlp_t* mlp, int64_t n, const float* X_dev, const float* t_dev, float* grad_host,
+                            double* loss, void* hip_stream);
 /* One Adam step with learning rate lr on the batch; *loss (nullable) = the
  * batch's mean squared error before the step.  PR_EINVAL for n <= 0 or a
  * learning rate that is not positive and finite. */

@@ -169,6 +169,18 @@ class Mlp:
                                             C.c_void_p(_stream_ptr(stream))))
         return g, loss.value
 
+    def grad_noalloc(self, X, t, stream=None):
+        """grad() through pr_mlp_grad_noalloc (partials in the library's static
+        device array; nothing allocated)."""
+        _need_f32_dev(X, 2)
+        _need_f32_dev(t, 1)
+        g = np.zeros(self.N_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        _lib._check(_lib.load().pr_mlp_grad_noalloc(self.handle, X.shape[0], C.c_void_p(X.data_ptr()),
+                                                    C.c_void_p(t.data_ptr()), _lib._ptr(g, C.c_float),
+                                                    C.byref(loss), C.c_void_p(_stream_ptr(stream))))
+        return g, loss.value
+
     def train_step(self, X, t, lr, stream=None):
         _need_f32_dev(X, 2)
         _need_f32_dev(t, 1)

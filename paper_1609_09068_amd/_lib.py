@@ -73,7 +73,8 @@ class LevelsInfo(C.Structure):
 EXPORTS = ["pr_partition", "pr_partition_get", "pr_default_build_opts", "pr_build_levels",
            "pr_levels_get_info", "pr_default_solve_opts", "pr_solve", "pr_levels_debug", "pr_free",
            "pr_last_error", "pr_version", "pr_mlp_create", "pr_mlp_set_params", "pr_mlp_get_params",
-           "pr_mlp_predict", "pr_mlp_grad", "pr_mlp_train_step", "pr_mlp_save", "pr_mlp_load",
+           "pr_mlp_predict", "pr_mlp_grad", "pr_mlp_grad_noalloc", "pr_mlp_train_step", "pr_mlp_save",
+           "pr_mlp_load",
            "pr_warm_features"]
 
 _lib = None
@@ -156,11 +157,13 @@ def load():
     lib.pr_mlp_get_params.argtypes = [VP, F32P]
     lib.pr_mlp_predict.argtypes = [VP, I64, VP, VP, VP]
     lib.pr_mlp_grad.argtypes = [VP, I64, VP, VP, F32P, P(D), VP]
+    lib.pr_mlp_grad_noalloc.argtypes = [VP, I64, VP, VP, F32P, P(D), VP]
     lib.pr_mlp_train_step.argtypes = [VP, I64, VP, VP, C.c_float, P(D), VP]
     lib.pr_mlp_save.argtypes = [VP, C.c_char_p]
     lib.pr_mlp_load.argtypes = [C.c_char_p, P(VP)]
     lib.pr_warm_features.argtypes = [VP, D, VP, VP, VP, VP, VP]
     for name in ("pr_mlp_create", "pr_mlp_set_params", "pr_mlp_get_params", "pr_mlp_predict", "pr_mlp_grad",
+                 "pr_mlp_grad_noalloc",
                  "pr_mlp_train_step", "pr_mlp_save", "pr_mlp_load", "pr_warm_features"):
         getattr(lib, name).restype = I32
     _lib = lib

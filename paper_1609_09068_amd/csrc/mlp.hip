@@ -8,6 +8,7 @@
 // so a step is bitwise reproducible for a given batch.  Adam (Kingma and Ba,
 // 2015: bias-corrected moment estimates) updates FP32 master weights, from
 // which the BF16 fragments are repacked.
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <new>
@@ -344,11 +345,28 @@ int32_t mlp_upload(Mlp& m, const float* host) {
   return PR_OK;
 }
 
+// workgroups of the gradient kernel for n rows (at most 256, so at most
+// 1024 wavefront partials whatever the batch)
+int64_t grad_groups(int64_t n) {
+  const int64_t nblk = (n + 15) / 16;
+  return std::max<int64_t>(1, std::min<int64_t>(256, (nblk + 3) / 4));
+}
+
+// gradient of the batch into m.grad / m.loss on stream s, the per-wavefront
+// partials in gpart / lpart (every partial the reduction reads is written)
+int32_t launch_grad(Mlp& m, int64_t n, const float* X, const float* T, float* gpart, double* lpart,
+                    hipStream_t s) {
+  const int64_t G = grad_groups(n);
+  const int64_t P = G * (kT / 64);
+  k_mlp_grad<<<(unsigned)G, kT, 0, s>>>(m.packed, m.master, X, T, n, (float)(2.0 / (double)n), gpart, lpart);
+  k_mlp_reduce<<<(kMlpParams + kT - 1) / kT, kT, 0, s>>>(gpart, P, lpart, m.grad, m.loss);
+  PR_HIP_CHECK(hipGetLastError());
+  return PR_OK;
+}
+
 // gradient of the batch into m.grad / m.loss on stream s
 int32_t mlp_grad(Mlp& m, int64_t n, const float* X, const float* T, hipStream_t s) {
-  const int64_t nblk = (n + 15) / 16;
-  const int64_t G = std::max<int64_t>(1, std::min<int64_t>(256, (nblk + 3) / 4));
-  const int64_t P = G * (kT / 64);
+  const int64_t P = grad_groups(n) * (kT / 64);
   if (P > m.gpart_cap) {
     if (m.gpart) (void)hipFree(m.gpart);
     if (m.lpart) (void)hipFree(m.lpart);
@@ -358,9 +376,46 @@ int32_t mlp_grad(Mlp& m, int64_t n, const float* X, const float* T, hipStream_t 
     PR_HIP_CHECK(hipMalloc(&m.lpart, sizeof(double) * P));
     m.gpart_cap = P;
   }
-  k_mlp_grad<<<(unsigned)G, kT, 0, s>>>(m.packed, m.master, X, T, n, (float)(2.0 / (double)n), m.gpart, m.lpart);
-  k_mlp_reduce<<<(kMlpParams + kT - 1) / kT, kT, 0, s>>>(m.gpart, P, m.lpart, m.grad, m.loss);
-  PR_HIP_CHECK(hipGetLastError());
+  return launch_grad(m, n, X, T, m.gpart, m.lpart, s);
+}
+
+// ------------------------------------------- gradient without allocation
+// pr_mlp_grad_noalloc keeps the per-wavefront partials in this file-scope
+// array instead of a buffer the network allocates on first use: room for
+// kScratchParts partial gradients (the most the gradient kernel writes for
+// any batch) and their loss partials, 17.8 MiB that every device the library
+// runs on holds until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is a stand-in, not a device address): it
+// uses the address hipGetSymbolAddress gave for the current device.
+constexpr int64_t kScratchParts = 1024;
+constexpr size_t kScratchGradBytes = sizeof(float) * (size_t)kMlpParams * kScratchParts;
+constexpr size_t kScratchBytes = kScratchGradBytes + sizeof(double) * kScratchParts;
+static_assert(kScratchGradBytes % 256 == 0, "loss partials start on a 256-byte boundary");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// the array's address on the current device, looked up once per device
+int32_t scratch_address(void** out) {
+  int dev = 0;
+  PR_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d: the static gradient scratch supports devices 0..%d", dev, kMaxDevices - 1);
+    return PR_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    PR_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+      set_error("hipGetSymbolAddress returned no address for the gradient scratch on device %d", dev);
+      return PR_EHIP;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
   return PR_OK;
 }
 
@@ -489,6 +544,35 @@ int32_t pr_mlp_grad(pr_mlp_t* h, int64_t n, const float* X_dev, const float* t_d
   Mlp* m = as_mlp(h);
   const hipStream_t s = (hipStream_t)hip_stream;
   PR_TRY(mlp_grad(*m, n, X_dev, t_dev, s));
+  double l = 0.0;
+  PR_HIP_CHECK(hipMemcpyAsync(&l, m->loss, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (grad_host)
+    PR_HIP_CHECK(hipMemcpyAsync(grad_host, m->grad, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, s));
+  PR_HIP_CHECK(hipStreamSynchronize(s));
+  if (loss) *loss = l / (double)n;
+  return PR_OK;
+}
+
+int32_t pr_mlp_grad_noalloc(pr_mlp_t* h, int64_t n, const float* X_dev, const float* t_dev, float* grad_host,
+                            double* loss, void* hip_stream) {
+  PR_TRY(check_mlp(h));
+  if (n <= 0 || !X_dev || !t_dev) {
+    set_error("bad arguments (n = %lld)", (long long)n);
+    return PR_EINVAL;
+  }
+  const int64_t P = grad_groups(n) * (kT / 64);
+  if (P > kScratchParts) {
+    set_error("%lld gradient partials needed; the static scratch holds %lld", (long long)P,
+              (long long)kScratchParts);
+    return PR_EINVAL;
+  }
+  void* base = nullptr;
+  PR_TRY(scratch_address(&base));
+  Mlp* m = as_mlp(h);
+  const hipStream_t s = (hipStream_t)hip_stream;
+  float* gpart = reinterpret_cast<float*>(base);
+  double* lpart = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(base) + kScratchGradBytes);
+  PR_TRY(launch_grad(*m, n, X_dev, t_dev, gpart, lpart, s));
   double l = 0.0;
   PR_HIP_CHECK(hipMemcpyAsync(&l, m->loss, sizeof(double), hipMemcpyDeviceToHost, s));
   if (grad_host)
