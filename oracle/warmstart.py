@@ -190,3 +190,85 @@ def forward_bf16(theta, X):
     h1 = gelu(to_bf16(X) @ to_bf16(P["W1"]).T + P["b1"])
     h2 = gelu(to_bf16(h1) @ to_bf16(P["W2"]).T + P["b2"])
     return to_bf16(h2) @ to_bf16(P["W3"][0]) + P["b3"][0]
+
+
+GELU_CURVATURE = 0.7979  # max over x of |d^2/dx^2 x Phi(x)| = |phi(x) (2 - x^2)| (at x = 0: 2 / sqrt(2 pi))
+
+
+def loss_and_grad_bf16(theta, X, t):
+    """loss_and_grad with every matrix-product operand of the forward and the
+    backward pass rounded to bfloat16 (products summed in float64, everything
+    else exact): the arithmetic a BF16-operand, wide-accumulator gradient
+    performs, up to the order of its sums."""
+    P = unpack(theta)
+    X = np.asarray(X, dtype=np.float64)
+    b = to_bf16
+    z1 = b(X) @ b(P["W1"]).T + P["b1"]
+    h1 = gelu(z1)
+    z2 = b(h1) @ b(P["W2"]).T + P["b2"]
+    h2 = gelu(z2)
+    y = b(h2) @ b(P["W3"][0]) + P["b3"][0]
+    B = len(y)
+    d = y - np.asarray(t, dtype=np.float64)
+    L = float(np.mean(d * d))
+    dy = 2.0 * d / B
+    gW3 = b(dy) @ b(h2)
+    gb3 = dy.sum()
+    dh2 = b(dy)[:, None] * b(P["W3"][0])[None, :]
+    dz2 = dh2 * gelu_grad(z2)
+    gW2 = b(dz2).T @ b(h1)
+    gb2 = dz2.sum(axis=0)
+    dh1 = b(dz2) @ b(P["W2"])
+    dz1 = dh1 * gelu_grad(z1)
+    gW1 = b(dz1).T @ b(X)
+    gb1 = dz1.sum(axis=0)
+    return L, np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), [gb3]])
+
+
+def grad_bf16_bound(theta, X, t, u=2.0 ** -8):
+    """First-order bound, entry by entry, on |g_computed - g| for the gradient
+    of the mean squared error when every matrix-product operand of the forward
+    and backward passes is rounded to bfloat16 (unit roundoff u) and products
+    are summed exactly.  Errors are carried through the chain rule as absolute
+    bounds: a product of a (error ea) and b (error eb), both rounded, is off by
+    at most ea |b| + |a| eb + 2u |a| |b|; an elementwise factor GELU'(z) adds
+    |dh| GELU_CURVATURE e_z.  Also returns the magnitude gradient (the same
+    sums over absolute values), which bounds float32 accumulation error when
+    scaled by the accumulation depth times 2^-24."""
+    P = unpack(theta)
+    Xs = np.asarray(X, dtype=np.float64)
+    y, c = forward(theta, Xs, keep=True)
+    B = len(y)
+    aX = np.abs(Xs)
+    aW1, aW2, aW3 = np.abs(P["W1"]), np.abs(P["W2"]), np.abs(P["W3"][0])
+    z1, h1, z2, h2 = c["z1"], np.abs(c["h1"]), c["z2"], np.abs(c["h2"])
+    # forward
+    e_z1 = 2 * u * (aX @ aW1.T)
+    e_h1 = GELU_LIPSCHITZ * e_z1
+    e_z2 = 2 * u * (h1 @ aW2.T) + e_h1 @ aW2.T
+    e_h2 = GELU_LIPSCHITZ * e_z2
+    e_y = 2 * u * (h2 @ aW3) + e_h2 @ aW3
+    # backward
+    d = y - np.asarray(t, dtype=np.float64)
+    dy = np.abs(2.0 * d / B)
+    e_dy = 2.0 * e_y / B
+    e_gW3 = e_dy @ h2 + dy @ e_h2 + 2 * u * (dy @ h2)
+    e_gb3 = e_dy.sum()
+    dh2 = dy[:, None] * aW3[None, :]
+    e_dh2 = e_dy[:, None] * aW3[None, :] + 2 * u * dh2
+    gp2 = np.abs(gelu_grad(z2))
+    dz2 = dh2 * gp2
+    e_dz2 = e_dh2 * gp2 + dh2 * GELU_CURVATURE * e_z2
+    e_gW2 = e_dz2.T @ h1 + dz2.T @ e_h1 + 2 * u * (dz2.T @ h1)
+    e_gb2 = e_dz2.sum(axis=0)
+    dh1 = dz2 @ aW2
+    e_dh1 = e_dz2 @ aW2 + 2 * u * dh1
+    gp1 = np.abs(gelu_grad(z1))
+    dz1 = dh1 * gp1
+    e_dz1 = e_dh1 * gp1 + dh1 * GELU_CURVATURE * e_z1
+    e_gW1 = e_dz1.T @ aX + 2 * u * (dz1.T @ aX)
+    e_gb1 = e_dz1.sum(axis=0)
+    bound = np.concatenate([e_gW1.ravel(), e_gb1, e_gW2.ravel(), e_gb2, e_gW3.ravel(), [e_gb3]])
+    mag = np.concatenate([(dz1.T @ aX).ravel(), dz1.sum(axis=0), (dz2.T @ h1).ravel(), dz2.sum(axis=0),
+                          dy @ h2, [dy.sum()]])
+    return bound, mag

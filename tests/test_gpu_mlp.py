@@ -85,6 +85,41 @@ def test_gradient_matches_oracle(prm, n):
         assert r < 6e-2, (name, r)
 
 
+@pytest.mark.parametrize("n", [16, 999, 20000])
+def test_gradient_entry_by_entry(prm, n):
+    """Every gradient entry against the oracle: within the entrywise
+    first-order BF16 rounding bound of the exact gradient (plus float32
+    accumulation over at most 2^10 sequential partials, 2^-14 of the
+    magnitude gradient), and close to the oracle's emulation of the same
+    BF16 rounding decisions."""
+    pr, torch = prm
+    _say("mlp grad entrywise", n)
+    rng = np.random.default_rng(300 + n)
+    th = ws.init_params(7).astype(np.float32)
+    net = pr.Mlp.create(2)
+    net.set_params(th)
+    X = _features(rng, n)
+    t = (0.5 * X[:, 3] + 0.2 * np.sin(X[:, 0]) + rng.normal(0, 0.1, n)).astype(np.float32)
+    g, _ = net.grad(torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda"))
+    g = g.astype(np.float64)
+    th64, X64, t64 = th.astype(np.float64), X.astype(np.float64), t.astype(np.float64)
+    _, g_ref = ws.loss_and_grad(th64, X64, t64)
+    _, g_emu = ws.loss_and_grad_bf16(th64, X64, t64)
+    bound, mag = ws.grad_bf16_bound(th64, X64, t64)
+    tol = bound + 2.0 ** -14 * mag + 1e-12
+    for name, lo, hi in [("W1", 0, 256), ("b1", 256, 320), ("W2", 320, 4416), ("b2", 4416, 4480),
+                         ("W3", 4480, 4544), ("b3", 4544, 4545)]:
+        d_ex = np.abs(g[lo:hi] - g_ref[lo:hi])
+        d_em = np.abs(g[lo:hi] - g_emu[lo:hi])
+        e_em = np.abs(g_emu[lo:hi] - g_ref[lo:hi])
+        _say(f"  {name}: |gpu-exact|/bound max {np.max(d_ex / tol[lo:hi]):.3e}, |gpu-emu|/mag max "
+             f"{np.max(d_em / mag[lo:hi]):.3e}, |emu-exact|/mag max {np.max(e_em / mag[lo:hi]):.3e}")
+        assert np.all(d_ex <= tol[lo:hi]), name
+        # the same rounding decisions: float32 sums and an occasional one-ulp
+        # difference of a rounded operand remain, far below the BF16 rounding
+        assert np.all(d_em <= 2.0 ** -9 * mag[lo:hi] + 1e-12), name
+
+
 def test_gradient_is_deterministic(prm):
     pr, torch = prm
     rng = np.random.default_rng(5)

@@ -9,6 +9,8 @@ from oracle.componentwise import componentwise_solve
 from oracle.pagerank import pagerank_dense, pagerank_power_series
 from oracle.partition import partition_arrays_equal, partition_theorem
 
+from _rowcheck import check_rows
+
 pytestmark = pytest.mark.gpu
 
 C = 0.85
@@ -269,6 +271,8 @@ def test_config2_full_size_mixed(prm, c2, method):
     err = _rel_l1(R, ref)
     _say("c2 rel_l1", err, "iters_max", st["iters_max"], "ms", st["time_ms"])
     assert err <= 1e-6
+    # row by row: residual bound, exact rows outside SCCs, per-vertex error
+    check_rows(g, p.comp, p.comp_type, C, R, 1e-6, ref=ref, cert_abs=st["cert_abs"])
     # partition of the full graph is bit-exact
     if method == 0:
         assert partition_arrays_equal(p.as_dict(), partition_theorem(g.n, g.row_ptr, g.col))
@@ -281,8 +285,6 @@ def test_config3_full_size(prm):
     method both meet the oracle's FP64 residual bound, which holds at any
     size: ||R - R*||_1 <= ||W - (I - cA^T)R||_1 / (1 - c)."""
     import os
-
-    from oracle.pagerank import residual_bound
 
     pr, torch = prm
     g = config_graph("c3_deep_5m")
@@ -299,9 +301,8 @@ def test_config3_full_size(prm):
         R = torch.empty_like(Wd)
         rc, st = pr.pr_solve(lv, C, Wd, R, eps=1e-6, precision=0, method=method, use_graph=1, **opts)
         assert rc == 0 and st["cert_rel"] <= 1e-6 and st["n_not_converged"] == 0
-        bound, AT = residual_bound(g.n, g.row_ptr, g.col, C, W, R.cpu().numpy(), AT)
-        _say("c3 residual bound", bound)
-        assert bound <= 1e-6
+        bound, AT = check_rows(g, part.comp, part.comp_type, C, R.cpu().numpy(), 1e-6, W=W, AT=AT)
+        assert st["cert_rel"] >= 0.999 * bound
 
 
 def test_autotuner_sweeps_caches_and_stays_exact(prm, c1, tmp_path, monkeypatch):

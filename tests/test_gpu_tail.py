@@ -11,6 +11,8 @@ from oracle.componentwise import componentwise_solve
 from oracle.pagerank import pagerank_dense, pagerank_power_series
 from oracle.partition import partition_theorem
 
+from _rowcheck import check_rows
+
 pytestmark = pytest.mark.gpu
 C = 0.85
 
@@ -234,6 +236,7 @@ def test_web_1m_in_the_timed_launch_shape(prm):
     net = pr.Mlp.load_file(path)
     Wd = torch.tensor(W, device="cuda")
     R = torch.empty_like(Wd)
+    AT = None
     for team in (16384, 65536):
         lv = pr.pr_build_levels(part, g.row_ptr, g.col, rows_per_wave=64, small_cutoff=16, team_edges=team)
         for opts, rep in itertools.product((dict(warm_start=net), {}), range(2)):
@@ -241,9 +244,11 @@ def test_web_1m_in_the_timed_launch_shape(prm):
             R.fill_(-1.0)
             rc, st = pr.pr_solve(lv, C, Wd, R, eps=1e-6, precision=0, tail_estimate=1, use_graph=1, **opts)
             assert rc == 0
-            err = np.abs(R.cpu().numpy() - ref).sum() / ref.sum()
+            Rh = R.cpu().numpy()
+            err = np.abs(Rh - ref).sum() / ref.sum()
             assert err <= 1e-6 and st["cert_rel"] <= 1e-6, (err, st["cert_rel"])
             assert st["n_not_converged"] == 0
+            AT = check_rows(g, part.comp, part.comp_type, C, Rh, 1e-6, ref=ref, cert_abs=st["cert_abs"], AT=AT)[1]
 
 
 def test_tail_is_inert_under_the_papers_stop_rule(prm):

@@ -258,3 +258,28 @@ def test_tail_with_noisy_guess_meets_the_bound(seed):
         assert res <= c * st["last"][C_] * (1 + 1e-8) + slack
         n_eq += bool(abs(res - c * st["last"][C_]) <= slack)
     assert n_eq > 0  # some SCCs did stop on the estimate
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_grad_bf16_bound_covers_emulated_rounding(seed):
+    """The entrywise first-order gradient bound covers the emulated
+    BF16-operand gradient (same rounding decisions as a BF16 kernel), and it
+    catches planted mistakes: W2's gradient transposed, or b2's with the
+    wrong sign."""
+    rng = np.random.default_rng(seed)
+    n = 2000
+    th = ws.init_params(seed + 10)
+    X = np.column_stack([rng.uniform(0, 7, n), rng.uniform(0, 7, n), rng.uniform(0, 3, n),
+                         rng.uniform(0.3, 4, n)])
+    t = 0.5 * X[:, 3] + rng.normal(0, 0.3, n)
+    _, g = ws.loss_and_grad(th, X, t)
+    _, ge = ws.loss_and_grad_bf16(th, X, t)
+    bound, mag = ws.grad_bf16_bound(th, X, t)
+    assert np.all(np.abs(ge - g) <= bound * (1 + 1e-6) + 1e-15)
+    assert np.all(bound >= 0) and np.all(mag >= np.abs(g) * (1 - 1e-12))
+    w2 = g.copy()
+    w2[320:4416] = g[320:4416].reshape(64, 64).T.ravel()
+    assert np.any(np.abs(w2 - g) > bound)
+    b2 = g.copy()
+    b2[4416:4480] *= -1.0
+    assert np.any(np.abs(b2 - g) > bound)
