@@ -8,10 +8,10 @@ vertices and 200M edges (giant SCC of half the vertices, 8% dangling).
    series return R whose FP64 residual bound, computed by the oracle, is at
    most 1e-6 (Sec. 4.4: ||R - R*||_1 <= ||W - (I - cA^T)R||_1 / (1 - c)),
    and the solve's own cert_rel is that bound.
- * Row by row: every row outside an SCC (one-vertex components and CACs,
-   solved exactly in one pass, Sec. 4.3.1) has a residual at FP64 rounding
-   level, so no vertex there can be wrong by more than rounding; the worst
-   row and the worst SCC are printed."""
+ * Row by row, for the componentwise method: every row outside an SCC
+   (one-vertex components and CACs, solved exactly in one pass, Sec. 4.3.1)
+   has a residual at FP64 rounding level, so no vertex there can be wrong by
+   more than rounding; the worst row and the worst SCC are printed."""
 import sys
 import time
 
@@ -74,5 +74,5 @@ def test_c5_mixed_meets_1e6_row_by_row(c5, c, path):
     _say(f"rc={rc} cert_rel={st['cert_rel']:.3e} trunc={st['cert_trunc_rel']:.3e} "
          f"rounds={st['refine_rounds']} terms_max={st['iters_max']} ms={st['time_ms']:.1f}")
     assert rc == 0 and st["n_not_converged"] == 0
-    bound, _ = check_rows(g, part.comp, part.comp_type, c, Rh, 1e-6, AT=AT)
+    bound, _ = check_rows(g, part.comp, part.comp_type, c, Rh, 1e-6, AT=AT, componentwise=path != "plain")
     assert st["cert_rel"] >= 0.999 * bound and st["cert_rel"] <= 1e-6

@@ -272,7 +272,7 @@ def test_config2_full_size_mixed(prm, c2, method):
     _say("c2 rel_l1", err, "iters_max", st["iters_max"], "ms", st["time_ms"])
     assert err <= 1e-6
     # row by row: residual bound, exact rows outside SCCs, per-vertex error
-    check_rows(g, p.comp, p.comp_type, C, R, 1e-6, ref=ref, cert_abs=st["cert_abs"])
+    check_rows(g, p.comp, p.comp_type, C, R, 1e-6, ref=ref, cert_abs=st["cert_abs"], componentwise=method == 0)
     # partition of the full graph is bit-exact
     if method == 0:
         assert partition_arrays_equal(p.as_dict(), partition_theorem(g.n, g.row_ptr, g.col))
@@ -301,7 +301,8 @@ def test_config3_full_size(prm):
         R = torch.empty_like(Wd)
         rc, st = pr.pr_solve(lv, C, Wd, R, eps=1e-6, precision=0, method=method, use_graph=1, **opts)
         assert rc == 0 and st["cert_rel"] <= 1e-6 and st["n_not_converged"] == 0
-        bound, AT = check_rows(g, part.comp, part.comp_type, C, R.cpu().numpy(), 1e-6, W=W, AT=AT)
+        bound, AT = check_rows(g, part.comp, part.comp_type, C, R.cpu().numpy(), 1e-6, W=W, AT=AT,
+                               componentwise=method == 0)
         assert st["cert_rel"] >= 0.999 * bound
 
 
