@@ -200,7 +200,8 @@ typedef struct pr_solve_opts {
                            ((1-rho)(1-c)) <= eps ||W'_C||_1, which bounds ||R' - R*_C||_1 exactly as
                            the plain rule does (the residual of R' is (P_{k+1} - rho P_k)/(1-rho)).
                            The plain test is tried first.  After a kept starting guess the rule
-                           runs on the residual series r_0, r_1, ... (rho from r_2 on).
+                           runs on the residual series r_0, r_1, ... (rho from r_2 on).  With
+                           PR_METHOD_PLAIN the rule runs on the whole graph's series.
                            Default 0. */
   int32_t refine;       /* FP64 residual certificate and refinement (Sec. 4.4): after the solve,
                            r = W - (I - c A^T) R is formed in FP64 over every edge and
@@ -210,7 +211,11 @@ typedef struct pr_solve_opts {
                            same method, to the looser target 0.25 eps / cert_rel, and R += d.
                            0 (default) = at most 2 such rounds; k > 0 = at most k; -1 = no residual
                            pass (cert_rel is then the truncation bound alone). */
-  int32_t reserved[2];
+  int32_t cold;         /* 1 = launch every gang phase (large SCCs, or the whole graph for
+                           PR_METHOD_PLAIN) for the worst-case term bound instead of the terms
+                           earlier solves of this plan needed plus a margin: the launch cost of a
+                           first solve.  Results do not depend on it.  Default 0. */
+  int32_t reserved[1];
 } pr_solve_opts;
 
 void pr_default_solve_opts(pr_solve_opts* o);

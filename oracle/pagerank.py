@@ -131,7 +131,7 @@ def pagerank_random_walks(n, row_ptr, col, c, W, walks_per_unit, seed):
 
 
 def pagerank_power_series(n, row_ptr, col, c, W, *, stop="cert", eps=1e-6, tol=None,
-                          max_iter=1_000_000, AT=None, loops=False):
+                          max_iter=1_000_000, AT=None, loops=False, tail=False):
     """The power series of Sec. 4.3.2 on the whole graph (the paper's baseline,
     "method 1" of Sec. 5.2):  P_0 = W,  P_{k+1} = c A^T P_k,  R = sum_k P_k.
 
@@ -142,6 +142,13 @@ def pagerank_power_series(n, row_ptr, col, c, W, *, stop="cert", eps=1e-6, tol=N
                a relative 1-norm error below eps.
       "paper": stop after the first k with max(P_k) < tol (the listing of
                Sec. 4.3.2; an absolute max-norm rule).
+    tail (with "cert"): the certified geometric tail estimate on the whole
+    graph, the rule the componentwise solve applies per SCC.  After term
+    P_{k+1}, with rho = ||P_k||_1 / ||P_{k-1}||_1 in (0, 1), the candidate
+    R' = P_0 + ... + P_k + rho/(1-rho) P_k has residual W - (I - cA^T)R' =
+    (P_{k+1} - rho P_k)/(1-rho); the series stops with R' once that residual's
+    norm is at most eps (1-c) ||W||_1 (the plain test is tried first).  The
+    returned last norm is then the residual norm divided by c.
     Returns (R, iterations, ||P_K||_1).
     """
     if AT is None:
@@ -152,21 +159,37 @@ def pagerank_power_series(n, row_ptr, col, c, W, *, stop="cert", eps=1e-6, tol=N
     wnorm = float(np.sum(np.abs(W)))
     k = 0
     last = wnorm
+    norm_prev, norm_prev2 = wnorm, None  # ||P_k||_1 and ||P_{k-1}||_1
     while k < max_iter:
         if stop == "cert" and wnorm == 0.0:
             break
-        p = c * (AT @ p)
-        R += p
+        q = c * (AT @ p)
         k += 1
-        last = float(np.sum(np.abs(p)))
+        qn = float(np.sum(np.abs(q)))
         if stop == "cert":
-            if last <= eps * (1.0 - c) * wnorm:
+            if qn <= eps * (1.0 - c) * wnorm:
+                R += q
+                last = qn
                 break
+            if tail and norm_prev2 is not None and norm_prev2 > 0.0:
+                rho = norm_prev / norm_prev2
+                if 0.0 < rho < 1.0:
+                    res = float(np.sum(np.abs(q - rho * p))) / (1.0 - rho)
+                    if res <= eps * (1.0 - c) * wnorm:
+                        R += rho / (1.0 - rho) * p
+                        last = res / c
+                        break
         elif stop == "paper":
-            if p.size == 0 or float(np.max(p)) < tol:
+            if q.size == 0 or float(np.max(q)) < tol:
+                R += q
+                last = qn
                 break
         else:
             raise ValueError(stop)
+        R += q
+        last = qn
+        norm_prev2, norm_prev = norm_prev, qn
+        p = q
     return R, k, last
 
 

@@ -39,7 +39,8 @@ class SolveOpts(C.Structure):
                 ("use_graph", C.c_int32), ("eps", C.c_double), ("tol", C.c_double),
                 ("max_iter", C.c_int64), ("warm_start", C.c_void_p), ("trace", C.c_int32),
                 ("kernel_timing", C.c_int32), ("warm_scope", C.c_int32), ("small_direct", C.c_int32),
-                ("tail_estimate", C.c_int32), ("refine", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("tail_estimate", C.c_int32), ("refine", C.c_int32), ("cold", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class SolveStats(C.Structure):

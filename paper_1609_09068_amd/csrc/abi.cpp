@@ -272,6 +272,10 @@ int32_t pr_solve(pr_levels_t* lh, double c, const void* W_dev, void* R_dev, cons
     set_error("tail_estimate = %d, expected 0 or 1", o.tail_estimate);
     return PR_EINVAL;
   }
+  if (o.cold != 0 && o.cold != 1) {
+    set_error("cold = %d, expected 0 or 1", o.cold);
+    return PR_EINVAL;
+  }
   if (o.refine < -1 || o.refine > 16) {
     set_error("refine = %d, expected -1 (no residual pass), 0 (default) or 1..16 rounds", o.refine);
     return PR_EINVAL;

@@ -603,7 +603,7 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
   p.int_src = plain ? lv.full_src : lv.int_src;
   p.vpath = lv.vpath;
   p.direct_max = plain ? 0 : o.small_direct;
-  p.tail = (!plain && o.tail_estimate && o.stop == PR_STOP_CERT_L1) ? 1 : 0;
+  p.tail = (o.tail_estimate && o.stop == PR_STOP_CERT_L1) ? 1 : 0;
   p.signed_w = signed_w ? 1 : 0;
   p.mslot_ptr = lv.mslot_ptr;
   p.mslot_src = lv.mslot_src;
@@ -730,6 +730,7 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
   // results never depend on the bound.
   auto hint_at = [&](int gang) -> size_t { return (size_t)(p.tail ? 1 : 0) * lv.h_gang_sccs.size() + gang; };
   auto budget = [&](int gang) -> int64_t {
+    if (o.cold) return kb;
     const int64_t h = lv.h_gang_hint[hint_at(gang)];
     return h > 0 ? std::min(kb, h + std::max<int64_t>(4, h / 4)) : kb;
   };

@@ -291,3 +291,29 @@ def test_tail_with_zero_mass_sccs(prm):
         assert d.max() <= 1 and np.count_nonzero(d) <= 2
         dead = scc & (sto["iters"] == 0)
         assert dead.any() and (it[dead] == 0).all()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_plain_method_with_tail_matches_oracle(prm, seed):
+    """The plain whole-graph series stopped on the tail estimate: the same
+    term count as the oracle's whole-graph rule in FP64 (hub rows summed in
+    pieces included), R within eps of the dense solve, and a replayed graph
+    bitwise equal to the eager solve."""
+    pr, torch = prm
+    g = _hub_graph(60 + seed)
+    W = np.random.default_rng(seed).uniform(0.5, 1.5, g.n)
+    _say("plain + tail seed", seed)
+    Re, rc, st, lv = _run(prm, g, W, dict(build_plain=1), method=1, eps=1e-9, precision=1, tail_estimate=1)
+    Rref, kref, _ = pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-9, tail=True)
+    _, kplain, _ = pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-9)
+    dense = pagerank_dense(g.n, g.row_ptr, g.col, C, W)
+    _say("terms", st["iters_max"], "oracle", kref, "without the estimate", kplain)
+    assert rc == 0 and st["iters_max"] == kref and kref < kplain
+    assert np.abs(Re - dense).sum() / dense.sum() <= 1e-9
+    assert np.allclose(Re, Rref, rtol=1e-11)
+    Wd = torch.tensor(W, dtype=torch.float64, device="cuda")
+    Rg = torch.empty_like(Wd)
+    for _ in range(2):
+        rc, stg = pr.pr_solve(lv, C, Wd, Rg, method=1, eps=1e-9, precision=1, tail_estimate=1, use_graph=1)
+        torch.cuda.synchronize()
+        assert rc == 0 and np.array_equal(Rg.cpu().numpy(), Re)

@@ -491,3 +491,37 @@ def test_residual_rows_of_exact_and_planted_errors():
     for u in succ:
         want[u] += C * e / outdeg[v]
     assert np.allclose(r2 - r, want, rtol=0, atol=1e-12)
+
+
+def test_whole_graph_tail_estimate_pins():
+    """The whole-graph series with the tail estimate: on a directed cycle
+    (P_k = c^k W, rho = c exactly) it stops after two terms with the exact
+    R = W/(1-c); on a strongly connected graph it is the componentwise rule on
+    its single SCC (same term count, same R up to rounding); on random graphs
+    it is within eps of the dense solve and its residual norm is c times the
+    returned last norm (the residual identity of the estimate)."""
+    n = 12
+    g = csr_from_edges(n, list(range(n)), [(i + 1) % n for i in range(n)])
+    R, k, _ = PR.pagerank_power_series(n, g.row_ptr, g.col, C, np.ones(n), eps=1e-10, tail=True)
+    assert k == 2 and np.allclose(R, 1.0 / (1.0 - C), rtol=1e-14)
+    # one SCC: a cycle through every vertex plus random chords
+    rng = np.random.default_rng(9)
+    n = 300
+    order = rng.permutation(n)
+    src = list(order) + list(rng.integers(0, n, 900))
+    dst = list(np.roll(order, -1)) + list(rng.integers(0, n, 900))
+    g = csr_from_edges(n, src, dst)
+    W = rng.uniform(0.5, 1.5, n)
+    Rp, kp, lp = PR.pagerank_power_series(n, g.row_ptr, g.col, C, W, eps=1e-9, tail=True)
+    Rc, st = CW.componentwise_solve(n, g.row_ptr, g.col, C, W, eps=1e-9, tail=True, return_stats=True)
+    assert int(st["iters"].max()) == kp and np.allclose(Rp, Rc, rtol=1e-12)
+    for seed in range(4):
+        g = random_digraph(200, 900, 40 + seed)
+        W = np.random.default_rng(seed).uniform(0.5, 1.5, g.n)
+        Rt, kt, lt = PR.pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-8, tail=True)
+        Rn, kn, _ = PR.pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-8)
+        ref = PR.pagerank_dense(g.n, g.row_ptr, g.col, C, W)
+        assert kt <= kn
+        assert np.abs(Rt - ref).sum() / ref.sum() <= 1e-8
+        r, _, _ = PR.residual_rows(g.n, g.row_ptr, g.col, C, W, Rt)
+        assert np.abs(r).sum() == pytest.approx(C * lt, rel=1e-9)
