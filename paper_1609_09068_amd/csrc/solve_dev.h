@@ -589,6 +589,45 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
         }
       }
     }
+    if (ns <= 4u) {
+      // sources of earlier items that are already published are added now
+      // and dropped from the list.  The walk adds a vertex's sources of
+      // earlier items before its sources in the item, each group in edge
+      // order, so the sum is the same whether they are added here or there:
+      // the result does not depend on timing.
+      const uint32_t sl[4] = {s0, s1, s2, s3};
+      double xe[4];
+      bool all = true;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const bool ext = (uint32_t)m < ns && (sl[m] & kExt);
+        xe[m] = ext ? ld_x(p.x, (int)(sl[m] & ~kExt)) : 0.0;
+        all = all && (!ext || x_ok(xe[m]));
+      }
+      if (all) {
+        uint32_t keep[4] = {0u, 0u, 0u, 0u};
+        uint32_t nk = 0u;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          if ((uint32_t)m < ns && (sl[m] & kExt)) acc += xe[m];
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          if ((uint32_t)m < ns && !(sl[m] & kExt)) {
+            if (nk == 0u) keep[0] = sl[m];
+            else if (nk == 1u) keep[1] = sl[m];
+            else if (nk == 2u) keep[2] = sl[m];
+            else keep[3] = sl[m];
+            ++nk;
+          }
+        }
+        s0 = keep[0];
+        s1 = keep[1];
+        s2 = keep[2];
+        s3 = keep[3];
+        ns = nk;
+      }
+    }
     if (ns > 4u) {  // many sources: the ones of earlier items are added now, in edge order
       for (uint32_t e = lo; e < hi; e += 4) {
         int u[4];
@@ -726,9 +765,17 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
                       : (int)w == prev          ? xprev
                                                 : ld_lx((int)w);
             }
+            // sources of earlier items first, then the ones in the item
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-              if ((uint32_t)m < n) {
+              if ((uint32_t)m < n && (w4[m] & kExt)) {
+                ok = ok && x_ok(xs[m]);
+                r += xs[m];
+              }
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              if ((uint32_t)m < n && !(w4[m] & kExt)) {
                 ok = ok && x_ok(xs[m]);
                 r += xs[m];
               }
