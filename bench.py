@@ -330,6 +330,24 @@ def run_c4(args, pr, torch):
                       "device": torch.cuda.get_device_name(0)}), flush=True)
 
 
+def run_stream_probe(args, pr, torch):
+    """Achievable read bandwidth (pr_bandwidth_probe): buffers far larger than
+    the 256 MB MALL (HBM-bound), ones that stay resident in it (after the
+    untimed passes each pass reads from the MALL), and one that fits an XCD's
+    4 MB L2.  The gather kernels' rooflines are read against these."""
+    out = {"study": "stream probe", "device": torch.cuda.get_device_name(0), "kernel": "pr_bandwidth_probe", "rows": []}
+    for label, mib, reps in (("hbm", 4096, 10), ("hbm", 2048, 20), ("mall", 200, 100), ("mall", 96, 200),
+                             ("mall", 40, 400), ("l2", 2, 2000)):
+        x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        ms = pr.bandwidth_probe(x, reps)
+        row = {"what": f"read {mib} MiB ({label})", "ms": round(ms, 5),
+               "gb_s": round(mib * (1 << 20) / (ms * 1e-3) / 1e9, 1)}
+        out["rows"].append(row)
+        log(json.dumps(row))
+        del x
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +366,8 @@ def main():
     ap.add_argument("--study", action="store_true",
                     help="precision study: c in {0.85, 0.99} x {mixed, fp64} x {componentwise, plain}; prints one "
                          "JSON line of its own instead of the benchmark line")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="achievable HBM / MALL / L2 read bandwidth of the device; prints one JSON line of its own")
     ap.add_argument("--c4", action="store_true",
                     help="learned-start evaluation on five fresh 1M-vertex web-like graphs; prints one JSON line "
                          "of its own instead of the benchmark line")
@@ -397,6 +417,9 @@ def main():
     from graphgen import config_graph
 
     torch.cuda.set_device(0)
+    if args.stream_probe:
+        run_stream_probe(args, pr, torch)
+        return
     if args.c4:
         run_c4(args, pr, torch)
         return
