@@ -380,6 +380,15 @@ void pr_free(void* handle);
 /* Thread-local description of the last failure on this thread. */
 const char* pr_last_error(void);
 
+/* Measurement: the achievable read bandwidth of the current device, the
+ * ceiling the gather-bound kernels are reported against.  Reads the device
+ * buffer buf_dev (bytes long, 16-byte aligned) reps times with 16-byte loads
+ * from a grid of 8 workgroups per compute unit and writes the average
+ * milliseconds per pass to *ms_out (so bytes / ms is the rate).  A buffer far
+ * larger than the 256 MB last-level cache measures HBM; a smaller one, after
+ * the untimed warm-up passes, the cache.  Returns after the work completes. */
+int32_t pr_bandwidth_probe(const void* buf_dev, int64_t bytes, int32_t reps, void* hip_stream, double* ms_out);
+
 /* Library version string. */
 const char* pr_version(void);
 

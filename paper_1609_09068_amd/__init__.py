@@ -297,3 +297,13 @@ def pr_last_error() -> str:
 
 def version() -> str:
     return _lib.load().pr_version().decode()
+
+
+def bandwidth_probe(buf, reps=20, stream=None):
+    """Milliseconds per read pass over a device tensor (pr_bandwidth_probe)."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise TypeError("expected a contiguous device tensor")
+    ms = C.c_double()
+    _lib._check(_lib.load().pr_bandwidth_probe(C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(), reps,
+                                               C.c_void_p(_stream_ptr(stream)), C.byref(ms)))
+    return ms.value

@@ -76,7 +76,7 @@ EXPORTS = ["pr_partition", "pr_partition_get", "pr_default_build_opts", "pr_buil
            "pr_last_error", "pr_version", "pr_mlp_create", "pr_mlp_set_params", "pr_mlp_get_params",
            "pr_mlp_predict", "pr_mlp_grad", "pr_mlp_grad_noalloc", "pr_mlp_train_step", "pr_mlp_save",
            "pr_mlp_load",
-           "pr_warm_features"]
+           "pr_warm_features", "pr_bandwidth_probe"]
 
 _lib = None
 _owners = None
@@ -163,6 +163,8 @@ def load():
     lib.pr_mlp_save.argtypes = [VP, C.c_char_p]
     lib.pr_mlp_load.argtypes = [C.c_char_p, P(VP)]
     lib.pr_warm_features.argtypes = [VP, D, VP, VP, VP, VP, VP]
+    lib.pr_bandwidth_probe.argtypes = [VP, I64, I32, VP, P(D)]
+    lib.pr_bandwidth_probe.restype = I32
     for name in ("pr_mlp_create", "pr_mlp_set_params", "pr_mlp_get_params", "pr_mlp_predict", "pr_mlp_grad",
                  "pr_mlp_grad_noalloc",
                  "pr_mlp_train_step", "pr_mlp_save", "pr_mlp_load", "pr_warm_features"):
