@@ -171,6 +171,12 @@ int32_t pr_levels_get_info(const pr_levels_t* lv, pr_levels_info* info);
 
 #define PR_PREC_MIXED 0 /* series terms and SpMV in FP32; R, sums, norms, boundary mass in FP64 */
 #define PR_PREC_FP64 1  /* everything in FP64 */
+#define PR_PREC_AUTO 2  /* PR_PREC_MIXED when eps >= 2^-23 / (1 - c) (with PR_STOP_CERT_L1), else
+                           PR_PREC_FP64: FP32 terms leave a relative error of about 2^-24 / (1 - c)
+                           (the rounding of each term, carried through the series), so below that
+                           target the refinement rounds would cost more than FP64 terms.
+                           PR_STOP_PAPER_MAXABS: PR_PREC_MIXED.  pr_solve_stats.precision_used
+                           reports the choice. */
 
 typedef struct pr_solve_opts {
   int32_t method;    /* PR_METHOD_* */
@@ -245,7 +251,8 @@ typedef struct pr_solve_stats {
                               solve (rounding excluded) */
   double res_l1;           /* ||W - (I - c A^T) R||_1 of the returned R in FP64 (0 with refine = -1) */
   int32_t refine_rounds;   /* correction solves run (their terms and edges are included above) */
-  int32_t reserved[3];
+  int32_t precision_used;  /* PR_PREC_MIXED or PR_PREC_FP64 (the choice of PR_PREC_AUTO) */
+  int32_t reserved[2];
 } pr_solve_stats;
 
 /*

@@ -14,7 +14,7 @@ import numpy as np
 
 from . import _lib
 from .weights import expand_integer_weights  # noqa: F401
-from ._lib import (PR_METHOD_COMPONENTWISE, PR_METHOD_PLAIN, PR_PREC_FP64, PR_PREC_MIXED,  # noqa: F401
+from ._lib import (PR_METHOD_COMPONENTWISE, PR_METHOD_PLAIN, PR_PREC_AUTO, PR_PREC_FP64, PR_PREC_MIXED,  # noqa: F401
                    PR_STOP_CERT_L1, PR_STOP_PAPER_MAXABS, PRError, PR_NOT_CONVERGED)
 
 

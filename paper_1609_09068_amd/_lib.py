@@ -26,6 +26,7 @@ PR_STOP_CERT_L1 = 0
 PR_STOP_PAPER_MAXABS = 1
 PR_PREC_MIXED = 0
 PR_PREC_FP64 = 1
+PR_PREC_AUTO = 2
 
 
 class BuildOpts(C.Structure):
@@ -51,7 +52,7 @@ class SolveStats(C.Structure):
                 ("kernel_ms", C.c_double), ("kt_ms", C.c_double * 4), ("kt_count", C.c_int64 * 4),
                 ("gang_edge_iters", C.c_int64), ("gang_vert_iters", C.c_int64),
                 ("cert_trunc_rel", C.c_double), ("res_l1", C.c_double), ("refine_rounds", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("precision_used", C.c_int32), ("reserved", C.c_int32 * 2)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "kt_ms", "kt_count")}

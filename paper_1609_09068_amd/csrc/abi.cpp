@@ -248,7 +248,7 @@ int32_t pr_solve(pr_levels_t* lh, double c, const void* W_dev, void* R_dev, cons
     set_error("unknown method %d", o.method);
     return PR_EINVAL;
   }
-  if (o.precision != PR_PREC_MIXED && o.precision != PR_PREC_FP64) {
+  if (o.precision != PR_PREC_MIXED && o.precision != PR_PREC_FP64 && o.precision != PR_PREC_AUTO) {
     set_error("unknown precision %d", o.precision);
     return PR_EINVAL;
   }

@@ -105,9 +105,13 @@ int32_t autotune_levels(Levels& lv, hipStream_t s) {
     o.precision = PR_PREC_MIXED;
     double best_ms = 1e300;
     int32_t rc = PR_OK;
-    for (int rpw : {16, 4, 64, 1}) {
-      for (int small : {64, 16}) {
-        for (int team : {65536, 16384}) {
+    // every shape is timed as the median of three solves per method after one
+    // untimed solve; a shape later in this order replaces the best only when
+    // it is more than 1.5% faster, so shapes within the timing noise of each
+    // other do not flip from one sweep to the next
+    for (int rpw : {64, 16, 4, 1}) {
+      for (int small : {16, 64}) {
+        for (int team : {16384, 65536}) {
           lv.opts.rows_per_wave = rpw;
           lv.opts.small_cutoff = small;
           lv.opts.team_edges = team;
@@ -118,13 +122,18 @@ int32_t autotune_levels(Levels& lv, hipStream_t s) {
             if (method == PR_METHOD_PLAIN && !lv.full_ptr) continue;
             o.method = method;
             pr_solve_stats st;
-            for (int rep = 0; rep < 2 && !rc; ++rep) rc = solve_levels(lv, 0.85, W, R, o, s, &st);
-            if (rc > 0) rc = PR_OK;  // not converged within max_iter: still a valid timing
+            double t[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int rep = 0; rep < 4 && !rc; ++rep) {
+              rc = solve_levels(lv, 0.85, W, R, o, s, &st);
+              if (rc > 0) rc = PR_OK;  // not converged within max_iter: still a valid timing
+              t[rep] = st.kernel_ms;
+            }
             if (rc) break;
-            ms += st.kernel_ms;
+            std::sort(t + 1, t + 4);
+            ms += t[2];
           }
           if (rc) break;
-          if (ms < best_ms) {
+          if (ms < best_ms * (best_ms < 1e299 ? 0.985 : 1.0)) {
             best_ms = ms;
             best = Choice{rpw, small, team};
           }

@@ -949,9 +949,13 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
 // precision to the looser target 0.25 eps / cert (its FP32 rounding is
 // relative to d, which is about cert times smaller than R), R += d, and the
 // residual again (Sec. 4.4: ||R - R*||_1 <= ||r||_1 / (1 - c)).
-int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_solve_opts& o,
+int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_solve_opts& o_in,
                      hipStream_t s, pr_solve_stats* st) {
   const auto host_t0 = std::chrono::steady_clock::now();
+  pr_solve_opts o = o_in;
+  if (o.precision == PR_PREC_AUTO)  // FP32 terms leave about 2^-24 / (1 - c) of relative error
+    o.precision = (o.stop != PR_STOP_CERT_L1 || o.eps >= std::ldexp(1.0, -23) / (1.0 - c)) ? PR_PREC_MIXED
+                                                                                         : PR_PREC_FP64;
   const bool residual = o.refine >= 0 && lv.n > 0;
   pr_solve_stats a{};
   int32_t rc = solve_once(lv, c, W, R, o, s, &a, false, residual);
@@ -1002,6 +1006,7 @@ int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_
     refined_to_eps = !(a.cert_rel > o.eps);
   }
   a.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host_t0).count();
+  a.precision_used = o.precision;
   if (st) *st = a;
   return (a.n_not_converged || !refined_to_eps) ? PR_NOT_CONVERGED : PR_OK;
 }

@@ -144,3 +144,18 @@ def test_unrefined_bound_above_eps_is_reported(prm, c1):
     assert st["refine_rounds"] == 1 and rc == pr._lib.PR_NOT_CONVERGED
     assert st["cert_rel"] > 1e-15 and bound > 1e-15
     assert bound <= 1e-11 and st["cert_rel"] <= 1e-11
+
+
+@pytest.mark.parametrize("c,want", [(0.85, 0), (0.99, 1)])
+def test_auto_precision(prm, c1, c, want):
+    """PR_PREC_AUTO: FP32 terms at c = 0.85 and eps 1e-6 (their rounding,
+    about 2^-24 / (1-c) = 4e-7, is below eps), FP64 terms at c = 0.99 (6e-6);
+    the same result as the explicit choice, bit for bit, and within eps by
+    the oracle's residual bound."""
+    pr, torch = prm
+    g, lv = c1
+    rc, st, R = _run(prm, lv, g, c, precision=pr.PR_PREC_AUTO, eps=1e-6, tail_estimate=1)
+    rc2, st2, R2 = _run(prm, lv, g, c, precision=want, eps=1e-6, tail_estimate=1)
+    bound, _ = residual_bound(g.n, g.row_ptr, g.col, c, np.ones(g.n), R)
+    assert rc == 0 and st["precision_used"] == want and st2["precision_used"] == want
+    assert np.array_equal(R, R2) and bound <= 1e-6
