@@ -39,16 +39,26 @@ def transition_dense(n, row_ptr, col, loops=False):
     return A
 
 
-def transition_T_csr(n, row_ptr, col, loops=False):
-    """A^T as a scipy CSR matrix: row v holds 1/outdeg(u) for every edge u->v
-    (self-loops only with loops=True)."""
+def transition_T_csr(n, row_ptr, col, loops=False, weight=None):
+    """A^T as a scipy CSR matrix: row v holds a_uv for every edge u->v
+    (self-loops only with loops=True).  Unweighted, a_uv = 1/outdeg(u); for a
+    weighted graph (Def. 3.4, a Markov chain's transition weights, one weight
+    per edge in col order) a_uv = w_uv / s_u with s_u the total weight of u's
+    kept out-edges (repeated edges add up; a vertex whose kept out-edges all
+    weigh zero has a zero row, like a dangling vertex)."""
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
     src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
     keep = (src != col) | loops
     src, dst = src[keep], col[keep]
-    deg = np.bincount(src, minlength=n).astype(np.float64)
-    val = 1.0 / deg[src]
+    if weight is None:
+        deg = np.bincount(src, minlength=n).astype(np.float64)
+        val = 1.0 / deg[src]
+    else:
+        wv = np.asarray(weight, dtype=np.float64)[keep]
+        s = np.bincount(src, weights=wv, minlength=n)
+        val = np.zeros_like(wv)
+        np.divide(wv, s[src], out=val, where=s[src] > 0)
     return sp.csr_matrix((val, (dst, src)), shape=(n, n))
 
 

@@ -445,6 +445,42 @@ def test_integer_weights_as_parallel_edges(seed):
     assert not np.allclose(CW.componentwise_solve(g.n, g.row_ptr, g.col, C, W, eps=1e-13), Rw, rtol=1e-3)
 
 
+def test_weighted_sparse_transition_closed_form():
+    """The sparse weighted A^T (used for the series and the residual of
+    weighted graphs) on the closed-form chain above: the series with it gives
+    R_0 = (1 + c) / (1 - 3c^2/4); the weights are not normalised by edge
+    count (a planted mistake, 1/outdeg, gives R_1 = 1 + c R_0 / 2)."""
+    rp = np.array([0, 2, 3, 3])
+    col = np.array([1, 2, 0])
+    w = np.array([3.0, 1.0, 1.0])
+    AT = PR.transition_T_csr(3, rp, col, weight=w)
+    R, _, _ = PR.pagerank_power_series(3, rp, col, C, np.ones(3), eps=1e-15, AT=AT)
+    r0 = (1 + C) / (1 - 0.75 * C * C)
+    np.testing.assert_allclose(R, [r0, 1 + 0.75 * C * r0, 1 + 0.25 * C * r0], rtol=1e-13)
+    Ru, _, _ = PR.pagerank_power_series(3, rp, col, C, np.ones(3), eps=1e-15)
+    assert abs(Ru[1] - (1 + 0.75 * C * r0)) > 0.1
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("loops", [False, True])
+def test_weighted_sparse_series_matches_dense(seed, loops):
+    """Real weights (some zero, so a vertex can lose every out-weight), with
+    repeated edges and loops: the series with the sparse weighted A^T and its
+    residual bound agree with the dense weighted solve."""
+    g = random_digraph(200, 900, seed + 120, loops=True, duplicates=True)
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.0, 2.0, g.m) * (rng.random(g.m) > 0.1)
+    W = rng.uniform(0.5, 1.5, g.n)
+    ref = PR.pagerank_dense_weighted(g.n, g.row_ptr, g.col, w, C, W, loops=loops)
+    AT = PR.transition_T_csr(g.n, g.row_ptr, g.col, loops=loops, weight=w)
+    R, _, _ = PR.pagerank_power_series(g.n, g.row_ptr, g.col, C, W, eps=1e-14, AT=AT)
+    np.testing.assert_allclose(R, ref, rtol=1e-11)
+    bound, _ = PR.residual_bound(g.n, g.row_ptr, g.col, C, W, ref, AT=AT)
+    assert bound < 1e-13
+    # the unweighted residual of the weighted answer is not small
+    assert PR.residual_bound(g.n, g.row_ptr, g.col, C, W, ref, loops=loops)[0] > 1e-4
+
+
 def test_weight_expansion_validates_and_drops_zero_weights():
     from paper_1609_09068_amd.weights import expand_integer_weights
 
