@@ -141,6 +141,32 @@ int32_t pr_build_levels(const pr_partition_t* p, int64_t n, const int64_t* row_p
                         const int32_t* col_idx, const pr_build_opts* opts, void* hip_stream,
                         pr_levels_t** out);
 
+/*
+ * pr_build_levels_weighted -- the same plan for a weighted graph: a Markov
+ * chain's transition weights (Def. 3.4, where A's non-zero rows are scaled
+ * to sum to one; Sec. 4.3.1 uses the entries a_wu of that A).
+ *
+ * weight: host array of m doubles, one per edge in col_idx order; edge
+ * u -> v gets a_uv = w_uv / s_u with s_u the total weight of u's out-edges
+ * (self-loops only with keep_loops, repeated edges add up).  Weights must be
+ * finite and non-negative; a zero weight leaves the edge in the partition
+ * (the components and levels are those of the graph) but adds nothing to A,
+ * and a vertex whose out-edges all weigh zero is dangling.  The array is
+ * copied; the caller keeps ownership.  The partition is the unweighted one
+ * (pr_partition on the same row_ptr / col_idx).
+ *
+ * Solves on a weighted plan run the same kernels with one multiply by the
+ * edge weight in every gather (FP64 weights for x, W' and the residual, an
+ * FP32 copy for FP32 series terms) and accept every option except
+ * warm_start (PR_EINVAL: the network's features are those of unweighted
+ * graphs).  The FP64 residual certificate uses the FP64 weights.
+ * Errors: as pr_build_levels, and PR_EINVAL for a NULL, negative or
+ * non-finite weight (the message names the first bad edge).
+ */
+int32_t pr_build_levels_weighted(const pr_partition_t* p, int64_t n, const int64_t* row_ptr,
+                                 const int32_t* col_idx, const double* weight, const pr_build_opts* opts,
+                                 void* hip_stream, pr_levels_t** out);
+
 typedef struct pr_levels_info {
   int64_t n, m;             /* vertices, edges without self-loops */
   int64_t n_comp, n_levels;

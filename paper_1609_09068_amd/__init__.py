@@ -259,14 +259,25 @@ def _stream_ptr(stream):
     return getattr(stream, "cuda_stream", stream)
 
 
-def pr_build_levels(part: Partition, row_ptr, col, stream=None, **opts) -> Levels:
+def pr_build_levels(part: Partition, row_ptr, col, stream=None, weight=None, **opts) -> Levels:
+    """The solve plan; with `weight` (one float per edge, col order) the plan
+    of the weighted graph (pr_build_levels_weighted)."""
     row_ptr, col = _lib._as_csr(row_ptr, col)
     n = len(row_ptr) - 1
     o = build_opts(**opts)
     h = C.c_void_p()
-    _lib._check(_lib.load().pr_build_levels(part.handle, n, _lib._ptr(row_ptr, C.c_int64),
-                                            _lib._ptr(col, C.c_int32), C.byref(o),
-                                            C.c_void_p(_stream_ptr(stream)), C.byref(h)))
+    lib = _lib.load()
+    if weight is None:
+        rc = lib.pr_build_levels(part.handle, n, _lib._ptr(row_ptr, C.c_int64), _lib._ptr(col, C.c_int32),
+                                 C.byref(o), C.c_void_p(_stream_ptr(stream)), C.byref(h))
+    else:
+        w = np.ascontiguousarray(weight, dtype=np.float64)
+        if w.shape != col.shape:
+            raise ValueError(f"weight has shape {w.shape}, expected {col.shape}")
+        rc = lib.pr_build_levels_weighted(part.handle, n, _lib._ptr(row_ptr, C.c_int64), _lib._ptr(col, C.c_int32),
+                                          _lib._ptr(w, C.c_double), C.byref(o), C.c_void_p(_stream_ptr(stream)),
+                                          C.byref(h))
+    _lib._check(rc)
     return Levels(h.value, n)
 
 

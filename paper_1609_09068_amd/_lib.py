@@ -72,7 +72,7 @@ class LevelsInfo(C.Structure):
 
 
 # every symbol include/pr.h declares
-EXPORTS = ["pr_partition", "pr_partition_get", "pr_default_build_opts", "pr_build_levels",
+EXPORTS = ["pr_partition", "pr_partition_get", "pr_default_build_opts", "pr_build_levels", "pr_build_levels_weighted",
            "pr_levels_get_info", "pr_default_solve_opts", "pr_solve", "pr_levels_debug", "pr_free",
            "pr_last_error", "pr_version", "pr_mlp_create", "pr_mlp_set_params", "pr_mlp_get_params",
            "pr_mlp_predict", "pr_mlp_grad", "pr_mlp_grad_noalloc", "pr_mlp_train_step", "pr_mlp_save",
@@ -139,6 +139,8 @@ def load():
     lib.pr_default_build_opts.restype = None
     lib.pr_build_levels.argtypes = [VP, I64, P(I64), P(I32), P(BuildOpts), VP, P(VP)]
     lib.pr_build_levels.restype = I32
+    lib.pr_build_levels_weighted.argtypes = [VP, I64, P(I64), P(I32), P(C.c_double), P(BuildOpts), VP, P(VP)]
+    lib.pr_build_levels_weighted.restype = I32
     lib.pr_levels_get_info.argtypes = [VP, P(LevelsInfo)]
     lib.pr_levels_get_info.restype = I32
     lib.pr_default_solve_opts.argtypes = [P(SolveOpts)]

@@ -142,9 +142,9 @@ void pr_default_solve_opts(pr_solve_opts* o) {
   o->warm_start = nullptr;
 }
 
-int32_t pr_build_levels(const pr_partition_t* ph, int64_t n, const int64_t* row_ptr,
-                        const int32_t* col_idx, const pr_build_opts* opts, void* hip_stream,
-                        pr_levels_t** out) {
+// pr_build_levels and pr_build_levels_weighted (weight null for the former)
+static int32_t build_plan(const pr_partition_t* ph, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                          const double* weight, const pr_build_opts* opts, void* hip_stream, pr_levels_t** out) {
   if (!out) {
     set_error("out is NULL");
     return PR_EINVAL;
@@ -167,6 +167,15 @@ int32_t pr_build_levels(const pr_partition_t* ph, int64_t n, const int64_t* row_
   if (hash_csr(n, row_ptr, col_idx) != p->graph_hash) {
     set_error("the partition was computed on a different graph");
     return PR_EINVAL;
+  }
+  if (weight) {
+    const int64_t m = row_ptr[n];
+    for (int64_t e = 0; e < m; ++e) {
+      if (!(weight[e] >= 0.0) || !std::isfinite(weight[e])) {
+        set_error("weight[%lld] = %g: edge weights must be finite and non-negative", (long long)e, weight[e]);
+        return PR_EINVAL;
+      }
+    }
   }
   pr_build_opts o;
   pr_default_build_opts(&o);
@@ -195,7 +204,7 @@ int32_t pr_build_levels(const pr_partition_t* ph, int64_t n, const int64_t* row_
     set_error("out of host memory");
     return PR_ENOMEM;
   }
-  rc = build_levels(*p, row_ptr, col_idx, o, (hipStream_t)hip_stream, *lv);
+  rc = build_levels(*p, row_ptr, col_idx, weight, o, (hipStream_t)hip_stream, *lv);
   if (rc) {
     delete lv;
     return rc;
@@ -203,6 +212,21 @@ int32_t pr_build_levels(const pr_partition_t* ph, int64_t n, const int64_t* row_
   registry_add(lv, KIND_LEVELS);
   *out = reinterpret_cast<pr_levels_t*>(lv);
   return PR_OK;
+}
+
+int32_t pr_build_levels(const pr_partition_t* ph, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                        const pr_build_opts* opts, void* hip_stream, pr_levels_t** out) {
+  return build_plan(ph, n, row_ptr, col_idx, nullptr, opts, hip_stream, out);
+}
+
+int32_t pr_build_levels_weighted(const pr_partition_t* ph, int64_t n, const int64_t* row_ptr,
+                                 const int32_t* col_idx, const double* weight, const pr_build_opts* opts,
+                                 void* hip_stream, pr_levels_t** out) {
+  if (!weight) {
+    set_error("weight is NULL");
+    return PR_EINVAL;
+  }
+  return build_plan(ph, n, row_ptr, col_idx, weight, opts, hip_stream, out);
 }
 
 int32_t pr_levels_get_info(const pr_levels_t* lh, pr_levels_info* info) {

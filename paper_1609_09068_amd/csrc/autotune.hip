@@ -72,6 +72,7 @@ int32_t autotune_levels(Levels& lv, hipStream_t s) {
   hipDeviceProp_t prop;
   PR_HIP_CHECK(hipGetDeviceProperties(&prop, lv.device));
   uint64_t key = mix(lv.graph_hash, (uint64_t)lv.n);
+  if (lv.weighted) key = mix(key, lv.weight_hash);
   for (const char* q = prop.gcnArchName; *q; ++q) key = mix(key, (uint64_t)(unsigned char)*q);
   for (const char* q = pr_version(); *q; ++q) key = mix(key, (uint64_t)(unsigned char)*q);
   key = mix(key, lv.full_ptr ? 1u : 0u);

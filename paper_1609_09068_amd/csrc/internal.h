@@ -128,8 +128,17 @@ struct Levels {
   int32_t* int_src = nullptr;
   uint32_t* full_ptr = nullptr;   // [n+1] whole-graph pull CSR (method PLAIN)
   int32_t* full_src = nullptr;
-  float* inv_deg32 = nullptr;     // [n] 1/outdeg (0 for dangling)
+  float* inv_deg32 = nullptr;     // [n] 1/outdeg (0 for dangling); weighted: 1/s_u, s_u = total out-weight
   double* inv_deg64 = nullptr;    // [n]
+  // weighted graph (Def. 3.4, a_uv = w_uv / s_u): the raw weight of every
+  // edge, parallel to bnd_src, int_src and full_src (null when unweighted)
+  bool weighted = false;
+  uint64_t weight_hash = 0;
+  double* bnd_w64 = nullptr;
+  double* int_w64 = nullptr;
+  float* int_w32 = nullptr;
+  double* full_w64 = nullptr;
+  float* full_w32 = nullptr;
   Item* items = nullptr;          // [n_items]
   uint32_t* vpath = nullptr;      // [n] vertex items: path order of the CAC sweep (see k_item_paths)
   uint32_t* mslot_ptr = nullptr;  // [n+1] first slot of each row (rows of workgroup SCCs own slots)
@@ -222,8 +231,9 @@ struct Mlp {
 };
 void mlp_destroy(void* h);
 
-int32_t build_levels(const Partition& p, const int64_t* row_ptr, const int32_t* col,
+int32_t build_levels(const Partition& p, const int64_t* row_ptr, const int32_t* col, const double* weight,
                      const pr_build_opts& opts, hipStream_t stream, Levels& lv);
+uint64_t hash_weights(int64_t m, const double* weight);
 int32_t make_schedule(Levels& lv, hipStream_t stream);
 int32_t autotune_levels(Levels& lv, hipStream_t stream);
 int32_t solve_levels(Levels& lv, double c, const double* W, double* R, const pr_solve_opts& o,

@@ -91,6 +91,20 @@ uint64_t hash_csr(int64_t n, const int64_t* row_ptr, const int32_t* col) {
   return r;
 }
 
+uint64_t hash_weights(int64_t m, const double* weight) {
+  // fingerprint of the edge weights (their bit patterns), for the autotune
+  // cache key of a weighted plan
+  constexpr uint64_t kP1 = 0x9E3779B97F4A7C15ull, kP2 = 0xC2B2AE3D27D4EB4Full;
+  uint64_t h = 0x452821E638D01377ull ^ (uint64_t)m;
+  for (int64_t e = 0; e < m; ++e) {
+    uint64_t w;
+    std::memcpy(&w, weight + e, sizeof(w));
+    h ^= w * kP1;
+    h = ((h << 31) | (h >> 33)) * kP2;
+  }
+  return h ^ (h >> 29);
+}
+
 namespace {
 
 enum : uint8_t { ST_NEW = 0, ST_STACK = 1, ST_SCC = 2, ST_CAC = 3 };

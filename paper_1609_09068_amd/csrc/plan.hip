@@ -120,6 +120,77 @@ __global__ void k_emit_edges(const int64_t* row_ptr, const int32_t* col, const i
   }
 }
 
+// weighted graph (Def. 3.4): s_u = total weight of u's out-edges (loops only
+// with keep_loops) and 1/s_u; a vertex whose out-edges all weigh zero acts
+// as dangling (1/s_u = 0).  odeg keeps the number of edges.
+__global__ void k_degrees_w(const int64_t* row_ptr, const int32_t* col, const double* w, const int32_t* perm,
+                            int64_t n, int32_t keep_loops, uint32_t* odeg, float* inv32, double* inv64) {
+  int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const int32_t u = perm[i];
+  uint32_t d = 0;
+  double sw = 0.0;
+  for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+    if (col[e] != u || keep_loops) {
+      ++d;
+      sw += w[e];
+    }
+  }
+  odeg[i] = d;
+  inv64[i] = sw > 0.0 ? 1.0 / sw : 0.0;
+  inv32[i] = sw > 0.0 ? (float)(1.0 / sw) : 0.0f;
+}
+
+// weighted graph: as k_emit_edges, with the edge's position in plan-source
+// order as the sort value and the source and weight stored by position
+__global__ void k_emit_edges_w(const int64_t* row_ptr, const int32_t* col, const double* w, const int32_t* perm,
+                               const int32_t* iperm, const uint32_t* optr, int64_t n, int32_t keep_loops,
+                               uint32_t* dkey, uint32_t* pval, uint32_t* spos, double* wpos) {
+  int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const int32_t u = perm[i];
+  uint32_t pos = optr[i];
+  for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+    const int32_t v = col[e];
+    if (v == u && !keep_loops) continue;
+    dkey[pos] = (uint32_t)iperm[v];
+    pval[pos] = pos;
+    spos[pos] = (uint32_t)i;
+    wpos[pos] = w[e];
+    ++pos;
+  }
+}
+
+// after the stable sort by destination: source and weight of every edge
+__global__ void k_edge_gather(const uint32_t* pval, const uint32_t* spos, const double* wpos, int64_t m,
+                              uint32_t* sval, double* wsort) {
+  int64_t e = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (e >= m) return;
+  const uint32_t q = pval[e];
+  sval[e] = spos[q];
+  wsort[e] = wpos[q];
+}
+
+__global__ void k_split_copy_w(const uint32_t* full_ptr, const double* wsort, const uint32_t* bptr,
+                               const uint32_t* iptr, int64_t n, double* bw, double* iw64, float* iw32) {
+  int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t lo = full_ptr[i];
+  const uint32_t nb = bptr[i + 1] - bptr[i];
+  for (uint32_t j = 0; j < nb; ++j) bw[bptr[i] + j] = wsort[lo + j];
+  const uint32_t ni = iptr[i + 1] - iptr[i];
+  for (uint32_t j = 0; j < ni; ++j) {
+    const double v = wsort[lo + nb + j];
+    iw64[iptr[i] + j] = v;
+    iw32[iptr[i] + j] = (float)v;
+  }
+}
+
+__global__ void k_to_f32(const double* a, int64_t m, float* b) {
+  int64_t e = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (e < m) b[e] = (float)a[e];
+}
+
 __global__ void k_count_rows(const uint32_t* dkey, int64_t m, uint32_t* cnt) {
   int64_t e = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (e >= m) return;
@@ -194,7 +265,7 @@ Levels::~Levels() {
                 full_ptr, full_src, inv_deg32, inv_deg64, items, gangs, gsccs, gbounds, gpart, gpmx, gpdiff, gnhist,
                 gwsum, gdone, x, R, wprime, y0, y1, iters, lastnorm, counters, red, wgstats, trace,
                 seg_heads, ghubs, gpieces, gpiece_ptr, gpiece_part, ghub_pieces, warm_buf, warm_gws, vpath,
-                mslot_ptr, mslot_src, res_part, res_w, res_d};
+                mslot_ptr, mslot_src, res_part, res_w, res_d, bnd_w64, int_w64, int_w32, full_w64, full_w32};
   drop_graphs();
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (hipEvent_t e : kev) (void)hipEventDestroy(e);
@@ -202,7 +273,7 @@ Levels::~Levels() {
     if (p) (void)hipFree(p);
 }
 
-int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t* h_col,
+int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t* h_col, const double* h_weight,
                      const pr_build_opts& opts, hipStream_t s, Levels& lv) {
   const int64_t n = P.n;
   const int64_t K = P.n_comp;
@@ -213,6 +284,8 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
   lv.n_levels = P.n_levels;
   lv.opts = opts;
   lv.graph_hash = P.graph_hash;
+  lv.weighted = h_weight != nullptr;
+  if (lv.weighted) lv.weight_hash = hash_weights(m_in, h_weight);
   DevScratch scr;
   // ---- uploads
   int64_t* d_rp;
@@ -227,6 +300,11 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
   PR_TRY(scr.get(sizeof(int32_t) * n, (void**)&d_emit));
   PR_HIP_CHECK(hipMemcpyAsync(d_rp, h_row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
   if (m_in) PR_HIP_CHECK(hipMemcpyAsync(d_col, h_col, sizeof(int32_t) * m_in, hipMemcpyHostToDevice, s));
+  double* d_w = nullptr;
+  if (lv.weighted) {
+    PR_TRY(scr.get(sizeof(double) * m_in, (void**)&d_w));
+    if (m_in) PR_HIP_CHECK(hipMemcpyAsync(d_w, h_weight, sizeof(double) * m_in, hipMemcpyHostToDevice, s));
+  }
   if (n) {
     PR_HIP_CHECK(hipMemcpyAsync(d_comp, P.comp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     PR_HIP_CHECK(hipMemcpyAsync(d_emit, P.emit_pos.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
@@ -280,7 +358,10 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
   PR_TRY(scr.get(sizeof(uint32_t) * (n + 1), (void**)&optr));
   PR_TRY(dalloc(&lv.inv_deg32, n));
   PR_TRY(dalloc(&lv.inv_deg64, n));
-  if (n)
+  if (n && lv.weighted)
+    k_degrees_w<<<nblk(n), kB, 0, s>>>(d_rp, d_col, d_w, lv.perm, n, opts.keep_loops, odeg, lv.inv_deg32,
+                                       lv.inv_deg64);
+  else if (n)
     k_degrees<<<nblk(n), kB, 0, s>>>(d_rp, d_col, lv.perm, n, opts.keep_loops, odeg, lv.inv_deg32, lv.inv_deg64);
   PR_TRY(scan_u32(odeg, optr, n, s));
   uint32_t m32 = 0;
@@ -294,8 +375,24 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
   PR_TRY(scr.get(sizeof(uint32_t) * m, (void**)&dkey));
   PR_TRY(scr.get(sizeof(uint32_t) * m, (void**)&sval));
   PR_TRY(scr.get(sizeof(uint32_t) * n, (void**)&rcnt));
-  if (n) k_emit_edges<<<nblk(n), kB, 0, s>>>(d_rp, d_col, lv.perm, iperm, optr, n, opts.keep_loops, dkey, sval);
-  PR_TRY(radix_sort_pairs(dkey, sval, m, bit_length((uint64_t)std::max<int64_t>(n - 1, 0)), s));
+  double* wsort = nullptr;
+  if (lv.weighted) {
+    // sort the edges' positions, then fetch source and weight by position
+    uint32_t *pval, *spos;
+    double* wpos;
+    PR_TRY(scr.get(sizeof(uint32_t) * m, (void**)&pval));
+    PR_TRY(scr.get(sizeof(uint32_t) * m, (void**)&spos));
+    PR_TRY(scr.get(sizeof(double) * m, (void**)&wpos));
+    PR_TRY(scr.get(sizeof(double) * m, (void**)&wsort));
+    if (n)
+      k_emit_edges_w<<<nblk(n), kB, 0, s>>>(d_rp, d_col, d_w, lv.perm, iperm, optr, n, opts.keep_loops, dkey, pval,
+                                            spos, wpos);
+    PR_TRY(radix_sort_pairs(dkey, pval, m, bit_length((uint64_t)std::max<int64_t>(n - 1, 0)), s));
+    if (m) k_edge_gather<<<nblk(m), kB, 0, s>>>(pval, spos, wpos, m, sval, wsort);
+  } else {
+    if (n) k_emit_edges<<<nblk(n), kB, 0, s>>>(d_rp, d_col, lv.perm, iperm, optr, n, opts.keep_loops, dkey, sval);
+    PR_TRY(radix_sort_pairs(dkey, sval, m, bit_length((uint64_t)std::max<int64_t>(n - 1, 0)), s));
+  }
   uint32_t* fptr;
   PR_TRY(scr.get(sizeof(uint32_t) * (n + 1), (void**)&fptr));
   if (n) PR_HIP_CHECK(hipMemsetAsync(rcnt, 0, sizeof(uint32_t) * n, s));
@@ -324,11 +421,27 @@ int32_t build_levels(const Partition& P, const int64_t* h_row_ptr, const int32_t
   PR_TRY(dalloc(&lv.bnd_src, mb));
   PR_TRY(dalloc(&lv.int_src, mi));
   if (n) k_split_copy<<<nblk(n), kB, 0, s>>>(fptr, sval, lv.bnd_ptr, lv.int_ptr, n, lv.bnd_src, lv.int_src);
+  if (lv.weighted) {
+    PR_TRY(dalloc(&lv.bnd_w64, mb));
+    PR_TRY(dalloc(&lv.int_w64, mi));
+    PR_TRY(dalloc(&lv.int_w32, mi));
+    if (n)
+      k_split_copy_w<<<nblk(n), kB, 0, s>>>(fptr, wsort, lv.bnd_ptr, lv.int_ptr, n, lv.bnd_w64, lv.int_w64,
+                                            lv.int_w32);
+  }
   if (opts.build_plain) {
     PR_TRY(dalloc(&lv.full_ptr, n + 1));
     PR_TRY(dalloc(&lv.full_src, m));
     PR_HIP_CHECK(hipMemcpyAsync(lv.full_ptr, fptr, sizeof(uint32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
     if (m) PR_HIP_CHECK(hipMemcpyAsync(lv.full_src, sval, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
+    if (lv.weighted) {
+      PR_TRY(dalloc(&lv.full_w64, m));
+      PR_TRY(dalloc(&lv.full_w32, m));
+      if (m) {
+        PR_HIP_CHECK(hipMemcpyAsync(lv.full_w64, wsort, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+        k_to_f32<<<nblk(m), kB, 0, s>>>(wsort, m, lv.full_w32);
+      }
+    }
   }
 
   // ---- host copies of the pull row pointers (gang row bounds)

@@ -53,13 +53,13 @@ int32_t dalloc(T** p, size_t count) {
 
 using GangFn = void (*)(SolveParams, int, int, int);
 
-template <typename YT>
+template <typename YT, bool WT>
 GangFn gang_kernel(int rpw) {
   switch (rpw) {
-    case 64: return k_gang<YT, 64>;
-    case 16: return k_gang<YT, 16>;
-    case 4: return k_gang<YT, 4>;
-    default: return k_gang<YT, 1>;
+    case 64: return k_gang<YT, 64, WT>;
+    case 16: return k_gang<YT, 16, WT>;
+    case 4: return k_gang<YT, 4, WT>;
+    default: return k_gang<YT, 1, WT>;
   }
 }
 using HubFn = void (*)(SolveParams, int, int);
@@ -79,13 +79,16 @@ WarmGangFn gang_warm_kernel(int rpw) {
 WarmGangFn pick_gang_warm(int precision, int rpw) {
   return precision == PR_PREC_FP64 ? gang_warm_kernel<double>(rpw) : gang_warm_kernel<float>(rpw);
 }
-SegFn pick_segment(int precision, int rpw, bool warm = false, bool tail = false) {
-  const void* f = precision == PR_PREC_FP64 ? (tail ? seg_kernel_f64_tail(rpw, warm) : seg_kernel_f64(rpw, warm))
-                                            : (tail ? seg_kernel_f32_tail(rpw, warm) : seg_kernel_f32(rpw, warm));
+SegFn pick_segment(int precision, int rpw, bool warm = false, bool tail = false, bool weighted = false) {
+  const void* f = weighted ? (precision == PR_PREC_FP64 ? seg_kernel_w64(rpw, tail) : seg_kernel_w32(rpw, tail))
+                  : precision == PR_PREC_FP64
+                      ? (tail ? seg_kernel_f64_tail(rpw, warm) : seg_kernel_f64(rpw, warm))
+                      : (tail ? seg_kernel_f32_tail(rpw, warm) : seg_kernel_f32(rpw, warm));
   return reinterpret_cast<SegFn>(const_cast<void*>(f));
 }
-GangFn pick_gang(int precision, int rpw) {
-  return precision == PR_PREC_FP64 ? gang_kernel<double>(rpw) : gang_kernel<float>(rpw);
+GangFn pick_gang(int precision, int rpw, bool weighted = false) {
+  if (weighted) return precision == PR_PREC_FP64 ? gang_kernel<double, true>(rpw) : gang_kernel<float, true>(rpw);
+  return precision == PR_PREC_FP64 ? gang_kernel<double, false>(rpw) : gang_kernel<float, false>(rpw);
 }
 
 }  // namespace
@@ -549,6 +552,8 @@ static SolveParams residual_params(const Levels& lv, double c, const double* W) 
   q.int_ptr = lv.int_ptr;
   q.int_src = lv.int_src;
   q.inv64 = lv.inv_deg64;
+  q.bnd_w = lv.bnd_w64;
+  q.int_w64 = lv.int_w64;
   return q;
 }
 
@@ -562,7 +567,8 @@ static void launch_residual(const Levels& lv, double c, const double* W, const d
                             hipStream_t s) {
   const unsigned g = residual_grid(lv.n);
   k_res_prep<<<g, kThreads, 0, s>>>(R, lv.perm, lv.inv_deg64, lv.n, lv.R, lv.x);
-  k_residual<<<g, kThreads, 0, s>>>(residual_params(lv, c, W), lv.R, lv.x, rw, lv.res_part);
+  if (lv.weighted) k_residual<true><<<g, kThreads, 0, s>>>(residual_params(lv, c, W), lv.R, lv.x, rw, lv.res_part);
+  else k_residual<false><<<g, kThreads, 0, s>>>(residual_params(lv, c, W), lv.R, lv.x, rw, lv.res_part);
   k_res_sum<<<1, kThreads, 0, s>>>(lv.res_part, (int)g, out);
 }
 
@@ -601,6 +607,9 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
   p.bnd_src = lv.bnd_src;
   p.int_ptr = plain ? lv.full_ptr : lv.int_ptr;
   p.int_src = plain ? lv.full_src : lv.int_src;
+  p.bnd_w = lv.bnd_w64;
+  p.int_w64 = plain ? lv.full_w64 : lv.int_w64;
+  p.int_w32 = plain ? lv.full_w32 : lv.int_w32;
   p.vpath = lv.vpath;
   p.direct_max = plain ? 0 : o.small_direct;
   p.tail = (o.tail_estimate && o.stop == PR_STOP_CERT_L1) ? 1 : 0;
@@ -635,6 +644,10 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
   p.gpiece_part = lv.gpiece_part;
   p.n_gslots = lv.n_gslots;
   p.timeout = (unsigned long long)clock_khz * 1000ull * 30ull;  // 30 s
+  if (o.warm_start && !plain && lv.weighted) {
+    set_error("warm_start is not available for a weighted plan (the network's features are those of unweighted graphs)");
+    return PR_EINVAL;
+  }
   if (o.warm_start && !plain) {
     const Mlp* m = reinterpret_cast<const Mlp*>(o.warm_start);
     if (m->device != lv.device) {
@@ -690,17 +703,17 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
   double sumW = 0.0;
   for (int i = 0; i < kRedBlocks; ++i) sumW += wparts[2 * i];
   const int64_t kb = term_bound(o, c, sumW);
-  const SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave, p.mlp != nullptr, p.tail != 0);
-  // the variants with the starting guess or the tail estimate need more
-  // registers: size their grid to what stays resident
+  const SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave, p.mlp != nullptr, p.tail != 0, lv.weighted);
+  // the variants with the starting guess, the tail estimate or edge weights
+  // need more registers: size their grid to what stays resident
   unsigned seg_grid = (unsigned)lv.grid;
-  if (p.mlp || p.tail) {
+  if (p.mlp || p.tail || lv.weighted) {
     int occ = 0, cus = 0;
     PR_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)seg, kThreads, 0));
     PR_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, lv.device));
     seg_grid = (unsigned)std::max(1, std::min(lv.grid, std::max(occ, 1) * cus));
   }
-  const GangFn gk = pick_gang(o.precision, lv.opts.rows_per_wave);
+  const GangFn gk = pick_gang(o.precision, lv.opts.rows_per_wave, lv.weighted);
   hipEvent_t ev0, ev1;
   PR_HIP_CHECK(hipEventCreate(&ev0));
   PR_HIP_CHECK(hipEventCreate(&ev1));

@@ -50,6 +50,13 @@ struct SolveParams {
   const int32_t* int_src;
   const float* inv32;
   const double* inv64;
+  // weighted graph (Def. 3.4 with a_uv = w_uv / s_u, s_u the total weight of
+  // u's out-edges): the raw weight of every edge, parallel to bnd_src and
+  // int_src (FP32 copy for FP32 terms), and inv32/inv64 hold 1/s_u; null
+  // for a plain graph, where every weight is one and s_u the out-degree
+  const double* bnd_w;
+  const double* int_w64;
+  const float* int_w32;
   double* x;
   double* R;
   double* wprime;
@@ -277,83 +284,9 @@ __device__ inline double block_max(double v, double* lds) {
 }
 
 // ---------------------------------------------------------------- gathers
-// A lane-per-row gather hands rows with more than kLongLane sources to the
-// whole wavefront; a group of LPR lanes hands over rows longer than
-// max(kLongLane, 8 LPR).
+// A vertex item hands a row with more than kLongLane CAC sources to the
+// whole wavefront.
 constexpr uint32_t kLongLane = 32;
-
-// this lane's share (stride STRIDE from lo) of sum x[src[e]], e in [lo, hi);
-// returns false if a source is not final yet (the sum is then garbage)
-template <int STRIDE>
-__device__ inline bool lane_partial_x(const SolveParams& p, const int32_t* src, uint32_t lo, uint32_t hi,
-                                      double* out) {
-  double acc = 0.0;
-  bool ok = true;
-  uint32_t e = lo;
-  for (; e + 3 * STRIDE < hi; e += 4 * STRIDE) {
-    const int32_t s0 = src[e], s1 = src[e + STRIDE], s2 = src[e + 2 * STRIDE], s3 = src[e + 3 * STRIDE];
-    const double a0 = ld_x(p.x, s0), a1 = ld_x(p.x, s1), a2 = ld_x(p.x, s2), a3 = ld_x(p.x, s3);
-    ok = ok && x_ok(a0) && x_ok(a1) && x_ok(a2) && x_ok(a3);
-    acc += a0;
-    acc += a1;
-    acc += a2;
-    acc += a3;
-  }
-  for (; e < hi; e += STRIDE) {
-    const double a = ld_x(p.x, src[e]);
-    ok = ok && x_ok(a);
-    acc += a;
-  }
-  *out = acc;
-  return ok;
-}
-
-// per-lane blocking version: sources live in other items, so waiting here
-// cannot hold up a lane of the same wavefront
-template <int STRIDE>
-__device__ inline double lane_partial_x_wait(const SolveParams& p, const int32_t* src, uint32_t lo, uint32_t hi) {
-  double acc = 0.0;
-  if (lane_partial_x<STRIDE>(p, src, lo, hi, &acc)) return acc;
-  const unsigned long long t0 = wall_clock64();
-  int nap = 1;
-  while (true) {
-    backoff_sleep(nap);
-    if (lane_partial_x<STRIDE>(p, src, lo, hi, &acc)) return acc;
-    if (timed_out(p, t0)) return 0.0;
-  }
-}
-
-// whole-wavefront sum of x over [lo, hi), blocking (wave-uniform arguments)
-__device__ inline double wave_gather_x_wait(const SolveParams& p, const int32_t* src, uint32_t lo, uint32_t hi) {
-  const int lane = threadIdx.x & 63;
-  double part = 0.0;
-  bool ok = lane_partial_x<64>(p, src, lo + lane, hi, &part);
-  if (!__all(ok)) {
-    const unsigned long long t0 = wall_clock64();
-    int nap = 1;
-    while (true) {
-      backoff_sleep(nap);
-      ok = lane_partial_x<64>(p, src, lo + lane, hi, &part);
-      if (__all(ok)) break;
-      if (timed_out(p, t0)) {
-        part = 0.0;
-        break;
-      }
-    }
-  }
-  return wave_sum(part);
-}
-
-// whole-wavefront attempt without waiting; false if a source is not final
-__device__ inline bool wave_gather_x_try(const SolveParams& p, const int32_t* src, uint32_t lo, uint32_t hi,
-                                         double* out) {
-  const int lane = threadIdx.x & 63;
-  double part = 0.0;
-  const bool ok = lane_partial_x<64>(p, src, lo + lane, hi, &part);
-  if (!__all(ok)) return false;
-  *out = wave_sum(part);
-  return true;
-}
 
 // ------------------------------------------------------------ tiled gather
 // A wavefront sums, for up to 64 consecutive rows [ra, ra+nr), the values
@@ -363,7 +296,8 @@ __device__ inline bool wave_gather_x_try(const SolveParams& p, const int32_t* sr
 // each row's part of the chunk from LDS, 64/RPW rows at a time with LPR
 // lanes per row.  Row sums accumulate chunk by chunk in edge order, so the
 // result does not depend on timing.  With WAIT_X the values are the x
-// vector and a chunk is re-read until every source is final.
+// vector and a chunk is re-read until every source is final.  With WT every
+// value is multiplied by its edge's weight wt[e] as it is staged.
 constexpr int kChunk = 512;
 constexpr uint32_t kBigPart = 16;  // per lane of a row: above this the whole wavefront sums the row's part
 
@@ -375,9 +309,9 @@ struct WaveTile {
   unsigned long long* rdy;  // latest end of a readiness wait in the current item (trace)
 };
 
-template <int RPW, typename VT, bool WAIT_X>
+template <int RPW, typename VT, bool WAIT_X, bool WT = false>
 __device__ __attribute__((always_inline)) VT wave_tile_gather(const SolveParams& p, const uint32_t* ptr, const int32_t* src, const VT* val,
-                               int ra, int nr, WaveTile* t) {
+                               int ra, int nr, WaveTile* t, const VT* wt = nullptr) {
   constexpr int LPR = 64 / RPW;
   const int lane = threadIdx.x & 63;
   VT* buf = reinterpret_cast<VT*>(t->buf);
@@ -393,10 +327,12 @@ __device__ __attribute__((always_inline)) VT wave_tile_gather(const SolveParams&
   for (uint32_t cs = E0; cs < E1; cs += kChunk) {
     const uint32_t ce = cs + kChunk < E1 ? cs + kChunk : E1;
     int32_t idx[8];
+    VT wv[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const uint32_t e = cs + lane + 64 * j;
       idx[j] = e < ce ? src[e] : -1;
+      if constexpr (WT) wv[j] = e < ce ? wt[e] : (VT)0;
     }
     if constexpr (WAIT_X) {
       double v[8];
@@ -436,15 +372,19 @@ __device__ __attribute__((always_inline)) VT wave_tile_gather(const SolveParams&
       }
       if (p.trace && lane == 0) atomicMax(t->rdy, wall_clock64());
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
+      for (int j = 0; j < 8; ++j) {
+        if constexpr (WT) v[j] *= (double)wv[j];
         if (idx[j] >= 0) buf[lane + 64 * j] = (VT)v[j];
+      }
     } else {
       VT v[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) v[j] = idx[j] >= 0 ? val[idx[j]] : (VT)0;
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
+      for (int j = 0; j < 8; ++j) {
+        if constexpr (WT) v[j] *= wv[j];
         if (idx[j] >= 0) buf[lane + 64 * j] = v[j];
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
@@ -502,7 +442,16 @@ __device__ __attribute__((always_inline)) VT wave_tile_gather(const SolveParams&
 // x_v = c R_v / outdeg(v) is published the moment R_v is final when a later
 // item needs it (a CAC edge into a later item), else when the item ends.
 // Every sum has a fixed order (the schedule depends only on the graph).
+// With WT (a weighted graph) x_v = c R_v / s_v and every source's x is
+// multiplied by its edge weight; the four listed sources keep their weights
+// beside them in LDS.
 constexpr int kWalkBatches = 2;
+// byte offset of the listed sources' weights in a vertex item's LDS (after
+// x, R, acc, c / outdeg, the source lists and the path tables)
+constexpr size_t kVertWtOff =
+    (4 * kThreads * sizeof(double) + kThreads * sizeof(uint4) + (3 * kThreads + 1 + kWaves) * sizeof(int32_t) + 31) &
+    ~(size_t)31;
+template <bool WT>
 __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, int vbeg, int vend, WaveTile* tile,
                                                           double* lds) {
   const int lane = threadIdx.x & 63;
@@ -522,6 +471,8 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
   int32_t* sQ = reinterpret_cast<int32_t*>(sI + kThreads);    // by vertex: path position | start << 16
   int32_t* sPB = sQ + kThreads;                               // path k: positions [sPB[k], sPB[k+1])
   int32_t* sWc = sPB + kThreads + 1;                          // path starts per wavefront
+  // by position: the weights of the four listed sources (WT only)
+  double* sWt = lds + kVertWtOff / sizeof(double);
   constexpr uint32_t kExt = 0x80000000u;  // source entry: vertex index of an earlier item (else local index)
   auto ld_lx = [&](int k) { return __hip_atomic_load(sX + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
   auto st_lx = [&](int k, double val) {
@@ -548,7 +499,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
     if (i == 0) sPB[npath] = nvi;  // visible after the barrier below
   }
   double acc = 0.0;
-  if (nr > 0) acc = wave_tile_gather<64, double, true>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile);
+  if (nr > 0) acc = wave_tile_gather<64, double, true, WT>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile, p.bnd_w);
   if (act) {
     acc += p.W[p.perm[v]];
     p.wprime[v] = acc;
@@ -570,8 +521,14 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
     }
     return xv;
   };
+  // edge weight of a CAC edge (one for a plain graph)
+  auto ew = [&](uint32_t e) -> double {
+    if constexpr (WT) return p.int_w64[e];
+    else return 1.0;
+  };
   // 1. note the CAC sources (four ids loaded at a time)
   uint32_t s0 = 0u, s1 = 0u, s2 = 0u, s3 = 0u, ns = 0u;
+  double g0 = 1.0, g1 = 1.0, g2 = 1.0, g3 = 1.0;  // their weights (WT)
   if (act && !lng) {
     for (uint32_t e = lo; e < hi; e += 4) {
       int u[4];
@@ -581,10 +538,11 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
       for (int j = 0; j < 4; ++j) {
         if (u[j] >= 0) {
           const uint32_t w = inside(u[j]) ? (uint32_t)(u[j] - vbeg) : (kExt | (uint32_t)u[j]);
-          if (ns == 0u) s0 = w;
-          else if (ns == 1u) s1 = w;
-          else if (ns == 2u) s2 = w;
-          else if (ns == 3u) s3 = w;
+          const double g = (WT && ns < 4u) ? ew(e + j) : 1.0;
+          if (ns == 0u) s0 = w, g0 = g;
+          else if (ns == 1u) s1 = w, g1 = g;
+          else if (ns == 2u) s2 = w, g2 = g;
+          else if (ns == 3u) s3 = w, g3 = g;
           ++ns;
         }
       }
@@ -596,6 +554,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
       // order, so the sum is the same whether they are added here or there:
       // the result does not depend on timing.
       const uint32_t sl[4] = {s0, s1, s2, s3};
+      const double gl[4] = {g0, g1, g2, g3};
       double xe[4];
       bool all = true;
 #pragma unroll
@@ -606,18 +565,19 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
       }
       if (all) {
         uint32_t keep[4] = {0u, 0u, 0u, 0u};
+        double gk[4] = {1.0, 1.0, 1.0, 1.0};
         uint32_t nk = 0u;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          if ((uint32_t)m < ns && (sl[m] & kExt)) acc += xe[m];
+          if ((uint32_t)m < ns && (sl[m] & kExt)) acc += WT ? xe[m] * gl[m] : xe[m];
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           if ((uint32_t)m < ns && !(sl[m] & kExt)) {
-            if (nk == 0u) keep[0] = sl[m];
-            else if (nk == 1u) keep[1] = sl[m];
-            else if (nk == 2u) keep[2] = sl[m];
-            else keep[3] = sl[m];
+            if (nk == 0u) keep[0] = sl[m], gk[0] = gl[m];
+            else if (nk == 1u) keep[1] = sl[m], gk[1] = gl[m];
+            else if (nk == 2u) keep[2] = sl[m], gk[2] = gl[m];
+            else keep[3] = sl[m], gk[3] = gl[m];
             ++nk;
           }
         }
@@ -625,6 +585,10 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
         s1 = keep[1];
         s2 = keep[2];
         s3 = keep[3];
+        g0 = gk[0];
+        g1 = gk[1];
+        g2 = gk[2];
+        g3 = gk[3];
         ns = nk;
       }
     }
@@ -641,7 +605,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
         for (int j = 0; j < 4; ++j) {
           if (u[j] >= 0 && !inside(u[j])) {
             if (!x_ok(xv[j])) xv[j] = wait_x(u[j]);
-            acc += xv[j];
+            acc += WT ? xv[j] * ew(e + j) : xv[j];
           }
         }
       }
@@ -657,7 +621,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
     double part = 0.0;
     for (uint32_t e = blo + lane; e < bhi; e += 64) {
       const int u = p.int_src[e];
-      if (!inside(u)) part += wait_x(u);
+      if (!inside(u)) part += WT ? wait_x(u) * ew(e) : wait_x(u);
     }
     part = wave_sum(part);
     if (lane == b) acc += part;
@@ -673,6 +637,12 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
     sA[q] = acc;
     sC[q] = p.c * p.inv64[v];
     sS[q] = make_uint4(s0, s1, s2, s3);
+    if constexpr (WT) {
+      sWt[4 * q] = g0;
+      sWt[4 * q + 1] = g1;
+      sWt[4 * q + 2] = g2;
+      sWt[4 * q + 3] = g3;
+    }
     __hip_atomic_store(sI + q, (uint32_t)i | (kind << 8) | ((ns > 4u ? 7u : ns) << 10) | (early ? 0x2000u : 0u) | 0x8000u,
                        __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
@@ -705,7 +675,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
     while (!stop && nb++ < kWalkBatches) {
       // the next eight positions in one LDS round trip; hops of kind 0 and 1
       // then run from registers
-      double a8[8], c8[8];
+      double a8[8], c8[8], w8[8];
       uint32_t i8[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -718,6 +688,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
         const int qq = q + j < qe ? q + j : qe - 1;
         a8[j] = sA[qq];
         c8[j] = sC[qq];
+        if constexpr (WT) w8[j] = sWt[4 * qq];  // kind 1: the weight of the one source
       }
       // eight written hops of kind 0 or 1 (kind bit 9 clear) inside the
       // path: a straight run with no per-hop branch on the kind
@@ -727,7 +698,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int loc = (int)(i8[j] & 0xffu);
-          const double r = (i8[j] & 0x100u) ? a8[j] + xprev : a8[j];
+          const double r = (i8[j] & 0x100u) ? (WT ? a8[j] + w8[j] * xprev : a8[j] + xprev) : a8[j];
           const double xv = c8[j] * r;
           st_lx(loc, xv);
           sR[loc] = r;
@@ -748,18 +719,23 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
           bool ok = (i8[j] & 0x8000u) != 0u;
           if (!ok) {
           } else if (kind == 1u) {
-            r += xprev;
+            r += WT ? w8[j] * xprev : xprev;
           } else if (kind == 2u) {
             const uint32_t n = (i8[j] >> 10) & 7u;
             const uint4 s4 = sS[q];
             const uint32_t w4[4] = {s4.x, s4.y, s4.z, s4.w};
+            double g4[4] = {1.0, 1.0, 1.0, 1.0};
+            if constexpr (WT) {
+#pragma unroll
+              for (int m = 0; m < 4; ++m) g4[m] = sWt[4 * q + m];
+            }
             double xs[4];
-            int nl = 0;  // self-loops (a plan built with keep_loops)
+            double nl = 0.0;  // self-loops (a plan built with keep_loops), by weight
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
               const uint32_t w = w4[m];
               const bool self = (uint32_t)m < n && w == (uint32_t)loc;
-              nl += self ? 1 : 0;
+              nl += self ? g4[m] : 0.0;
               xs[m] = ((uint32_t)m >= n || self) ? 0.0
                       : (w & kExt)              ? ld_x(p.x, (int)(w & ~kExt))
                       : (int)w == prev          ? xprev
@@ -770,33 +746,33 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
             for (int m = 0; m < 4; ++m) {
               if ((uint32_t)m < n && (w4[m] & kExt)) {
                 ok = ok && x_ok(xs[m]);
-                r += xs[m];
+                r += WT ? xs[m] * g4[m] : xs[m];
               }
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
               if ((uint32_t)m < n && !(w4[m] & kExt)) {
                 ok = ok && x_ok(xs[m]);
-                r += xs[m];
+                r += WT ? xs[m] * g4[m] : xs[m];
               }
             }
             // the loop's share returns to the vertex: R = (W' + sources) / (1 - c a_vv)
-            if (nl) r /= 1.0 - (double)nl * c8[j];
+            if (nl != 0.0) r /= 1.0 - nl * c8[j];
           } else if (kind == 3u) {
             const uint32_t l0 = p.int_ptr[vbeg + loc], l1 = p.int_ptr[vbeg + loc + 1];
-            int nl = 0;
+            double nl = 0.0;
             for (uint32_t e = l0; e < l1 && ok; ++e) {
               const int u = p.int_src[e];
               if (!inside(u)) continue;
               if (u - vbeg == loc) {
-                ++nl;
+                nl += ew(e);
                 continue;
               }
               const double xv = u - vbeg == prev ? xprev : ld_lx(u - vbeg);
               if (!x_ok(xv)) ok = false;
-              else r += xv;
+              else r += WT ? xv * ew(e) : xv;
             }
-            if (nl) r /= 1.0 - (double)nl * c8[j];
+            if (nl != 0.0) r /= 1.0 - nl * c8[j];
           }
           if (!ok) {
             stop = true;
@@ -945,12 +921,20 @@ __device__ __attribute__((always_inline)) WarmOut warm_preamble(const SolveParam
   return o;
 }
 
+// the inside-component edge weights in the type of the series terms
+template <typename YT>
+__device__ inline const YT* term_w(const SolveParams& p) {
+  if constexpr (sizeof(YT) == 8) return reinterpret_cast<const YT*>(p.int_w64);
+  else return reinterpret_cast<const YT*>(p.int_w32);
+}
+
 // An SCC with at most 256 vertices, iterated by one wavefront.  After the
 // weights are gathered, the component's internal rows are copied into LDS
 // (one-byte local source ids, two-byte row offsets) when they fit, so every
 // term touches only LDS and registers (R stays in registers, four rows per
-// lane).
-template <typename YT, bool WARM, bool TAIL = false>
+// lane).  A weighted graph (WT) reads its rows and weights from the plan
+// every term instead.
+template <typename YT, bool WARM, bool TAIL = false, bool WT = false>
 __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned long long* wst, WaveTile* tile) {
   const int lane = threadIdx.x & 63;
   const int vbeg = p.comp_vbeg[rank];
@@ -967,7 +951,8 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
     const int v = vbeg + i;
     double wp = 0.0;
     const int nr = nv - 64 * j < 64 ? nv - 64 * j : 64;
-    if (nr > 0) wp = wave_tile_gather<64, double, true>(p, p.bnd_ptr, p.bnd_src, p.x, vbeg + 64 * j, nr, tile);
+    if (nr > 0)
+      wp = wave_tile_gather<64, double, true, WT>(p, p.bnd_ptr, p.bnd_src, p.x, vbeg + 64 * j, nr, tile, p.bnd_w);
     if (act) wp += p.W[p.perm[v]];
     Rj[j] = wp;
     inv[j] = act ? p.inv32[v] : 0.0f;
@@ -981,7 +966,7 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
   // stage the internal rows in LDS (the tile is free after the gathers)
   const uint32_t eb = p.int_ptr[vbeg];
   const uint32_t ne = p.int_ptr[vbeg + nv] - eb;
-  const bool staged = ne <= (uint32_t)sizeof(tile->buf);
+  const bool staged = !WT && ne <= (uint32_t)sizeof(tile->buf);
   uint8_t* lsrc = reinterpret_cast<uint8_t*>(tile->buf);
   uint16_t* lptr = reinterpret_cast<uint16_t*>(tile->racc);  // racc + rlo + rhi: 1 KB >= 2 * 257
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1022,7 +1007,8 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
       M[lane * ld + nv] = wp;
       for (uint32_t e = rlo[0]; e < rhi[0]; ++e) {
         const int u = p.int_src[e] - vbeg;
-        M[lane * ld + u] -= p.c * p.inv64[vbeg + u];
+        if constexpr (WT) M[lane * ld + u] -= p.c * p.inv64[vbeg + u] * p.int_w64[e];
+        else M[lane * ld + u] -= p.c * p.inv64[vbeg + u];
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1045,7 +1031,8 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
       double acc = wp - xr;
       for (uint32_t e = rlo[0]; e < rhi[0]; ++e) {
         const int u = p.int_src[e] - vbeg;
-        acc += p.c * p.inv64[vbeg + u] * M[u * ld + nv];
+        if constexpr (WT) acc += p.c * p.inv64[vbeg + u] * p.int_w64[e] * M[u * ld + nv];
+        else acc += p.c * p.inv64[vbeg + u] * M[u * ld + nv];
       }
       rr = fabs(acc);
     }
@@ -1205,6 +1192,14 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
               s0 += (h[0] + h[1]) + (h[2] + h[3]);
               s1 += (h[4] + h[5]) + (h[6] + h[7]);
             }
+          } else if constexpr (WT) {
+            const YT* wt = term_w<YT>(p);
+            uint32_t e = rlo[j];
+            for (; e + 1 < rhi[j]; e += 2) {
+              s0 += ya[p.int_src[e] - vbeg] * wt[e];
+              s1 += ya[p.int_src[e + 1] - vbeg] * wt[e + 1];
+            }
+            if (e < rhi[j]) s0 += ya[p.int_src[e] - vbeg] * wt[e];
           } else {
             uint32_t e = rlo[j];
             for (; e + 1 < rhi[j]; e += 2) {
@@ -1265,8 +1260,9 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
 // One SCC iterated by one workgroup.  When the component fits, its rows
 // (two-byte local sources), 1/outdeg, R and both term vectors live in LDS
 // during the iteration; otherwise the vectors stay in global memory, touched
-// only by this workgroup.
-template <typename YT, int RPW, bool WARM, bool TAIL = false>
+// only by this workgroup.  A weighted graph (WT) takes the last path (rows,
+// weights and terms from global memory).
+template <typename YT, int RPW, bool WARM, bool TAIL = false, bool WT = false>
 __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, int rank, double* red, unsigned long long* wst, WaveTile* tiles,
                            unsigned char* raw, size_t raw_bytes) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1295,7 +1291,7 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
   double part = 0.0;
   for (int ra = w0; ra < w1; ra += 64) {
     const int nr = w1 - ra < 64 ? w1 - ra : 64;
-    double wp = wave_tile_gather<64, double, true>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile);
+    double wp = wave_tile_gather<64, double, true, WT>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile, p.bnd_w);
     if (lane < nr) {
       const int v = ra + lane;
       wp += p.W[p.perm[v]];
@@ -1346,13 +1342,13 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
   const uint32_t sb = p.mslot_ptr[vb];
   const uint32_t nslot = p.mslot_ptr[ve] - sb;
   const size_t need = (2 * ((size_t)nv + 1) + nslot) * sizeof(YT) + 64;
-  const bool staged = need <= raw_bytes && nv <= kThreads * kRPT && nslot <= (uint32_t)(kThreads * kSPT);
+  const bool staged = !WT && need <= raw_bytes && nv <= kThreads * kRPT && nslot <= (uint32_t)(kThreads * kSPT);
   // (the plan cuts slots only for components of at most 65535 vertices: the
   // ids are 16-bit and the component size is the zero pad)
   // larger components: the same two phases with the slots read from the plan
   // every term (L2-resident) and R, 1/outdeg and the row slot ranges in LDS
   const size_t need_big = (3 * (size_t)nv + 2 + nslot) * sizeof(YT) + 8 * (size_t)nv + 4 * ((size_t)nv + 1) + 64;
-  const bool staged_big = !staged && need_big <= raw_bytes && nv <= 65535;
+  const bool staged_big = !WT && !staged && need_big <= raw_bytes && nv <= 65535;
   if (staged_big) {
     double* lR = reinterpret_cast<double*>(raw);
     YT* l0 = reinterpret_cast<YT*>(lR + nv);
@@ -1619,7 +1615,7 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
         double pm = 0.0, dpart = 0.0;
         for (int ra = w0; ra < w1; ra += 64) {
           const int nr = w1 - ra < 64 ? w1 - ra : 64;
-          const YT s = wave_tile_gather<RPW, YT, false>(p, ptr, src, ya, ra, nr, tile);
+          const YT s = wave_tile_gather<RPW, YT, false, WT>(p, ptr, src, ya, ra, nr, tile, term_w<YT>(p));
           if (lane < nr) {
             const int v = ra + lane;
             YT iv;
@@ -1692,13 +1688,15 @@ static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + kThrea
                       (3 * kThreads + 1 + kWaves) * sizeof(int32_t) <=
                   kSegLds,
               "vertex item LDS");
+static_assert(kWaves * sizeof(WaveTile) + kVertWtOff + 4 * kThreads * sizeof(double) <= kSegLds,
+              "vertex item LDS with edge weights");
 
 // Persistent segment kernel.  Items are handed out in plan order by one
 // atomic counter per segment (one atomic per item).  This cannot deadlock,
 // whatever the number of resident workgroups: an item only waits for items
 // handed out before it, and those are held by running workgroups; the
 // lowest unfinished item has nothing left to wait for.
-template <typename YT, int RPW, bool WARM, bool TAIL = false>
+template <typename YT, int RPW, bool WARM, bool TAIL = false, bool WT = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ? 1 : ((TAIL || RPW < 16) ? 2 : 3)))) void k_segment(SolveParams p) {
   __shared__ double s_red[24];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kSegLds];
@@ -1729,15 +1727,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ?
     }
     int slot;
     if (it.kind == ITEM_VERTS) {
-      run_verts(p, it.a, it.b, &tiles[wave], reinterpret_cast<double*>(second));
+      run_verts<WT>(p, it.a, it.b, &tiles[wave], reinterpret_cast<double*>(second));
       slot = S_T_VERTS;
     } else if (it.kind == ITEM_SMALL) {
       const int r = it.a + wave;
       YT* ybuf = reinterpret_cast<YT*>(second) + (size_t)wave * 2 * kSmallMax;
-      if (r < it.b) run_small<YT, WARM, TAIL>(p, r, ybuf, s_stats, &tiles[wave]);
+      if (r < it.b) run_small<YT, WARM, TAIL, WT>(p, r, ybuf, s_stats, &tiles[wave]);
       slot = S_T_SMALL;
     } else {
-      run_medium<YT, RPW, WARM, TAIL>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
+      run_medium<YT, RPW, WARM, TAIL, WT>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
       slot = S_T_MEDIUM;
     }
     __syncthreads();
@@ -1853,7 +1851,7 @@ __device__ inline int first_hub(const SolveParams& p, const GangDesc& gd, int r)
   return lo;
 }
 
-template <typename YT, int RPW>
+template <typename YT, int RPW, bool WT = false>
 __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int k, int final_launch) {
   __shared__ double s_red[4];
   __shared__ WaveTile s_tile[kWaves];
@@ -1895,8 +1893,9 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
     if (k == 0) {
       for (int ra = w0; ra < w1; ra += 64) {
         const int nr = w1 - ra < 64 ? w1 - ra : 64;
-        double wp = p.plain ? 0.0 : wave_tile_gather<64, double, false>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr,
-                                                                         &s_tile[wave]);
+        double wp = p.plain ? 0.0
+                            : wave_tile_gather<64, double, false, WT>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr,
+                                                                      &s_tile[wave], p.bnd_w);
         if (lane < nr) {
           const int v = ra + lane;
           wp += p.W[p.perm[v]];
@@ -1972,7 +1971,7 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
         int rb = ra + 64 < w1 ? ra + 64 : w1;
         if (nexth < rb) rb = nexth;
         const int nr = rb - ra;
-        const YT sv = wave_tile_gather<RPW, YT, false>(p, ptr, p.int_src, yr, ra, nr, &s_tile[wave]);
+        const YT sv = wave_tile_gather<RPW, YT, false, WT>(p, ptr, p.int_src, yr, ra, nr, &s_tile[wave], term_w<YT>(p));
         if (lane < nr) {
           const int v = ra + lane;
           YT iv;
@@ -2005,14 +2004,26 @@ __global__ __launch_bounds__(kThreads) void k_gang(SolveParams p, int gang, int 
       const GangPiece pc = p.gpieces[q];
       YT a0 = 0, a1 = 0, a2 = 0, a3 = 0;
       uint32_t e = pc.ebeg + lane;
-      for (; e + 192 < pc.eend; e += 256) {
-        const int32_t s0 = p.int_src[e], s1 = p.int_src[e + 64], s2 = p.int_src[e + 128], s3 = p.int_src[e + 192];
-        a0 += yr[s0];
-        a1 += yr[s1];
-        a2 += yr[s2];
-        a3 += yr[s3];
+      if constexpr (WT) {
+        const YT* wt = term_w<YT>(p);
+        for (; e + 192 < pc.eend; e += 256) {
+          const int32_t s0 = p.int_src[e], s1 = p.int_src[e + 64], s2 = p.int_src[e + 128], s3 = p.int_src[e + 192];
+          a0 += yr[s0] * wt[e];
+          a1 += yr[s1] * wt[e + 64];
+          a2 += yr[s2] * wt[e + 128];
+          a3 += yr[s3] * wt[e + 192];
+        }
+        for (; e < pc.eend; e += 64) a0 += yr[p.int_src[e]] * wt[e];
+      } else {
+        for (; e + 192 < pc.eend; e += 256) {
+          const int32_t s0 = p.int_src[e], s1 = p.int_src[e + 64], s2 = p.int_src[e + 128], s3 = p.int_src[e + 192];
+          a0 += yr[s0];
+          a1 += yr[s1];
+          a2 += yr[s2];
+          a3 += yr[s3];
+        }
+        for (; e < pc.eend; e += 64) a0 += yr[p.int_src[e]];
       }
-      for (; e < pc.eend; e += 64) a0 += yr[p.int_src[e]];
       const YT sum = wave_sum((a0 + a1) + (a2 + a3));
       if (lane == 0) p.gpiece_part[q] = (double)sum;
     }
@@ -2315,6 +2326,7 @@ __global__ __launch_bounds__(kThreads) void k_res_prep(const double* Rout, const
     xr[i] = r * inv64[i];
   }
 }
+template <bool WT>
 __global__ __launch_bounds__(kThreads) void k_residual(SolveParams p, const double* Rp, const double* xr, double* rw,
                                                        double* part) {
   __shared__ WaveTile s_tile[kWaves];
@@ -2323,8 +2335,10 @@ __global__ __launch_bounds__(kThreads) void k_residual(SolveParams p, const doub
   double sr = 0.0, sR = 0.0;
   for (int64_t ra = ((int64_t)blockIdx.x * kWaves + wave) * 64; ra < p.n; ra += (int64_t)gridDim.x * kThreads) {
     const int nr = p.n - ra < 64 ? (int)(p.n - ra) : 64;
-    const double sb = wave_tile_gather<64, double, false>(p, p.bnd_ptr, p.bnd_src, xr, (int)ra, nr, &s_tile[wave]);
-    const double si = wave_tile_gather<64, double, false>(p, p.int_ptr, p.int_src, xr, (int)ra, nr, &s_tile[wave]);
+    const double sb =
+        wave_tile_gather<64, double, false, WT>(p, p.bnd_ptr, p.bnd_src, xr, (int)ra, nr, &s_tile[wave], p.bnd_w);
+    const double si =
+        wave_tile_gather<64, double, false, WT>(p, p.int_ptr, p.int_src, xr, (int)ra, nr, &s_tile[wave], p.int_w64);
     if (lane < nr) {
       const int v = (int)ra + lane;
       const int o = p.perm[v];
@@ -2369,10 +2383,12 @@ using SegFn = void (*)(SolveParams);
 // segment kernel variants by term type and stop rule, instantiated in the
 // seg_*.hip files: the address of k_segment<YT, rpw, warm, tail> (cast to
 // SegFn by the caller; rpw is rows per wavefront, warm selects the
-// starting-guess variant)
+// starting-guess variant), and of the weighted-graph variants (no guess)
 const void* seg_kernel_f32(int rpw, bool warm);
 const void* seg_kernel_f32_tail(int rpw, bool warm);
 const void* seg_kernel_f64(int rpw, bool warm);
 const void* seg_kernel_f64_tail(int rpw, bool warm);
+const void* seg_kernel_w32(int rpw, bool tail);
+const void* seg_kernel_w64(int rpw, bool tail);
 
 }  // namespace prlib

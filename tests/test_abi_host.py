@@ -158,3 +158,24 @@ def test_build_rejects_partition_of_another_graph_differing_in_one_edge():
     out = C.c_void_p()
     rc = lib.pr_build_levels(p.handle, g.n, _i64(rp), _i32(g.col), None, None, C.byref(out))
     assert rc == _lib.PR_EINVAL and b"different graph" in lib.pr_last_error()
+
+
+def test_weighted_build_rejects_bad_weights_before_device_work():
+    """pr_build_levels_weighted refuses a NULL weight array and a negative,
+    NaN or infinite weight with PR_EINVAL (naming the first bad edge) before
+    any device work; the Python binding checks the weight array's length."""
+    lib = _lib.load()
+    g = random_digraph(500, 2000, 11)
+    p = pr.pr_partition(g.row_ptr, g.col)
+    out = C.c_void_p()
+    rc = lib.pr_build_levels_weighted(p.handle, g.n, _i64(g.row_ptr), _i32(g.col), None, None, None, C.byref(out))
+    assert rc == _lib.PR_EINVAL and b"weight is NULL" in lib.pr_last_error()
+    for bad in (-1.0, float("nan"), float("inf")):
+        w = np.ones(g.m)
+        w[g.m // 2] = bad
+        rc = lib.pr_build_levels_weighted(p.handle, g.n, _i64(g.row_ptr), _i32(g.col),
+                                          w.ctypes.data_as(C.POINTER(C.c_double)), None, None, C.byref(out))
+        assert rc == _lib.PR_EINVAL, bad
+        assert f"weight[{g.m // 2}]".encode() in lib.pr_last_error()
+    with pytest.raises(ValueError):
+        pr.pr_build_levels(p, g.row_ptr, g.col, weight=np.ones(g.m - 1))
