@@ -330,6 +330,59 @@ def run_c4(args, pr, torch):
                       "device": torch.cuda.get_device_name(0)}), flush=True)
 
 
+def run_weighted(args, pr, torch):
+    """Weighted graphs (Def. 3.4): the workload's graph with seeded synthetic
+    transition weights, uniform in [0.5, 1.5), on a weighted plan; time to
+    eps for the componentwise and plain series under both stop rules, the
+    same graph unweighted for the cost of the weights.  Accuracy is the
+    solves' own FP64 residual certificate (parity with the oracle is in the
+    tests)."""
+    from graphgen import config_graph
+
+    g = config_graph(args.config)
+    w = np.random.default_rng(7001).uniform(0.5, 1.5, g.m)
+    part = pr.pr_partition(g.row_ptr, g.col)
+    bo = dict(rows_per_wave=args.rows_per_wave or 64, small_cutoff=args.small_cutoff or 16,
+              team_edges=args.team_edges or 16384)
+    lvw = pr.pr_build_levels(part, g.row_ptr, g.col, weight=w, **bo)
+    lvu = pr.pr_build_levels(part, g.row_ptr, g.col, **bo)
+    W = torch.ones(g.n, dtype=torch.float64, device="cuda")
+    R = torch.empty_like(W)
+    out = {"study": "weighted graph (synthetic transition weights, uniform [0.5, 1.5))", "config": args.config,
+           "n": g.n, "m": g.m, "c": args.c, "eps": args.eps, "shape": bo, "legs": {},
+           "device": torch.cuda.get_device_name(0)}
+    legs = (("weighted_componentwise_tail", lvw, dict(tail_estimate=1)),
+            ("weighted_componentwise_plain_stop", lvw, {}),
+            ("weighted_plain_tail", lvw, dict(method=1, tail_estimate=1)),
+            ("weighted_plain_plain_stop", lvw, dict(method=1)),
+            ("unweighted_componentwise_tail", lvu, dict(tail_estimate=1)),
+            ("unweighted_plain_tail", lvu, dict(method=1, tail_estimate=1)))
+    for name, lv, extra in legs:
+        for _ in range(max(args.warmup, 2)):
+            pr.pr_solve(lv, args.c, W, R, eps=args.eps, use_graph=1, **extra)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rc, st = pr.pr_solve(lv, args.c, W, R, eps=args.eps, use_graph=1, **extra)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        d = {"ms": round(ms, 4), "terms_sum": st["iters_sum"], "terms_max": st["iters_max"],
+             "edge_iters": st["edge_iters"], "gedge_iter_s": round(st["edge_iters"] / (ms * 1e-3) / 1e9, 3),
+             "cert_rel": st["cert_rel"], "refine_rounds": st["refine_rounds"], "rc": rc}
+        out["legs"][name] = d
+        log(name, json.dumps(d))
+    L = out["legs"]
+    out["speedup_vs_plain_tail"] = round(L["weighted_plain_tail"]["ms"] / L["weighted_componentwise_tail"]["ms"], 3)
+    out["speedup_vs_plain_both_plain_stop"] = round(
+        L["weighted_plain_plain_stop"]["ms"] / L["weighted_componentwise_plain_stop"]["ms"], 3)
+    out["weighted_over_unweighted_componentwise"] = round(
+        L["weighted_componentwise_tail"]["ms"] / L["unweighted_componentwise_tail"]["ms"], 3)
+    print(json.dumps(out), flush=True)
+    lvw.free()
+    lvu.free()
+    part.free()
+
+
 def run_stream_probe(args, pr, torch):
     """Achievable read bandwidth (pr_bandwidth_probe): buffers far larger than
     the 256 MB MALL (HBM-bound), ones that stay resident in it (after the
@@ -368,6 +421,8 @@ def main():
                          "JSON line of its own instead of the benchmark line")
     ap.add_argument("--stream-probe", action="store_true",
                     help="achievable HBM / MALL / L2 read bandwidth of the device; prints one JSON line of its own")
+    ap.add_argument("--weighted", action="store_true",
+                    help="weighted-graph study: the workload with synthetic transition weights (one JSON line)")
     ap.add_argument("--c4", action="store_true",
                     help="learned-start evaluation on five fresh 1M-vertex web-like graphs; prints one JSON line "
                          "of its own instead of the benchmark line")
@@ -422,6 +477,9 @@ def main():
         return
     if args.c4:
         run_c4(args, pr, torch)
+        return
+    if args.weighted:
+        run_weighted(args, pr, torch)
         return
     dev_name = torch.cuda.get_device_name(0)
     log("device", dev_name)

@@ -143,6 +143,8 @@ struct Levels {
   uint32_t* vpath = nullptr;      // [n] vertex items: path order of the CAC sweep (see k_item_paths)
   uint32_t* mslot_ptr = nullptr;  // [n+1] first slot of each row (rows of workgroup SCCs own slots)
   uint4* mslot_src = nullptr;     // [slots] up to 8 source ids of a row, local to the SCC, two per word
+  double* mslot_w64 = nullptr;    // [8 * slots] weighted plan: the slots' edge weights
+  float* mslot_w32 = nullptr;
   int64_t n_mslots = 0;
   int64_t n_items = 0;
   int32_t grid = 0;               // workgroups of a segment kernel launch

@@ -265,7 +265,8 @@ Levels::~Levels() {
                 full_ptr, full_src, inv_deg32, inv_deg64, items, gangs, gsccs, gbounds, gpart, gpmx, gpdiff, gnhist,
                 gwsum, gdone, x, R, wprime, y0, y1, iters, lastnorm, counters, red, wgstats, trace,
                 seg_heads, ghubs, gpieces, gpiece_ptr, gpiece_part, ghub_pieces, warm_buf, warm_gws, vpath,
-                mslot_ptr, mslot_src, res_part, res_w, res_d, bnd_w64, int_w64, int_w32, full_w64, full_w32};
+                mslot_ptr, mslot_src, res_part, res_w, res_d, bnd_w64, int_w64, int_w32, full_w64, full_w32,
+                mslot_w64, mslot_w32};
   drop_graphs();
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (hipEvent_t e : kev) (void)hipEventDestroy(e);

@@ -292,10 +292,12 @@ __global__ __launch_bounds__(64) void k_item_early(const Item* items, int64_t n_
 // Slots of the rows of workgroup SCCs: each row's in-edges inside its SCC
 // cut into groups of up to eight, each group stored as eight 16-bit source
 // ids local to the SCC (two per word; the SCC's size pads a short group).
-// One 16-byte load gives a thread a whole slot.
+// One 16-byte load gives a thread a whole slot.  A weighted plan also gets
+// the eight edge weights of every slot (zero for the pad), in FP64 and FP32.
 __global__ __launch_bounds__(256) void k_medium_slots(const Item* items, int64_t n_items, const int32_t* comp_vbeg,
                                                       const uint32_t* int_ptr, const int32_t* int_src,
-                                                      const uint32_t* mslot_ptr, uint4* mslot_src) {
+                                                      const uint32_t* mslot_ptr, uint4* mslot_src,
+                                                      const double* int_w, double* mslot_w64, float* mslot_w32) {
   for (int64_t q = blockIdx.x; q < n_items; q += gridDim.x) {
     const Item it = items[q];
     if (it.kind != ITEM_MEDIUM) continue;
@@ -313,6 +315,13 @@ __global__ __launch_bounds__(256) void k_medium_slots(const Item* items, int64_t
           w[m] = a0 | (a1 << 16);
         }
         mslot_src[sl] = make_uint4(w[0], w[1], w[2], w[3]);
+        if (int_w) {
+          for (int m = 0; m < 8; ++m) {
+            const double wt = e + m < e1 ? int_w[e + m] : 0.0;
+            mslot_w64[8 * (size_t)sl + m] = wt;
+            mslot_w32[8 * (size_t)sl + m] = (float)wt;
+          }
+        }
       }
     }
   }
@@ -384,11 +393,13 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   // device copies
   void* old[] = {lv.items, lv.gangs, lv.gsccs, lv.gbounds, lv.gpart, lv.gpmx, lv.gwsum, lv.gdone, lv.wgstats, lv.gpdiff, lv.gnhist,
                  lv.trace, lv.seg_heads, lv.ghubs, lv.gpieces, lv.gpiece_ptr, lv.gpiece_part, lv.ghub_pieces,
-                 lv.warm_buf, lv.warm_gws, lv.mslot_ptr, lv.mslot_src};
+                 lv.warm_buf, lv.warm_gws, lv.mslot_ptr, lv.mslot_src, lv.mslot_w64, lv.mslot_w32};
   for (void* q : old)
     if (q) (void)hipFree(q);
   lv.mslot_ptr = nullptr;
   lv.mslot_src = nullptr;
+  lv.mslot_w64 = nullptr;
+  lv.mslot_w32 = nullptr;
   lv.warm_buf = nullptr;  // sized by the schedule: allocated again on first use
   lv.warm_gws = nullptr;
   lv.items = nullptr;
@@ -448,9 +459,14 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
     lv.n_mslots = (int64_t)run;
     PR_TRY(upload(&lv.mslot_ptr, msp));
     PR_TRY(dalloc(&lv.mslot_src, std::max<size_t>(run, 1)));
+    if (lv.weighted) {
+      PR_TRY(dalloc(&lv.mslot_w64, 8 * std::max<size_t>(run, 1)));
+      PR_TRY(dalloc(&lv.mslot_w32, 8 * std::max<size_t>(run, 1)));
+    }
     if (run > 0) {
       k_medium_slots<<<(unsigned)std::min<size_t>(items.size(), 4096), 256, 0, s>>>(
-          lv.items, (int64_t)items.size(), lv.comp_vbeg, lv.int_ptr, lv.int_src, lv.mslot_ptr, lv.mslot_src);
+          lv.items, (int64_t)items.size(), lv.comp_vbeg, lv.int_ptr, lv.int_src, lv.mslot_ptr, lv.mslot_src,
+          lv.weighted ? lv.int_w64 : nullptr, lv.mslot_w64, lv.mslot_w32);
       PR_HIP_CHECK(hipGetLastError());
     }
   }
@@ -616,6 +632,8 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
   p.signed_w = signed_w ? 1 : 0;
   p.mslot_ptr = lv.mslot_ptr;
   p.mslot_src = lv.mslot_src;
+  p.mslot_w64 = lv.mslot_w64;
+  p.mslot_w32 = lv.mslot_w32;
   p.inv32 = lv.inv_deg32;
   p.inv64 = lv.inv_deg64;
   p.x = lv.x;

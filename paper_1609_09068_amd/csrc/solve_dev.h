@@ -83,6 +83,8 @@ struct SolveParams {
   const uint32_t* vpath;
   const uint32_t* mslot_ptr;
   const uint4* mslot_src;
+  const double* mslot_w64;  // weighted plan: eight edge weights per slot
+  const float* mslot_w32;
   const int32_t* comp_vbeg;
   int32_t* iters;
   double* lastnorm;
@@ -928,12 +930,19 @@ __device__ inline const YT* term_w(const SolveParams& p) {
   else return reinterpret_cast<const YT*>(p.int_w32);
 }
 
+// the slots' edge weights (eight per slot) in the type of the series terms
+template <typename YT>
+__device__ inline const YT* slot_w(const SolveParams& p) {
+  if constexpr (sizeof(YT) == 8) return reinterpret_cast<const YT*>(p.mslot_w64);
+  else return reinterpret_cast<const YT*>(p.mslot_w32);
+}
+
 // An SCC with at most 256 vertices, iterated by one wavefront.  After the
 // weights are gathered, the component's internal rows are copied into LDS
 // (one-byte local source ids, two-byte row offsets) when they fit, so every
 // term touches only LDS and registers (R stays in registers, four rows per
-// lane).  A weighted graph (WT) reads its rows and weights from the plan
-// every term instead.
+// lane).  A weighted graph (WT) keeps a lane's first sixteen edge weights in
+// registers on the one-row-per-lane path and reads the others from the plan.
 template <typename YT, bool WARM, bool TAIL = false, bool WT = false>
 __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, int rank, YT* ybuf, unsigned long long* wst, WaveTile* tile) {
   const int lane = threadIdx.x & 63;
@@ -966,7 +975,9 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
   // stage the internal rows in LDS (the tile is free after the gathers)
   const uint32_t eb = p.int_ptr[vbeg];
   const uint32_t ne = p.int_ptr[vbeg + nv] - eb;
-  const bool staged = !WT && ne <= (uint32_t)sizeof(tile->buf);
+  const bool staged = ne <= (uint32_t)sizeof(tile->buf);
+  const YT* ewt = nullptr;  // weights by staged edge index (WT)
+  if constexpr (WT) ewt = term_w<YT>(p) + eb;
   uint8_t* lsrc = reinterpret_cast<uint8_t*>(tile->buf);
   uint16_t* lptr = reinterpret_cast<uint16_t*>(tile->racc);  // racc + rlo + rhi: 1 KB >= 2 * 257
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1078,6 +1089,11 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
         pk[q >> 2] = (pk[q >> 2] & ~(0xffu << sh)) | ((uint32_t)lsrc[lo + q] << sh);
       }
     }
+    YT wr[16];  // the packed sources' edge weights (WT)
+    if constexpr (WT) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) wr[q] = (uint32_t)q < deg ? ewt[lo + q] : (YT)0;
+    }
     const int nq = (int)wave_max((double)(deg < 16u ? deg : 16u));  // wave-uniform
     const bool extra = wave_max((double)deg) > 16.0;
     if (lane == 0) {
@@ -1110,6 +1126,10 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
 #pragma unroll
         for (int q = 0; q < 16; ++q) g[q] = ya[(pk[q >> 2] >> (8u * (q & 3))) & 0xffu];
       }
+      if constexpr (WT) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) g[q] *= wr[q];
+      }
       YT sv = (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) +
               (((g[8] + g[9]) + (g[10] + g[11])) + ((g[12] + g[13]) + (g[14] + g[15])));
       if (extra) {
@@ -1120,6 +1140,10 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
           YT h[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) h[j] = ya[ix[j]];
+          if constexpr (WT) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) h[j] *= e + j < hi ? ewt[e + j] : (YT)0;
+          }
           sv += ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));
         }
       }
@@ -1188,7 +1212,10 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
             for (uint32_t e = lo; e < hi; e += 8) {
               YT h[8];
 #pragma unroll
-              for (int j = 0; j < 8; ++j) h[j] = e + j < hi ? ya[lsrc[e + j]] : (YT)0;
+              for (int j = 0; j < 8; ++j) {
+                if constexpr (WT) h[j] = e + j < hi ? ya[lsrc[e + j]] * ewt[e + j] : (YT)0;
+                else h[j] = e + j < hi ? ya[lsrc[e + j]] : (YT)0;
+              }
               s0 += (h[0] + h[1]) + (h[2] + h[3]);
               s1 += (h[4] + h[5]) + (h[6] + h[7]);
             }
@@ -1260,8 +1287,9 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
 // One SCC iterated by one workgroup.  When the component fits, its rows
 // (two-byte local sources), 1/outdeg, R and both term vectors live in LDS
 // during the iteration; otherwise the vectors stay in global memory, touched
-// only by this workgroup.  A weighted graph (WT) takes the last path (rows,
-// weights and terms from global memory).
+// only by this workgroup.  A weighted graph (WT) multiplies every slot entry
+// by its edge weight: from LDS on the register path (the weights staged
+// beside the slot sums), from the plan on the large-component path.
 template <typename YT, int RPW, bool WARM, bool TAIL = false, bool WT = false>
 __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, int rank, double* red, unsigned long long* wst, WaveTile* tiles,
                            unsigned char* raw, size_t raw_bytes) {
@@ -1342,13 +1370,15 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
   const uint32_t sb = p.mslot_ptr[vb];
   const uint32_t nslot = p.mslot_ptr[ve] - sb;
   const size_t need = (2 * ((size_t)nv + 1) + nslot) * sizeof(YT) + 64;
-  const bool staged = !WT && need <= raw_bytes && nv <= kThreads * kRPT && nslot <= (uint32_t)(kThreads * kSPT);
+  const size_t need_w = WT ? 16 + (size_t)kSlot * nslot * sizeof(YT) : 0;  // the slots' weights (WT)
+  const bool staged =
+      need + need_w <= raw_bytes && nv <= kThreads * kRPT && nslot <= (uint32_t)(kThreads * kSPT);
   // (the plan cuts slots only for components of at most 65535 vertices: the
   // ids are 16-bit and the component size is the zero pad)
   // larger components: the same two phases with the slots read from the plan
   // every term (L2-resident) and R, 1/outdeg and the row slot ranges in LDS
   const size_t need_big = (3 * (size_t)nv + 2 + nslot) * sizeof(YT) + 8 * (size_t)nv + 4 * ((size_t)nv + 1) + 64;
-  const bool staged_big = !WT && !staged && need_big <= raw_bytes && nv <= 65535;
+  const bool staged_big = !staged && need_big <= raw_bytes && nv <= 65535;
   if (staged_big) {
     double* lR = reinterpret_cast<double*>(raw);
     YT* l0 = reinterpret_cast<YT*>(lR + nv);
@@ -1369,6 +1399,8 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
     }
     __syncthreads();
     const uint4* gs = p.mslot_src + sb;
+    const YT* gw = nullptr;  // the slots' weights (WT)
+    if constexpr (WT) gw = slot_w<YT>(p) + (size_t)kSlot * sb;
     YT* la = l0;
     YT* lb = l1;
     // certified tail estimate as in the register path below
@@ -1396,6 +1428,10 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
               YT g[kSlot];
 #pragma unroll
               for (uint32_t m = 0; m < kSlot; ++m) g[m] = la[(wv[m / 2] >> (16 * (m & 1))) & 0xffffu];
+              if constexpr (WT) {
+#pragma unroll
+                for (uint32_t m = 0; m < kSlot; ++m) g[m] *= gw[kSlot * (size_t)sl + m];
+              }
               lpart[sl] = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
             }
           }
@@ -1471,6 +1507,12 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
     YT* l0 = reinterpret_cast<YT*>(raw);
     YT* l1 = l0 + nv + 1;
     YT* lpart = l1 + nv + 1;
+    // the slots' weights (WT), 16-byte aligned after the slot sums
+    YT* lw = reinterpret_cast<YT*>(raw + ((reinterpret_cast<unsigned char*>(lpart + nslot) - raw + 15) & ~(size_t)15));
+    if constexpr (WT) {
+      const YT* gw = slot_w<YT>(p) + (size_t)kSlot * sb;
+      for (uint32_t q = threadIdx.x; q < kSlot * nslot; q += kThreads) lw[q] = gw[q];
+    }
     for (int q = threadIdx.x; q < nv; q += kThreads) l0[q] = ya[vb + q];
     if (threadIdx.x == 0) {
       l0[nv] = (YT)0;
@@ -1521,6 +1563,10 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
             YT g[kSlot];
 #pragma unroll
             for (uint32_t m = 0; m < kSlot; ++m) g[m] = la[(sid[j][m / 2] >> (16 * (m & 1))) & 0xffffu];
+            if constexpr (WT) {
+#pragma unroll
+              for (uint32_t m = 0; m < kSlot; ++m) g[m] *= lw[kSlot * sl + m];
+            }
             lpart[sl] = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
           }
         }
@@ -1697,7 +1743,7 @@ static_assert(kWaves * sizeof(WaveTile) + kVertWtOff + 4 * kThreads * sizeof(dou
 // handed out before it, and those are held by running workgroups; the
 // lowest unfinished item has nothing left to wait for.
 template <typename YT, int RPW, bool WARM, bool TAIL = false, bool WT = false>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ? 1 : ((TAIL || RPW < 16) ? 2 : 3)))) void k_segment(SolveParams p) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ? 1 : ((TAIL || WT || RPW < 16) ? 2 : 3)))) void k_segment(SolveParams p) {
   __shared__ double s_red[24];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kSegLds];
   __shared__ unsigned long long s_stats[kWgStats];
