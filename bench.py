@@ -165,7 +165,7 @@ def summarize_pmc(fetch_dir, write_dir, calib_mb, out, method, shape=None):
         factor = calib_mb * 1024.0 / float(np.median(copy))
         calib[counter] = {"copy_mib": calib_mb, "counter_kib_median": float(np.median(copy)), "factor": factor}
         for fam in FAMILIES:
-            vals = [v for k, v in rows if (fam + "<") in k or k.endswith(fam) or (fam + "(") in k]
+            vals = [v for k, v in rows if (fam + "<") in k or (fam + "_w3<") in k or k.endswith(fam) or (fam + "(") in k]
             if fam == "k_gang":
                 vals = [v for k, v in rows if "k_gang<" in k]
             if vals:
@@ -435,6 +435,8 @@ def main():
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--small-cutoff", type=int, default=0)
     ap.add_argument("--team-edges", type=int, default=0)
+    ap.add_argument("--seg-waves", type=int, default=0, choices=[0, 2, 3],
+                    help="workgroups per CU of the tail-estimate segment kernel (0: default or autotuned)")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1, 2],
                     help="plan autotuner: 0 off, 1 cached or sweep, 2 sweep")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -456,7 +458,7 @@ def main():
         shape = None
         if args.rows_per_wave and args.small_cutoff and args.team_edges:
             shape = {"rows_per_wave": args.rows_per_wave, "small_cutoff": args.small_cutoff,
-                     "team_edges": args.team_edges}
+                     "team_edges": args.team_edges, "seg_waves": args.seg_waves or 2}
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.calib_copy_mb or 1024,
                       args.summarize_pmc[2], args.only or "componentwise", shape)
         return
@@ -498,7 +500,9 @@ def main():
         bopts["small_cutoff"] = args.small_cutoff
     if args.team_edges:
         bopts["team_edges"] = args.team_edges
-    if args.autotune and not (args.rows_per_wave or args.small_cutoff or args.team_edges):
+    if args.seg_waves:
+        bopts["seg_waves"] = args.seg_waves
+    if args.autotune and not (args.rows_per_wave or args.small_cutoff or args.team_edges or args.seg_waves):
         bopts["autotune"] = args.autotune
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -608,7 +612,7 @@ def main():
     mpl = mean_stats(st_epl)
     value = s["edge_iters"] / (ms_cw * 1e-3) / 1e9
     dom = int(np.argmax(mcw["kt_ms"])) if any(mcw["kt_ms"]) else 0
-    shape = {k: info[k] for k in ("rows_per_wave", "small_cutoff", "team_edges")}
+    shape = {k: info[k] for k in ("rows_per_wave", "small_cutoff", "team_edges", "seg_waves")}
     traffic_cw = load_traffic(args.traffic, FAMILIES[dom] + "/componentwise", shape)
     roof = roofline(dom, info, mcw, args.precision, False, traffic_cw)
     roof_spmv = roofline(1, info, mpl, args.precision, True, load_traffic(args.traffic, "k_gang/plain", shape))
@@ -697,7 +701,7 @@ def main():
                    "m_between": info["m_between"], "m_cac_internal": info["m_cac_internal"],
                    "gang_vertices": info["v_gang"], "rows_per_wave": info["rows_per_wave"],
                    "small_cutoff": info["small_cutoff"], "team_edges": info["team_edges"],
-                   "grid_wgs": info["grid_wgs"], "hipgraph": bool(args.graph),
+                   "grid_wgs": info["grid_wgs"], "seg_waves": info["seg_waves"], "hipgraph": bool(args.graph),
                    "tail_estimate": bool(args.tail_estimate),
                    "autotuned": bool(bopts.get("autotune", 0))},
         "time_to_1e-6_ms": times,

@@ -119,7 +119,15 @@ typedef struct pr_build_opts {
      4.3.1).  0 (default) = ignore them, as in the paper's experiments.  The
      partition does not depend on loops. */
   int32_t keep_loops;
-  int32_t reserved[6];
+  /* workgroups per CU of the segment kernel with the tail estimate (FP32 or
+     FP64 terms, no starting guess, unweighted, 16 or 64 rows per
+     wavefront): 2 (more registers, no spills; best where a segment's chain
+     of dependencies sets its time) or 3 (best where many SCC items are in
+     flight at once).  0 (default) = 2, or the autotuner's choice when
+     autotune is on (it times both on the chosen shape).  Other variants are
+     unaffected. */
+  int32_t seg_waves;
+  int32_t reserved[5];
 } pr_build_opts;
 
 void pr_default_build_opts(pr_build_opts* o);
@@ -183,6 +191,8 @@ typedef struct pr_levels_info {
   int64_t n_phases;         /* segment and gang phases of the componentwise solve */
   int64_t n_hubs;           /* rows summed in pieces (more than 2048 in-edges), all gangs */
   int32_t rows_per_wave, small_cutoff, team_edges, grid_wgs;
+  int32_t seg_waves;        /* the tail-estimate segment kernel's workgroups per CU (2 or 3) */
+  int32_t reserved_i32;
 } pr_levels_info;
 
 int32_t pr_levels_get_info(const pr_levels_t* lv, pr_levels_info* info);

@@ -32,7 +32,7 @@ PR_PREC_AUTO = 2
 class BuildOpts(C.Structure):
     _fields_ = [("small_cutoff", C.c_int32), ("team_edges", C.c_int32), ("rows_per_wave", C.c_int32),
                 ("build_plain", C.c_int32), ("autotune", C.c_int32), ("keep_loops", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("seg_waves", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class SolveOpts(C.Structure):
@@ -65,7 +65,8 @@ class LevelsInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n", "m", "n_comp", "n_levels", "n_scc", "n_cac", "n_singleton", "v_scc", "v_cac",
         "v_singleton", "m_scc_internal", "m_cac_internal", "m_between", "n_items", "n_gangs",
-        "n_gang_scc", "v_gang", "m_gang_internal", "m_gang_between", "n_phases", "n_hubs")] + [(k, C.c_int32) for k in ("rows_per_wave", "small_cutoff", "team_edges", "grid_wgs")]
+        "n_gang_scc", "v_gang", "m_gang_internal", "m_gang_between", "n_phases", "n_hubs")] + [(k, C.c_int32) for k in ("rows_per_wave", "small_cutoff", "team_edges", "grid_wgs", "seg_waves",
+                                                      "reserved_i32")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -55,7 +55,7 @@ extern "C" {
 
 const char* pr_last_error(void) { return g_last_error.c_str(); }
 
-const char* pr_version(void) { return "componentwise-pagerank-mi355x 0.1 (gfx950)"; }
+const char* pr_version(void) { return "componentwise-pagerank-mi355x 0.2 (gfx950)"; }
 
 void pr_free(void* handle) {
   if (!handle) return;
@@ -189,6 +189,10 @@ static int32_t build_plan(const pr_partition_t* ph, int64_t n, const int64_t* ro
   }
   if (o.small_cutoff > 256) {
     set_error("small_cutoff = %d exceeds 256", o.small_cutoff);
+    return PR_EINVAL;
+  }
+  if (o.seg_waves != 0 && o.seg_waves != 2 && o.seg_waves != 3) {
+    set_error("seg_waves = %d, expected 0, 2 or 3", o.seg_waves);
     return PR_EINVAL;
   }
   if (o.autotune < 0 || o.autotune > 2) {

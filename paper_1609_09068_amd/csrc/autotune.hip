@@ -4,10 +4,12 @@
 // by a gang of every workgroup (team_edges).  Each candidate schedule is
 // timed with real solves of this plan on the device (W = 1, c = 0.85,
 // certificate 1e-6, mixed precision; the plain method too when the plan
-// keeps it) and the fastest is kept.  Results are cached per graph, device
-// and library version: in memory for the process and, when the environment
+// keeps it) and the fastest is kept.  On that shape, unless the caller fixed
+// it, the tail-estimate segment kernel is then timed at two and at three
+// workgroups per CU (seg_waves).  Results are cached per graph, device and
+// library version: in memory for the process and, when the environment
 // variable PR_AUTOTUNE_CACHE names a file, in that file (one line per entry:
-// key, rows_per_wave, small_cutoff, team_edges).
+// key, rows_per_wave, small_cutoff, team_edges, seg_waves).
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -20,7 +22,7 @@ namespace prlib {
 namespace {
 
 struct Choice {
-  int32_t rpw, small, team;
+  int32_t rpw, small, team, waves;
 };
 
 std::mutex g_tune_mu;
@@ -39,12 +41,14 @@ bool file_lookup(uint64_t key, Choice* c) {
   if (!path || !*path) return false;
   FILE* f = fopen(path, "r");
   if (!f) return false;
-  unsigned long long k;
-  int a, b, d;
+  char line[256];
   bool found = false;
-  while (fscanf(f, "%llx %d %d %d", &k, &a, &b, &d) == 4) {
-    if (k == key && (a == 1 || a == 4 || a == 16 || a == 64) && b >= 1 && b <= 256 && d >= 1) {
-      *c = Choice{a, b, d};
+  while (fgets(line, sizeof(line), f)) {
+    unsigned long long k;
+    int a, b, d, w = 2;
+    if (sscanf(line, "%llx %d %d %d %d", &k, &a, &b, &d, &w) < 4) continue;
+    if (k == key && (a == 1 || a == 4 || a == 16 || a == 64) && b >= 1 && b <= 256 && d >= 1 && (w == 2 || w == 3)) {
+      *c = Choice{a, b, d, w};
       found = true;  // the last entry for a key wins
     }
   }
@@ -57,7 +61,7 @@ void file_store(uint64_t key, const Choice& c) {
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%016llx %d %d %d\n", (unsigned long long)key, c.rpw, c.small, c.team);
+  fprintf(f, "%016llx %d %d %d %d\n", (unsigned long long)key, c.rpw, c.small, c.team, c.waves);
   fclose(f);
 }
 
@@ -77,7 +81,9 @@ int32_t autotune_levels(Levels& lv, hipStream_t s) {
   for (const char* q = pr_version(); *q; ++q) key = mix(key, (uint64_t)(unsigned char)*q);
   key = mix(key, lv.full_ptr ? 1u : 0u);
   key = mix(key, lv.opts.keep_loops ? 2u : 0u);
-  Choice best{lv.opts.rows_per_wave, lv.opts.small_cutoff, lv.opts.team_edges};
+  const int32_t fixed_waves = lv.opts.seg_waves;  // 0: the autotuner's choice
+  key = mix(key, (uint64_t)fixed_waves);
+  Choice best{lv.opts.rows_per_wave, lv.opts.small_cutoff, lv.opts.team_edges, fixed_waves == 3 ? 3 : 2};
   bool have = false;
   if (lv.opts.autotune == 1) {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -104,44 +110,73 @@ int32_t autotune_levels(Levels& lv, hipStream_t s) {
     pr_default_solve_opts(&o);
     o.eps = 1e-6;
     o.precision = PR_PREC_MIXED;
-    double best_ms = 1e300;
     int32_t rc = PR_OK;
-    // every shape is timed as the median of three solves per method after one
-    // untimed solve; a shape later in this order replaces the best only when
-    // it is more than 1.5% faster, so shapes within the timing noise of each
-    // other do not flip from one sweep to the next
-    for (int rpw : {64, 16, 4, 1}) {
-      for (int small : {16, 64}) {
-        for (int team : {16384, 65536}) {
-          lv.opts.rows_per_wave = rpw;
-          lv.opts.small_cutoff = small;
-          lv.opts.team_edges = team;
-          rc = make_schedule(lv, s);
-          if (rc) break;
-          double ms = 0.0;
-          for (int method : {PR_METHOD_COMPONENTWISE, PR_METHOD_PLAIN}) {
-            if (method == PR_METHOD_PLAIN && !lv.full_ptr) continue;
-            o.method = method;
-            pr_solve_stats st;
-            double t[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int rep = 0; rep < 4 && !rc; ++rep) {
-              rc = solve_levels(lv, 0.85, W, R, o, s, &st);
-              if (rc > 0) rc = PR_OK;  // not converged within max_iter: still a valid timing
-              t[rep] = st.kernel_ms;
-            }
-            if (rc) break;
-            std::sort(t + 1, t + 4);
-            ms += t[2];
-          }
-          if (rc) break;
-          if (ms < best_ms * (best_ms < 1e299 ? 0.985 : 1.0)) {
-            best_ms = ms;
-            best = Choice{rpw, small, team};
-          }
-        }
-        if (rc) break;
+    // median of three timed solves after one untimed one (kernel time)
+    auto timed = [&](int method, int tail, double* out) -> int32_t {
+      o.method = method;
+      o.tail_estimate = tail;
+      pr_solve_stats st;
+      double t[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int rep = 0; rep < 4; ++rep) {
+        int32_t r = solve_levels(lv, 0.85, W, R, o, s, &st);
+        if (r < 0) return r;  // (not converged within max_iter is still a valid timing)
+        t[rep] = st.kernel_ms;
       }
+      std::sort(t + 1, t + 4);
+      *out = t[2];
+      return PR_OK;
+    };
+    auto schedule = [&](int rpw, int small, int team) {
+      lv.opts.rows_per_wave = rpw;
+      lv.opts.small_cutoff = small;
+      lv.opts.team_edges = team;
+      return make_schedule(lv, s);
+    };
+    // Three stages, each judged by the time its knob affects; a candidate
+    // later in its stage replaces the best only when it is more than 1.5%
+    // faster, so candidates within the timing noise of each other do not
+    // flip from one sweep to the next.
+    //  1. rows per wavefront (the gathers of both methods): the componentwise
+    //     solve with the tail estimate plus, when the plan keeps it, the plain
+    //     series, at small cutoff 64 and team edges 16384;
+    //  2. small cutoff x team edges: the componentwise solve alone;
+    //  3. (below) the tail-estimate segment kernel's workgroups per CU.
+    double best_ms = 1e300;
+    for (int rpw : {64, 16, 4, 1}) {
+      if ((rc = schedule(rpw, 64, 16384))) break;
+      double a = 0.0, b = 0.0;
+      if ((rc = timed(PR_METHOD_COMPONENTWISE, 1, &a))) break;
+      if (lv.full_ptr && (rc = timed(PR_METHOD_PLAIN, 0, &b))) break;
+      if (a + b < best_ms * (best_ms < 1e299 ? 0.985 : 1.0)) {
+        best_ms = a + b;
+        best = Choice{rpw, 64, 16384, best.waves};
+      }
+    }
+    best_ms = 1e300;
+    for (int small : {64, 16}) {
       if (rc) break;
+      for (int team : {16384, 65536}) {
+        if ((rc = schedule(best.rpw, small, team))) break;
+        double a = 0.0;
+        if ((rc = timed(PR_METHOD_COMPONENTWISE, 1, &a))) break;
+        if (a < best_ms * (best_ms < 1e299 ? 0.985 : 1.0)) {
+          best_ms = a;
+          best.small = small;
+          best.team = team;
+        }
+      }
+    }
+    //  3. workgroups per CU of the tail-estimate segment kernel, on the
+    //     chosen shape: three only when more than 1.5% faster than two
+    if (!rc && fixed_waves == 0 && !lv.weighted && (best.rpw == 16 || best.rpw == 64)) {
+      rc = schedule(best.rpw, best.small, best.team);
+      double tw[2] = {0.0, 0.0};
+      for (int v = 0; v < 2 && !rc; ++v) {
+        lv.opts.seg_waves = v == 0 ? 2 : 3;
+        rc = timed(PR_METHOD_COMPONENTWISE, 1, &tw[v]);
+      }
+      lv.opts.seg_waves = fixed_waves;
+      if (!rc) best.waves = tw[1] < 0.985 * tw[0] ? 3 : 2;
     }
     (void)hipFree(W);
     (void)hipFree(R);
@@ -153,6 +188,7 @@ int32_t autotune_levels(Levels& lv, hipStream_t s) {
   lv.opts.rows_per_wave = best.rpw;
   lv.opts.small_cutoff = best.small;
   lv.opts.team_edges = best.team;
+  lv.opts.seg_waves = best.waves;
   return make_schedule(lv, s);
 }
 

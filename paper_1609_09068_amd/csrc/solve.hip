@@ -519,6 +519,7 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   I.small_cutoff = lv.opts.small_cutoff;
   I.team_edges = lv.opts.team_edges;
   I.grid_wgs = lv.sgrid;
+  I.seg_waves = lv.opts.seg_waves == 3 ? 3 : 2;
   // a new schedule invalidates a captured graph
   lv.drop_graphs();
   // the uploads above read host vectors that end with this function
@@ -721,7 +722,11 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
   double sumW = 0.0;
   for (int i = 0; i < kRedBlocks; ++i) sumW += wparts[2 * i];
   const int64_t kb = term_bound(o, c, sumW);
-  const SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave, p.mlp != nullptr, p.tail != 0, lv.weighted);
+  SegFn seg = pick_segment(o.precision, lv.opts.rows_per_wave, p.mlp != nullptr, p.tail != 0, lv.weighted);
+  if (p.tail && !p.mlp && !lv.weighted && lv.opts.seg_waves == 3) {
+    const void* f3 = seg_kernel_tail_w3(lv.opts.rows_per_wave, o.precision == PR_PREC_FP64);
+    if (f3) seg = reinterpret_cast<SegFn>(const_cast<void*>(f3));
+  }
   // the variants with the starting guess, the tail estimate or edge weights
   // need more registers: size their grid to what stays resident
   unsigned seg_grid = (unsigned)lv.grid;
@@ -841,6 +846,7 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
     key = mix64(key, (uint64_t)(o.stop * 16 + o.precision * 4 + o.method));
     key = mix64(key, (uint64_t)o.small_direct);
     key = mix64(key, (uint64_t)o.tail_estimate);
+    key = mix64(key, (uint64_t)(uintptr_t)seg);  // the segment kernel variant (seg_waves)
     key = mix64(key, (uint64_t)(uintptr_t)p.mlp);
     key = mix64(key, (uint64_t)(uintptr_t)p.gmlp);
     key = mix64(key, (uint64_t)(signed_w ? 2 : 0) + (residual ? 1 : 0));

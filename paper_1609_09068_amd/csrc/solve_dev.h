@@ -1728,7 +1728,7 @@ __device__ inline void flush_stats(const SolveParams& p, unsigned long long* s_s
 // are gathered, and a vertex item keeps its local x values in the second part.
 static_assert(kDirectMax * (kDirectMax + 1) * sizeof(double) <= 512 * sizeof(double) + 64 * (sizeof(double) + 8),
               "direct-solve matrix fits the tile");
-constexpr size_t kSegLds = 53 * 1024;  // three workgroups per CU (the VGPR limit too)
+constexpr size_t kSegLds = 52 * 1024;  // three workgroups per CU (the VGPR limit too)
 static_assert(kWaves * sizeof(WaveTile) + kWaves * 2 * kSmallMax * sizeof(double) <= kSegLds, "segment LDS");
 static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + kThreads * sizeof(uint4) +
                       (3 * kThreads + 1 + kWaves) * sizeof(int32_t) <=
@@ -1742,8 +1742,8 @@ static_assert(kWaves * sizeof(WaveTile) + kVertWtOff + 4 * kThreads * sizeof(dou
 // whatever the number of resident workgroups: an item only waits for items
 // handed out before it, and those are held by running workgroups; the
 // lowest unfinished item has nothing left to wait for.
-template <typename YT, int RPW, bool WARM, bool TAIL = false, bool WT = false>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ? 1 : ((TAIL || WT || RPW < 16) ? 2 : 3)))) void k_segment(SolveParams p) {
+template <typename YT, int RPW, bool WARM, bool TAIL, bool WT>
+__device__ __attribute__((always_inline)) void segment_body(const SolveParams& p) {
   __shared__ double s_red[24];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kSegLds];
   __shared__ unsigned long long s_stats[kWgStats];
@@ -1801,6 +1801,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ?
   }
   if (threadIdx.x == 0) s_stats[S_T_SEGMENT] += wall_clock64() - t_k;
   flush_stats(p, s_stats);
+}
+
+// The segment kernel: the variants with the starting guess, the tail
+// estimate, edge weights or fewer than 16 rows per wavefront need more
+// registers and run two workgroups per CU; the others three.  k_segment_w3
+// runs the tail-estimate variant at three workgroups per CU (168 registers,
+// a few spills): faster where a segment is bound by throughput (many SCC
+// items in flight), slower where it is bound by its chain of dependencies;
+// the autotuner picks (pr_build_opts.seg_waves).
+template <typename YT, int RPW, bool WARM, bool TAIL = false, bool WT = false>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ? 1 : ((TAIL || WT || RPW < 16) ? 2 : 3)))) void k_segment(SolveParams p) {
+  segment_body<YT, RPW, WARM, TAIL, WT>(p);
+}
+template <typename YT, int RPW>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_segment_w3(SolveParams p) {
+  segment_body<YT, RPW, false, true, false>(p);
 }
 
 // ------------------------------------------------------------- gang phases
@@ -2436,5 +2452,8 @@ const void* seg_kernel_f64(int rpw, bool warm);
 const void* seg_kernel_f64_tail(int rpw, bool warm);
 const void* seg_kernel_w32(int rpw, bool tail);
 const void* seg_kernel_w64(int rpw, bool tail);
+// the tail-estimate variant at three workgroups per CU (rows per wavefront
+// 16 or 64; null otherwise)
+const void* seg_kernel_tail_w3(int rpw, bool fp64);
 
 }  // namespace prlib

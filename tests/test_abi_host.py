@@ -179,3 +179,14 @@ def test_weighted_build_rejects_bad_weights_before_device_work():
         assert f"weight[{g.m // 2}]".encode() in lib.pr_last_error()
     with pytest.raises(ValueError):
         pr.pr_build_levels(p, g.row_ptr, g.col, weight=np.ones(g.m - 1))
+
+
+def test_build_rejects_bad_seg_waves_before_device_work():
+    lib = _lib.load()
+    g = random_digraph(300, 1200, 13)
+    p = pr.pr_partition(g.row_ptr, g.col)
+    for bad in (1, 4, -2):
+        o = pr.build_opts(seg_waves=bad)
+        out = C.c_void_p()
+        rc = lib.pr_build_levels(p.handle, g.n, _i64(g.row_ptr), _i32(g.col), C.byref(o), None, C.byref(out))
+        assert rc == _lib.PR_EINVAL and b"seg_waves" in lib.pr_last_error()

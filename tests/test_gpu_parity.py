@@ -317,13 +317,14 @@ def test_autotuner_sweeps_caches_and_stays_exact(prm, c1, tmp_path, monkeypatch)
     info = lv.info()
     assert info["rows_per_wave"] in (1, 4, 16, 64)
     assert info["small_cutoff"] in (16, 64) and info["team_edges"] in (16384, 65536)
+    assert info["seg_waves"] in (2, 3)
     lines = cache.read_text().split()
-    assert len(lines) == 4 and int(lines[1]) == info["rows_per_wave"]
+    assert len(lines) == 5 and int(lines[1]) == info["rows_per_wave"] and int(lines[4]) == info["seg_waves"]
     # cached: the same choice without a sweep (the file is not appended to)
     lv2 = pr.pr_build_levels(part, g.row_ptr, g.col, autotune=1)
-    assert {k: lv2.info()[k] for k in ("rows_per_wave", "small_cutoff", "team_edges")} == \
-        {k: info[k] for k in ("rows_per_wave", "small_cutoff", "team_edges")}
-    assert len(cache.read_text().split()) == 4
+    keys = ("rows_per_wave", "small_cutoff", "team_edges", "seg_waves")
+    assert {k: lv2.info()[k] for k in keys} == {k: info[k] for k in keys}
+    assert len(cache.read_text().split()) == 5
     Wd = torch.tensor(W, device="cuda")
     Rd = torch.empty_like(Wd)
     pr.pr_solve(lv2, C, Wd, Rd, eps=1e-10, precision=1)
@@ -380,3 +381,32 @@ def test_random_dag_cacs(prm, seed):
     Rd2 = torch.empty_like(Wd)
     pr.pr_solve(lv, C, Wd, Rd2, precision=1)
     assert np.array_equal(Rd.cpu().numpy(), Rd2.cpu().numpy())
+
+
+@pytest.mark.parametrize("rpw", [16, 64])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_three_workgroups_per_cu_variant_is_bitwise_equal(prm, c1, rpw, prec):
+    """The tail-estimate segment kernel at three workgroups per CU
+    (seg_waves = 3) does the same arithmetic in the same order as at two: the
+    result is bitwise equal, eager and replayed, and the plan reports the
+    variant it runs."""
+    pr, torch = prm
+    g, W, ref = c1
+    part = pr.pr_partition(g.row_ptr, g.col)
+    Wd = torch.tensor(W, device="cuda")
+    out = {}
+    for waves in (2, 3):
+        lv = pr.pr_build_levels(part, g.row_ptr, g.col, rows_per_wave=rpw, small_cutoff=64, seg_waves=waves)
+        assert lv.info()["seg_waves"] == waves
+        for graph in (0, 1, 1):
+            _say("seg_waves", waves, "rpw", rpw, "prec", prec, "graph", graph)
+            Rd = torch.empty_like(Wd)
+            rc, st = pr.pr_solve(lv, C, Wd, Rd, eps=1e-6 if prec == 0 else 1e-10, precision=prec,
+                                 tail_estimate=1, use_graph=graph)
+            torch.cuda.synchronize()
+            assert rc == 0
+            out.setdefault(waves, []).append(Rd.cpu().numpy())
+        lv.free()
+    for r in out[2] + out[3]:
+        assert np.array_equal(r, out[2][0])
+    assert _rel_l1(out[3][0], ref) <= (1e-6 if prec == 0 else 1e-10)
