@@ -257,3 +257,45 @@ def test_weighted_graph_replay_and_warm_start_refused(prm):
     assert ei.value.code == pr._lib.PR_EINVAL
     net.free()
     lv.free()
+
+
+def _tiny(n, edges):
+    return csr_from_edges(n, [a for a, _ in edges], [b for _, b in edges], drop_loops=False)
+
+
+@pytest.mark.parametrize("case", ["single", "isolated", "zero_chain", "cycle_zero_edge", "fig1_real", "loop_single"])
+def test_weighted_edge_cases(prm, case):
+    """Degenerate weighted inputs against the dense weighted solve (FP64):
+    no edges at all; a chain whose weights are all zero (A = 0, so R = W); a
+    5-cycle with one zero-weight edge (still one SCC in the partition, a
+    chain in A); the worked example with real weights; a single vertex with a
+    weighted self-loop kept (R = W / (1 - c))."""
+    loops = case == "loop_single"
+    if case == "single":
+        g, w = _tiny(1, []), np.zeros(0)
+    elif case == "isolated":
+        g, w = _tiny(4, []), np.zeros(0)
+    elif case == "zero_chain":
+        g = _tiny(6, [(i, i + 1) for i in range(5)])
+        w = np.zeros(g.m)
+    elif case == "cycle_zero_edge":
+        g = _tiny(5, [(i, (i + 1) % 5) for i in range(5)])
+        w = np.array([0.0 if g.col[e] == 0 else 1.5 for e in range(g.m)])
+    elif case == "fig1_real":
+        g = _tiny(8, [(0, 1), (0, 2), (1, 3), (2, 4), (2, 5), (1, 5), (4, 5), (6, 7), (3, 1), (7, 6), (1, 6)])
+        w = np.linspace(0.25, 2.5, g.m)
+    else:
+        g, w = _tiny(1, [(0, 0)]), np.array([2.0])
+    W = np.linspace(0.5, 1.5, g.n)
+    ref = pagerank_dense_weighted(g.n, g.row_ptr, g.col, w, C, W, loops=loops)
+    for method in (0, 1):
+        _say("weighted edge case", case, "method", method)
+        R, rc, st, lv, _ = _solve_w(prm, g, w, W, dict(keep_loops=int(loops)), eps=1e-13, precision=1,
+                                    method=method)
+        assert rc == 0
+        np.testing.assert_allclose(R, ref, rtol=1e-12, atol=0)
+        lv.free()
+    if case == "zero_chain":
+        np.testing.assert_array_equal(R, W)
+    if case == "loop_single":  # R of the last solve (the plain series, truncated at eps 1e-13)
+        np.testing.assert_allclose(R, W / (1 - C), rtol=1e-12)
