@@ -230,16 +230,16 @@ static void add_gang(const std::vector<uint32_t>& ptr, int G, int vb, int ve, co
 // paths: a vertex continues the path of its deepest in-item predecessor that
 // no other vertex continues yet (the first such in edge order), else it starts
 // a path.  vpath lists the item's vertices path after path, each path in
-// order (local index in bits 0-7, bit 8 set where a path starts), so that one
+// order (local index in bits 0-9, kVStart where a path starts), so that one
 // lane can walk a whole path with the running value in a register.
 // k_item_early then sets bit 16 of vpath[u] for every vertex u with a CAC
 // edge into a later vertex item: those publish x the moment they are final,
 // the others when their item ends.
 __global__ __launch_bounds__(64) void k_item_paths(Item* items, int64_t n_items, const uint32_t* int_ptr,
                                                     const int32_t* int_src, uint32_t* vpath) {
-  __shared__ int32_t depth[kThreads];
-  __shared__ int16_t succ[kThreads];
-  __shared__ uint8_t head[kThreads];
+  __shared__ int32_t depth[kVertMax];
+  __shared__ int16_t succ[kVertMax];
+  __shared__ uint8_t head[kVertMax];
   for (int64_t q = blockIdx.x; q < n_items; q += gridDim.x) {
     const Item it = items[q];
     if (it.kind != ITEM_VERTS) continue;
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(64) void k_item_paths(Item* items, int64_t n_items,
       int pos = 0;
       for (int h = 0; h < nv; ++h) {
         if (!head[h]) continue;
-        for (int i = h; i >= 0; i = succ[i]) vpath[it.a + pos++] = (uint32_t)(i | (i == h ? 0x100 : 0));
+        for (int i = h; i >= 0; i = succ[i]) vpath[it.a + pos++] = (uint32_t)i | (i == h ? kVStart : 0u);
       }
     }
     __syncthreads();
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(64) void k_item_early(const Item* items, int64_t n_
     for (int v = it.a + (int)threadIdx.x; v < it.b; v += 64)
       for (uint32_t e = int_ptr[v]; e < int_ptr[v + 1]; ++e) {
         const int u = int_src[e];
-        if (u < it.a) atomicOr(&vpath[u], 0x10000u);
+        if (u < it.a) atomicOr(&vpath[u], kVEarly);
       }
   }
 }
@@ -358,7 +358,8 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
     }
     if (sc < e) {
       const int32_t v0 = lv.h_comp_vbeg[sc], v1 = lv.h_comp_vbeg[e];
-      for (int32_t v = v0; v < v1; v += kThreads) items.push_back(Item{ITEM_VERTS, v, std::min(v1, v + kThreads), 0});
+      const int32_t vstep = lv.weighted ? kVertMaxW : kVertMax;
+      for (int32_t v = v0; v < v1; v += vstep) items.push_back(Item{ITEM_VERTS, v, std::min(v1, v + vstep), 0});
     }
     if (!large.empty()) {
       if ((int64_t)items.size() > seg_start) phases.push_back(Phase{0, (int32_t)seg_start, (int32_t)items.size()});

@@ -448,6 +448,13 @@ __device__ __attribute__((always_inline)) VT wave_tile_gather(const SolveParams&
 // multiplied by its edge weight; the four listed sources keep their weights
 // beside them in LDS.
 constexpr int kWalkBatches = 2;
+// Vertex items hold up to kVertMax positions, one per thread (kVertMaxW on
+// a weighted plan).
+constexpr int kVertMax = kThreads;
+constexpr int kVertMaxW = kThreads;
+// plan path order (vpath): local index in bits 0-9, bit 10 starts a path,
+// bit 16 marks a vertex with a CAC edge into a later item
+constexpr uint32_t kVIdx = 0x3ffu, kVStart = 0x400u, kVEarly = 0x10000u;
 // byte offset of the listed sources' weights in a vertex item's LDS (after
 // x, R, acc, c / outdeg, the source lists and the path tables)
 constexpr size_t kVertWtOff =
@@ -480,13 +487,21 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
   auto st_lx = [&](int k, double val) {
     __hip_atomic_store(sX + k, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
-  // path order: position i holds vertex pw & 255; bit 8 starts a path
+  // path bounds: -1 until written after the barrier below; no barrier
+  // follows those writes, so the walk reads its bounds with a wait on the mark
+  auto ld_pb = [&](int k) { return __hip_atomic_load(sPB + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+  auto st_pb = [&](int k, int32_t val) {
+    __hip_atomic_store(sPB + k, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  // path order: position i holds vertex pw & kVIdx; kVStart starts a path
   const uint32_t pw = act ? p.vpath[v] : 0u;
-  const bool pstart = act && (pw & 0x100u);
-  const bool early = pw & 0x10000u;  // v has a CAC edge into a later item
-  if (act) sQ[pw & 0xffu] = i | (pstart ? 0x10000 : 0);
+  const bool pstart = act && (pw & kVStart);
+  const bool early = pw & kVEarly;  // v has a CAC edge into a later item
+  if (act) sQ[pw & kVIdx] = i | (pstart ? 0x10000 : 0);
   sX[i] = kXPending;  // the LDS still holds the previous item's values
   sI[i] = 0u;    // bit 15 marks a position whose entries are written
+  st_pb(i, -1);
+  if (i == 0) st_pb(kThreads, -1);
   const unsigned long long sm = __ballot(pstart);
   if (lane == 0) sWc[wave] = (int32_t)__popcll(sm);
   __syncthreads();
@@ -497,8 +512,8 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
       if (w < wave) pid += sWc[w];
       npath += sWc[w];
     }
-    if (pstart) sPB[pid] = i;
-    if (i == 0) sPB[npath] = nvi;  // visible after the barrier below
+    if (pstart) st_pb(pid, i);
+    if (i == 0) st_pb(npath, nvi);
   }
   double acc = 0.0;
   if (nr > 0) acc = wave_tile_gather<64, double, true, WT>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile, p.bnd_w);
@@ -659,8 +674,10 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) tot += sWc[w];
     if (i < tot) {
-      q = sPB[i];
-      qe = sPB[i + 1];
+      // written by other wavefronts right after the barrier: almost never
+      // still -1 here
+      while ((q = ld_pb(i)) < 0) __builtin_amdgcn_s_sleep(1);
+      while ((qe = ld_pb(i + 1)) < 0) __builtin_amdgcn_s_sleep(1);
     }
   }
   double xprev = 0.0;
