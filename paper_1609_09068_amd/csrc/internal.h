@@ -181,7 +181,7 @@ struct Levels {
   std::vector<int64_t> h_comp_int_edges;     // [K] by rank
   std::vector<int32_t> h_comp_id_of_rank;    // [K]
   // per-solve work areas
-  double* x = nullptr;            // [n] c R_v / outdeg(v), -1 = not ready
+  double* x = nullptr;            // [n] c R_v / outdeg(v), a quiet NaN until final
   double* R = nullptr;            // [n] rank in plan order (teams)
   double* wprime = nullptr;       // [n] W' in plan order (debug / features)
   void* y0 = nullptr;             // [n] series terms (float or double), ping

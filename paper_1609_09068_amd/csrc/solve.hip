@@ -25,9 +25,10 @@
 //             the stop, in a fixed order.  Rows with very many in-edges are
 //             summed in pieces and combined by a small launch per term.
 //
-// Dependencies inside a segment are data driven: x starts at -1 ("not
-// ready") and every x_u is written once, with an agent-scope store, after
-// R_u is final; readers poll with agent-scope loads.  Items are popped in
+// Dependencies inside a segment are data driven: x starts as a quiet NaN
+// ("not ready"; a correction solve's x can have either sign) and every x_u
+// is written once, with an agent-scope store, after R_u is final; readers
+// poll with agent-scope loads.  Items are popped in
 // plan order, so every item an item waits for went to a running workgroup.
 //
 // Precision: series terms y_k = c P_k / outdeg and their row sums are FP32
