@@ -191,7 +191,9 @@ typedef struct pr_levels_info {
   int64_t n_phases;         /* segment and gang phases of the componentwise solve */
   int64_t n_hubs;           /* rows summed in pieces (more than 2048 in-edges), all gangs */
   int32_t rows_per_wave, small_cutoff, team_edges, grid_wgs;
-  int32_t seg_waves;        /* the tail-estimate segment kernel's workgroups per CU (2 or 3) */
+  int32_t seg_waves;        /* workgroups per CU of the tail-estimate segment kernel this plan runs
+                               (2 or 3; 3 only when asked for and the plan is unweighted at 16 or 64
+                               rows per wavefront) */
   int32_t reserved_i32;
 } pr_levels_info;
 

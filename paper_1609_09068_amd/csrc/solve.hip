@@ -521,7 +521,10 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   I.small_cutoff = lv.opts.small_cutoff;
   I.team_edges = lv.opts.team_edges;
   I.grid_wgs = lv.sgrid;
-  I.seg_waves = lv.opts.seg_waves == 3 ? 3 : 2;
+  // the three-workgroup tail kernel exists for unweighted plans at 16 or 64
+  // rows per wavefront; every other plan runs the two-workgroup one
+  const bool w3 = lv.opts.seg_waves == 3 && !lv.weighted && (lv.opts.rows_per_wave == 16 || lv.opts.rows_per_wave == 64);
+  I.seg_waves = w3 ? 3 : 2;
   // a new schedule invalidates a captured graph
   lv.drop_graphs();
   // the uploads above read host vectors that end with this function

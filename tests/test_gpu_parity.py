@@ -410,3 +410,20 @@ def test_three_workgroups_per_cu_variant_is_bitwise_equal(prm, c1, rpw, prec):
     for r in out[2] + out[3]:
         assert np.array_equal(r, out[2][0])
     assert _rel_l1(out[3][0], ref) <= (1e-6 if prec == 0 else 1e-10)
+
+
+def test_seg_waves_reports_the_kernel_that_runs(prm, c1):
+    """Asked for three workgroups per CU where that variant does not exist
+    (4 rows per wavefront, or a weighted plan) the plan reports two."""
+    pr, torch = prm
+    g, W, ref = c1
+    part = pr.pr_partition(g.row_ptr, g.col)
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col, rows_per_wave=4, seg_waves=3)
+    assert lv.info()["seg_waves"] == 2
+    lv.free()
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col, weight=np.ones(g.m), rows_per_wave=64, seg_waves=3)
+    assert lv.info()["seg_waves"] == 2
+    lv.free()
+    lv = pr.pr_build_levels(part, g.row_ptr, g.col, rows_per_wave=64, seg_waves=3)
+    assert lv.info()["seg_waves"] == 3
+    lv.free()
