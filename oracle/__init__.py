@@ -17,4 +17,6 @@ componentwise the level-by-level solve of Sec. 4.3 (eq. PR:levels, the CAC
               sweep of Sec. 4.3.1, the power series per SCC).
 warmstart     per-vertex features and the 4-64-64-1 GELU network used for the
               learned starting guess (forward, backward, Adam) in float64.
+gauss_seidel  block Gauss-Seidel sweeps inside one SCC (the alternative to
+              the series that Sec. 4.3.2 names), with its residual certificate.
 """
