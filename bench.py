@@ -557,6 +557,7 @@ def main():
         legs += [("componentwise_guess", 0, dict(tail, warm_start=net)),
                  ("componentwise_guess_plain_stop", 0, dict(warm_start=net))]
     legs += [("componentwise_plain_stop", 0, {}),
+             ("componentwise_gauss_seidel4", 0, dict(gs_blocks=4)),
              ("componentwise_small_direct", 0, dict(small_direct=24)),
              ("plain", 1, dict(tail)),
              ("plain_plain_stop", 1, {})]

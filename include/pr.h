@@ -259,7 +259,16 @@ typedef struct pr_solve_opts {
                            PR_METHOD_PLAIN) for the worst-case term bound instead of the terms
                            earlier solves of this plan needed plus a margin: the launch cost of a
                            first solve.  Results do not depend on it.  Default 0. */
-  int32_t reserved[1];
+  int32_t gs_blocks;    /* 0 (default) = every SCC by the power series.  1..8 = the SCCs that one
+                           workgroup iterates with their rows and slots in registers (above
+                           small_cutoff, at most 1024 rows and 1024 slots, below team_edges) take
+                           block Gauss-Seidel sweeps instead, the alternative Sec. 4.3.2 names:
+                           the component's rows in plan order cut into gs_blocks blocks, each
+                           block updated from the newest values of the blocks before it; the
+                           component stops once ||R_new - R_old||_1 <= eps (1 - c) ||W'_C||_1
+                           (the certificate adds c ||dR||_1 / (1 - c)).  One block is the Jacobi
+                           iteration (the series, iterated on R).  Not with tail_estimate,
+                           warm_start or a weighted plan (PR_EINVAL). */
 } pr_solve_opts;
 
 void pr_default_solve_opts(pr_solve_opts* o);

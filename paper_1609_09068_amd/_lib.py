@@ -41,7 +41,7 @@ class SolveOpts(C.Structure):
                 ("max_iter", C.c_int64), ("warm_start", C.c_void_p), ("trace", C.c_int32),
                 ("kernel_timing", C.c_int32), ("warm_scope", C.c_int32), ("small_direct", C.c_int32),
                 ("tail_estimate", C.c_int32), ("refine", C.c_int32), ("cold", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("gs_blocks", C.c_int32)]
 
 
 class SolveStats(C.Structure):

@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libpr.so")
 ARCH = os.environ.get("PR_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["abi.cpp", "partition.cpp", "devsort.hip", "plan.hip", "solve.hip", "seg_f32.hip", "seg_f32_tail.hip",
-           "seg_f64.hip", "seg_f64_tail.hip", "seg_w32.hip", "seg_w64.hip", "seg_tail_w3.hip", "mlp.hip", "autotune.hip", "probe.hip"]
+           "seg_f64.hip", "seg_f64_tail.hip", "seg_w32.hip", "seg_w64.hip", "seg_tail_w3.hip", "seg_gs.hip", "mlp.hip", "autotune.hip", "probe.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -308,6 +308,14 @@ int32_t pr_solve(pr_levels_t* lh, double c, const void* W_dev, void* R_dev, cons
     set_error("refine = %d, expected -1 (no residual pass), 0 (default) or 1..16 rounds", o.refine);
     return PR_EINVAL;
   }
+  if (o.gs_blocks < 0 || o.gs_blocks > 8) {
+    set_error("gs_blocks = %d, expected 0..8", o.gs_blocks);
+    return PR_EINVAL;
+  }
+  if (o.gs_blocks > 0 && (o.tail_estimate || o.warm_start || lv->weighted)) {
+    set_error("gs_blocks > 0 does not combine with tail_estimate, warm_start or a weighted plan");
+    return PR_EINVAL;
+  }
   if (o.small_direct < 0 || o.small_direct > 24) {
     set_error("small_direct = %d, expected 0..24", o.small_direct);
     return PR_EINVAL;

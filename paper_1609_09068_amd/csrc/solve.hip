@@ -636,6 +636,7 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
   p.direct_max = plain ? 0 : o.small_direct;
   p.tail = (o.tail_estimate && o.stop == PR_STOP_CERT_L1) ? 1 : 0;
   p.signed_w = signed_w ? 1 : 0;
+  p.gs_blocks = plain ? 0 : o.gs_blocks;
   p.mslot_ptr = lv.mslot_ptr;
   p.mslot_src = lv.mslot_src;
   p.mslot_w64 = lv.mslot_w64;
@@ -732,10 +733,12 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
     const void* f3 = seg_kernel_tail_w3(lv.opts.rows_per_wave, o.precision == PR_PREC_FP64);
     if (f3) seg = reinterpret_cast<SegFn>(const_cast<void*>(f3));
   }
+  if (p.gs_blocks > 0)
+    seg = reinterpret_cast<SegFn>(const_cast<void*>(seg_kernel_gs(lv.opts.rows_per_wave, o.precision == PR_PREC_FP64)));
   // the variants with the starting guess, the tail estimate or edge weights
   // need more registers: size their grid to what stays resident
   unsigned seg_grid = (unsigned)lv.grid;
-  if (p.mlp || p.tail || lv.weighted) {
+  if (p.mlp || p.tail || lv.weighted || p.gs_blocks) {
     int occ = 0, cus = 0;
     PR_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)seg, kThreads, 0));
     PR_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, lv.device));
@@ -852,6 +855,8 @@ static int32_t solve_once(Levels& lv, double c, const double* W, double* R, cons
     key = mix64(key, (uint64_t)o.small_direct);
     key = mix64(key, (uint64_t)o.tail_estimate);
     key = mix64(key, (uint64_t)(uintptr_t)seg);  // the segment kernel variant (seg_waves)
+    key = mix64(key, (uint64_t)o.gs_blocks);
+    key = mix64(key, (uint64_t)(o.trace == 1));
     key = mix64(key, (uint64_t)(uintptr_t)p.mlp);
     key = mix64(key, (uint64_t)(uintptr_t)p.gmlp);
     key = mix64(key, (uint64_t)(signed_w ? 2 : 0) + (residual ? 1 : 0));

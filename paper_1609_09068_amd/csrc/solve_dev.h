@@ -18,6 +18,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kSmallMax = 256;  // rows of a wavefront-resident SCC
+constexpr int kGsMaxBlocks = 8;  // most Gauss-Seidel row blocks per sweep
 constexpr int kDirectMax = 24;  // largest SCC solved directly: 24 x 25 doubles fit a wavefront's tile
 
 // per-workgroup counters (LDS during a kernel, accumulated in global memory
@@ -39,6 +40,7 @@ struct SolveParams {
   int32_t direct_max;  // SCCs of a wavefront with at most this many vertices are solved directly
   int32_t tail;        // segment SCC series may stop on the certified geometric tail estimate
   int32_t signed_w;    // weights may be negative (the residual that a correction solve takes)
+  int32_t gs_blocks;   // > 0: workgroup SCCs on the register path take block Gauss-Seidel sweeps
   double c, eps, tol;
   int64_t max_iter;
   const double* W;
@@ -1307,7 +1309,7 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
 // only by this workgroup.  A weighted graph (WT) multiplies every slot entry
 // by its edge weight: from LDS on the register path (the weights staged
 // beside the slot sums), from the plan on the large-component path.
-template <typename YT, int RPW, bool WARM, bool TAIL = false, bool WT = false>
+template <typename YT, int RPW, bool WARM, bool TAIL = false, bool WT = false, bool GS = false>
 __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, int rank, double* red, unsigned long long* wst, WaveTile* tiles,
                            unsigned char* raw, size_t raw_bytes) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1388,8 +1390,10 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
   const uint32_t nslot = p.mslot_ptr[ve] - sb;
   const size_t need = (2 * ((size_t)nv + 1) + nslot) * sizeof(YT) + 64;
   const size_t need_w = WT ? 16 + (size_t)kSlot * nslot * sizeof(YT) : 0;  // the slots' weights (WT)
+  // the Gauss-Seidel blocks' first slots follow the slot sums (GS)
+  const size_t need_gs = GS ? sizeof(uint32_t) * (kGsMaxBlocks + 1) + 16 : 0;
   const bool staged =
-      need + need_w <= raw_bytes && nv <= kThreads * kRPT && nslot <= (uint32_t)(kThreads * kSPT);
+      need + need_w + need_gs <= raw_bytes && nv <= kThreads * kRPT && nslot <= (uint32_t)(kThreads * kSPT);
   // (the plan cuts slots only for components of at most 65535 vertices: the
   // ids are 16-bit and the component size is the zero pad)
   // larger components: the same two phases with the slots read from the plan
@@ -1566,7 +1570,96 @@ __device__ __attribute__((always_inline)) void run_medium(const SolveParams& p, 
     // c P_k / outdeg (a relative difference of one FP32 rounding)
     const bool tail = TAIL && p.tail;
     double nprev = last, nprev2 = -1.0;
-    if (!skip) {
+    if constexpr (GS) {
+      // Block Gauss-Seidel sweeps (the alternative to the series that Sec.
+      // 4.3.2 names): the component's rows, in plan order, cut into
+      // gs_blocks consecutive blocks; la holds c R / outdeg of the newest R
+      // (R starts at W').  A block's rows take W' plus their slot sums,
+      // formed from la once the earlier blocks of the sweep have written
+      // theirs.  The component stops after the first sweep with
+      // ||R_new - R_old||_1 <= eps (1 - c) ||W'||_1 (the paper's rule: max
+      // |R_new - R_old| < tol); then ||R - R*||_1 <= c ||dR||_1 / (1 - c),
+      // the bound the certificate adds for it.
+      uint32_t* lqb = reinterpret_cast<uint32_t*>(lpart + nslot);  // the blocks' first slots
+      const int B = p.gs_blocks < nv ? p.gs_blocks : nv;
+      for (int b = threadIdx.x; b <= B; b += kThreads)
+        lqb[b] = p.mslot_ptr[vb + (int)(((int64_t)nv * b) / B)] - sb;
+      double wr[kRPT];  // W' of this thread's rows
+#pragma unroll
+      for (int j = 0; j < kRPT; ++j) wr[j] = Rr[j];
+      __syncthreads();
+      if (!skip) {
+        conv = false;
+        while (k < p.max_iter) {
+          ++k;
+          double dsum = 0.0, dmax = 0.0;
+          for (int b = 0; b < B; ++b) {
+            const int r0 = (int)(((int64_t)nv * b) / B), r1 = (int)(((int64_t)nv * (b + 1)) / B);
+            const uint32_t q0 = lqb[b], q1 = lqb[b + 1];
+            // (A) the block's slot sums
+#pragma unroll
+            for (int j = 0; j < kSPT; ++j) {
+              const uint32_t sl = threadIdx.x + kThreads * j;
+              if (sl >= q0 && sl < q1) {
+                YT g[kSlot];
+#pragma unroll
+                for (uint32_t m = 0; m < kSlot; ++m) g[m] = la[(sid[j][m / 2] >> (16 * (m & 1))) & 0xffffu];
+                lpart[sl] = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
+              }
+            }
+            __syncthreads();
+            // (B) the block's rows
+#pragma unroll
+            for (int j = 0; j < kRPT; ++j) {
+              if (kThreads * j + wave * 64 < nv) {  // wave-uniform
+                const int r = threadIdx.x + kThreads * j;
+                const bool in = r >= r0 && r < r1;
+                const uint32_t f0 = fr[j] & 0xffffu, f1 = fr[j] >> 16;
+                const bool wide = f1 - f0 > kSlot;
+                YT sv = 0;
+                if (in && !wide) {
+                  YT h[kSlot];
+#pragma unroll
+                  for (uint32_t m = 0; m < kSlot; ++m) h[m] = f0 + m < f1 ? lpart[f0 + m] : (YT)0;
+                  sv = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));
+                }
+                unsigned long long m = __ballot(in && wide);
+                while (m) {
+                  const int bl = __ffsll(m) - 1;
+                  m &= m - 1;
+                  const uint32_t blo = __shfl(f0, bl, 64), bhi = __shfl(f1, bl, 64);
+                  YT ws = 0;
+                  for (uint32_t e = blo + lane; e < bhi; e += 256) {
+                    YT g[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) g[q] = e + 64 * q < bhi ? lpart[e + 64 * q] : (YT)0;
+                    ws += (g[0] + g[1]) + (g[2] + g[3]);
+                  }
+                  ws = wave_sum(ws);
+                  if (lane == bl) sv = ws;
+                }
+                if (in) {
+                  const double rn = wr[j] + (double)sv;
+                  const double d = fabs(rn - Rr[j]);
+                  Rr[j] = rn;
+                  la[r] = (YT)(c * rn * (double)ir[j]);
+                  dsum += d;
+                  dmax = fmax(dmax, d);
+                }
+              }
+            }
+            __syncthreads();  // the block's new values before the next block's sums
+          }
+          double norm, mx;
+          block_sum_max(dsum, dmax, red, (int)(k & 1), &norm, &mx);
+          last = norm;
+          if (stop_now(p, norm, mx, thresh)) {
+            conv = true;
+            break;
+          }
+        }
+      }
+    } else if (!skip) {
       conv = false;
       while (k < p.max_iter) {
         ++k;
@@ -1759,7 +1852,7 @@ static_assert(kWaves * sizeof(WaveTile) + kVertWtOff + 4 * kThreads * sizeof(dou
 // whatever the number of resident workgroups: an item only waits for items
 // handed out before it, and those are held by running workgroups; the
 // lowest unfinished item has nothing left to wait for.
-template <typename YT, int RPW, bool WARM, bool TAIL, bool WT>
+template <typename YT, int RPW, bool WARM, bool TAIL, bool WT, bool GS = false>
 __device__ __attribute__((always_inline)) void segment_body(const SolveParams& p) {
   __shared__ double s_red[24];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kSegLds];
@@ -1798,7 +1891,7 @@ __device__ __attribute__((always_inline)) void segment_body(const SolveParams& p
       if (r < it.b) run_small<YT, WARM, TAIL, WT>(p, r, ybuf, s_stats, &tiles[wave]);
       slot = S_T_SMALL;
     } else {
-      run_medium<YT, RPW, WARM, TAIL, WT>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
+      run_medium<YT, RPW, WARM, TAIL, WT, GS>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
       slot = S_T_MEDIUM;
     }
     __syncthreads();
@@ -1834,6 +1927,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WARM ?
 template <typename YT, int RPW>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_segment_w3(SolveParams p) {
   segment_body<YT, RPW, false, true, false>(p);
+}
+// the segment kernel with block Gauss-Seidel sweeps in workgroup SCCs
+// (gs_blocks > 0; no tail estimate, starting guess or edge weights)
+template <typename YT, int RPW>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_segment_gs(SolveParams p) {
+  segment_body<YT, RPW, false, false, false, true>(p);
 }
 
 // ------------------------------------------------------------- gang phases
@@ -2472,5 +2571,7 @@ const void* seg_kernel_w64(int rpw, bool tail);
 // the tail-estimate variant at three workgroups per CU (rows per wavefront
 // 16 or 64; null otherwise)
 const void* seg_kernel_tail_w3(int rpw, bool fp64);
+// the block Gauss-Seidel variant (gs_blocks > 0)
+const void* seg_kernel_gs(int rpw, bool fp64);
 
 }  // namespace prlib
