@@ -30,6 +30,9 @@
 // is written once, with an agent-scope store, after R_u is final; readers
 // poll with agent-scope loads.  Items are popped in
 // plan order, so every item an item waits for went to a running workgroup.
+// Inside a level the order is free (no edges join components of one level):
+// the vertex items come first, then the workgroup and wavefront SCCs, so the
+// pipelines of the large CACs start before the SCC items fill the machine.
 //
 // Precision: series terms y_k = c P_k / outdeg and their row sums are FP32
 // (PR_PREC_MIXED) or FP64; R, W', x, the norms and every sum across rows are
@@ -346,6 +349,12 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
     int64_t sc = r;
     while (sc < e && lv.h_comp_class[sc] == 0) ++sc;
     std::vector<int64_t> small, large;
+    // vertex items first: the CAC pipelines carry the longest chains
+    if (sc < e) {
+      const int32_t v0 = lv.h_comp_vbeg[sc], v1 = lv.h_comp_vbeg[e];
+      const int32_t vstep = lv.weighted ? kVertMaxW : kVertMax;
+      for (int32_t v = v0; v < v1; v += vstep) items.push_back(Item{ITEM_VERTS, v, std::min(v1, v + vstep), 0});
+    }
     for (int64_t q = r; q < sc; ++q) {
       const int32_t nv = lv.h_comp_vbeg[q + 1] - lv.h_comp_vbeg[q];
       if (nv <= lv.opts.small_cutoff) small.push_back(q);
@@ -356,11 +365,6 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
       const int64_t a = small[i];
       const int64_t b = small[std::min(small.size() - 1, i + kWaves - 1)] + 1;
       items.push_back(Item{ITEM_SMALL, (int32_t)a, (int32_t)b, 0});
-    }
-    if (sc < e) {
-      const int32_t v0 = lv.h_comp_vbeg[sc], v1 = lv.h_comp_vbeg[e];
-      const int32_t vstep = lv.weighted ? kVertMaxW : kVertMax;
-      for (int32_t v = v0; v < v1; v += vstep) items.push_back(Item{ITEM_VERTS, v, std::min(v1, v + vstep), 0});
     }
     if (!large.empty()) {
       if ((int64_t)items.size() > seg_start) phases.push_back(Phase{0, (int32_t)seg_start, (int32_t)items.size()});
