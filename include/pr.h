@@ -231,12 +231,17 @@ typedef struct pr_solve_opts {
   int32_t warm_scope;   /* with warm_start: 0 = only the SCCs iterated in gang phases (the large
                            ones, where the guess's two extra passes cost less than the terms it
                            saves), 1 = every SCC */
-  int32_t small_direct; /* SCCs of at most this many vertices (0..24; default 0 = none) that are
-                           iterated by one wavefront are solved directly instead: (I - cA_CC^T)R_C
-                           = W'_C by FP64 Gauss-Jordan elimination in LDS without pivoting (the
-                           matrix is column diagonally dominant), the paper's choice for small
-                           SCCs in the per-component method dispatch of Sec. 4.3.  Such an SCC
-                           counts zero terms; its FP64 residual enters the certificate. */
+  int32_t small_direct; /* SCCs of at most this many vertices (0..80; default 0 = none) are solved
+                           directly instead of iterated: (I - cA_CC^T)R_C = W'_C by FP64
+                           Gauss-Jordan elimination in LDS without pivoting (the matrix is column
+                           diagonally dominant), the paper's choice for small SCCs in the
+                           per-component method dispatch of Sec. 4.3.  The matrix must fit the
+                           LDS of the SCC's item: up to 24 vertices for an SCC run by one
+                           wavefront (at most small_cutoff vertices), up to 80 for one run by a
+                           workgroup; a plan built with small_cutoff <= 24 therefore solves every
+                           SCC of up to small_direct vertices directly.  Either path gives the same
+                           R bit for bit.  Such an SCC counts zero terms; its FP64 residual enters
+                           the certificate. */
   int32_t tail_estimate;/* 1 = with PR_STOP_CERT_L1, every iterated SCC may also stop on a geometric
                            estimate of the rest of its series (Sec. 4.3.2 series, Sec. 4.4 error):
                            after term P_{k+1}, with rho = ||P_k||/||P_{k-1}|| < 1, it takes

@@ -316,8 +316,8 @@ int32_t pr_solve(pr_levels_t* lh, double c, const void* W_dev, void* R_dev, cons
     set_error("gs_blocks > 0 does not combine with tail_estimate, warm_start or a weighted plan");
     return PR_EINVAL;
   }
-  if (o.small_direct < 0 || o.small_direct > 24) {
-    set_error("small_direct = %d, expected 0..24", o.small_direct);
+  if (o.small_direct < 0 || o.small_direct > 80) {
+    set_error("small_direct = %d, expected 0..80", o.small_direct);
     return PR_EINVAL;
   }
   if (o.warm_start && !registry_has(o.warm_start, KIND_MLP)) {

@@ -20,6 +20,7 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kSmallMax = 256;  // rows of a wavefront-resident SCC
 constexpr int kGsMaxBlocks = 8;  // most Gauss-Seidel row blocks per sweep
 constexpr int kDirectMax = 24;  // largest SCC solved directly: 24 x 25 doubles fit a wavefront's tile
+constexpr int kDirectMaxWG = 80;  // largest workgroup SCC solved directly: 80 x 81 doubles fit the segment LDS
 
 // per-workgroup counters (LDS during a kernel, accumulated in global memory
 // across the launches of a solve); the last ones are wall-clock ticks
@@ -1303,6 +1304,84 @@ __device__ __attribute__((always_inline)) void run_small(const SolveParams& p, i
   if (lane == 0) record_scc(p, rank, k, last, conv, ne, (uint64_t)nv, wst, true, ws);
 }
 
+// The direct solve of an SCC run by one workgroup (Sec. 4.3, small SCCs):
+// Gauss-Jordan elimination of [I - c A_CC^T | W'] in FP64 without pivoting
+// (every column of I - c A_CC^T has diagonal 1 and off-diagonal sum at most
+// c < 1, so the pivots stay at least 1 - c), the matrix in the segment LDS.
+// One row per thread builds it, a 16 x 16 grid of threads updates it, one
+// barrier per step.  The arithmetic and its order are those of the
+// wavefront's direct solve, so an SCC gets the same R on either path.  Kept
+// apart from run_medium so that its registers do not add to the iteration's.
+template <bool WT>
+__device__ __attribute__((always_inline)) void run_direct_wg(const SolveParams& p, int rank, double* red, unsigned long long* wst,
+                                                             WaveTile* tiles, unsigned char* raw) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int vb = p.comp_vbeg[rank], ve = p.comp_vbeg[rank + 1];
+  const int nv = ve - vb;
+  const double c = p.c;
+  // W' = W + the boundary mass (eq. PR:levels), 64 rows per wavefront
+  for (int ra = vb + 64 * wave; ra < ve; ra += 64 * kWaves) {
+    const int nr = ve - ra < 64 ? ve - ra : 64;
+    double wp = wave_tile_gather<64, double, true, WT>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tiles + wave, p.bnd_w);
+    if (lane < nr) p.wprime[ra + lane] = wp + p.W[p.perm[ra + lane]];
+  }
+  __syncthreads();  // the gathers are done with the tiles; W' is visible
+  double* M = reinterpret_cast<double*>(raw);
+  const int ld = nv + 1;
+  for (int q = tid; q < nv * ld; q += kThreads) M[q] = 0.0;
+  __syncthreads();
+  const bool own = tid < nv;  // nv <= kDirectMaxWG < kThreads: one row per thread
+  double wpv = 0.0;
+  if (own) {
+    const int v = vb + tid;
+    double* row = M + (size_t)tid * ld;
+    wpv = p.wprime[v];
+    row[tid] = 1.0;
+    row[nv] = wpv;
+    for (uint32_t e = p.int_ptr[v]; e < p.int_ptr[v + 1]; ++e) {
+      const int u = p.int_src[e] - vb;
+      if constexpr (WT) row[u] -= c * p.inv64[vb + u] * p.int_w64[e];
+      else row[u] -= c * p.inv64[vb + u];
+    }
+  }
+  __syncthreads();
+  const int ty = tid >> 4, tx = tid & 15;
+  for (int kk = 0; kk < nv; ++kk) {
+    const double inv_piv = 1.0 / M[kk * ld + kk];
+    for (int i = ty; i < nv; i += 16) {
+      if (i == kk) continue;
+      const double f = M[i * ld + kk] * inv_piv;
+      for (int j = kk + 1 + tx; j <= nv; j += 16) M[i * ld + j] -= f * M[kk * ld + j];
+    }
+    __syncthreads();
+  }
+  const double xr = own ? M[tid * ld + nv] / M[tid * ld + tid] : 0.0;
+  __syncthreads();
+  if (own) M[tid * ld + nv] = xr;
+  __syncthreads();
+  // residual W' - (I - c A_CC^T) R in FP64: ||R - R*||_1 <= ||r||_1 / (1 - c)
+  double rr = 0.0;
+  if (own) {
+    const int v = vb + tid;
+    double acc = wpv - xr;
+    for (uint32_t e = p.int_ptr[v]; e < p.int_ptr[v + 1]; ++e) {
+      const int u = p.int_src[e] - vb;
+      if constexpr (WT) acc += c * p.inv64[vb + u] * p.int_w64[e] * M[u * ld + nv];
+      else acc += c * p.inv64[vb + u] * M[u * ld + nv];
+    }
+    rr = fabs(acc);
+    p.R[v] = xr;
+    p.Rout[p.perm[v]] = xr;
+    st_x(p.x, v, c * xr * p.inv64[v]);
+  }
+  rr = block_sum(rr, red);
+  if (tid == 0) {
+    const uint32_t ne = p.int_ptr[ve] - p.int_ptr[vb];
+    record_scc(p, rank, 0, rr / c, true, ne, (uint64_t)nv, wst, false);  // the certificate adds rr / (1 - c)
+  }
+}
+
 // One SCC iterated by one workgroup.  When the component fits, its rows
 // (two-byte local sources), 1/outdeg, R and both term vectors live in LDS
 // during the iteration; otherwise the vectors stay in global memory, touched
@@ -1839,6 +1918,8 @@ __device__ inline void flush_stats(const SolveParams& p, unsigned long long* s_s
 static_assert(kDirectMax * (kDirectMax + 1) * sizeof(double) <= 512 * sizeof(double) + 64 * (sizeof(double) + 8),
               "direct-solve matrix fits the tile");
 constexpr size_t kSegLds = 52 * 1024;  // three workgroups per CU (the VGPR limit too)
+static_assert(kDirectMaxWG * (kDirectMaxWG + 1) * sizeof(double) <= kSegLds && kDirectMaxWG < kThreads,
+              "workgroup direct-solve matrix fits the segment LDS");
 static_assert(kWaves * sizeof(WaveTile) + kWaves * 2 * kSmallMax * sizeof(double) <= kSegLds, "segment LDS");
 static_assert(kWaves * sizeof(WaveTile) + 4 * kThreads * sizeof(double) + kThreads * sizeof(uint4) +
                       (3 * kThreads + 1 + kWaves) * sizeof(int32_t) <=
@@ -1891,7 +1972,9 @@ __device__ __attribute__((always_inline)) void segment_body(const SolveParams& p
       if (r < it.b) run_small<YT, WARM, TAIL, WT>(p, r, ybuf, s_stats, &tiles[wave]);
       slot = S_T_SMALL;
     } else {
-      run_medium<YT, RPW, WARM, TAIL, WT, GS>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
+      const int nvm = p.comp_vbeg[it.a + 1] - p.comp_vbeg[it.a];
+      if (nvm <= p.direct_max && nvm <= kDirectMaxWG) run_direct_wg<WT>(p, it.a, s_red, s_stats, tiles, s_raw);
+      else run_medium<YT, RPW, WARM, TAIL, WT, GS>(p, it.a, s_red, s_stats, tiles, s_raw, kSegLds);
       slot = S_T_MEDIUM;
     }
     __syncthreads();

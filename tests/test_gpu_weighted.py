@@ -164,14 +164,15 @@ def test_real_weights_fp64_match_the_definition(prm, small, team, seed):
 @pytest.mark.parametrize("rpw", [1, 4, 16, 64])
 def test_real_weights_all_row_widths_and_direct_solve(prm, rpw):
     """Every rows_per_wave, with and without the direct solve of small SCCs
-    (the weighted matrix I - c A_CC^T in LDS)."""
+    (the weighted matrix I - c A_CC^T in LDS), on wavefront SCCs and, with
+    wavefront SCCs up to 16 vertices, on workgroup SCCs."""
     g = scc_blocks(33, nblocks=60, max_size=40)
     w = _real_weights(g.m, 3)
     W = np.random.default_rng(4).uniform(0.5, 1.5, g.n)
     ref = _ref_weighted(g, w, W)
-    for direct in (0, 24):
-        _say("real weights rpw", rpw, "direct", direct)
-        R, rc, st, lv, _ = _solve_w(prm, g, w, W, dict(rows_per_wave=rpw, small_cutoff=64), eps=1e-13, precision=1,
+    for direct, small in ((0, 64), (24, 64), (40, 16)):
+        _say("real weights rpw", rpw, "direct", direct, "small", small)
+        R, rc, st, lv, _ = _solve_w(prm, g, w, W, dict(rows_per_wave=rpw, small_cutoff=small), eps=1e-13, precision=1,
                                     small_direct=direct)
         assert rc == 0
         np.testing.assert_allclose(R, ref, rtol=1e-10, atol=0)
