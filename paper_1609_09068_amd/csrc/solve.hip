@@ -339,7 +339,6 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   std::vector<Item> items;
   GangTables T;
   std::vector<Phase> phases;
-  std::vector<std::pair<int, int>> gang_ranges;
   int64_t seg_start = 0;
   int64_t r = 0;
   while (r < K) {
@@ -370,7 +369,6 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
       if ((int64_t)items.size() > seg_start) phases.push_back(Phase{0, (int32_t)seg_start, (int32_t)items.size()});
       seg_start = (int64_t)items.size();
       const int vb = lv.h_comp_vbeg[large.front()], ve = lv.h_comp_vbeg[large.back() + 1];
-      gang_ranges.push_back({vb, ve});
       phases.push_back(Phase{1, (int32_t)T.gangs.size(), 0});
       add_gang(lv.h_int_ptr, G, vb, ve, large, lv.h_comp_vbeg, T);
     }
@@ -511,12 +509,16 @@ int32_t make_schedule(Levels& lv, hipStream_t s) {
   I.n_gangs = lv.n_gangs;
   I.n_gang_scc = n_gscc_cw;
   I.v_gang = I.m_gang_internal = I.m_gang_between = 0;
-  for (const auto& gr : gang_ranges) {
+  // the gang SCCs' own rows: a level's gang range can also span smaller
+  // SCCs sorted between them (more vertices, fewer internal edges), which
+  // their items iterate and the gang skips
+  for (const int32_t q : lv.h_gang_rank) {
+    const int32_t a = lv.h_comp_vbeg[q], z = lv.h_comp_vbeg[q + 1];
     uint32_t b[2];
-    PR_HIP_CHECK(hipMemcpy(&b[0], lv.bnd_ptr + gr.first, sizeof(uint32_t), hipMemcpyDeviceToHost));
-    PR_HIP_CHECK(hipMemcpy(&b[1], lv.bnd_ptr + gr.second, sizeof(uint32_t), hipMemcpyDeviceToHost));
-    I.v_gang += gr.second - gr.first;
-    I.m_gang_internal += lv.h_int_ptr[gr.second] - lv.h_int_ptr[gr.first];
+    PR_HIP_CHECK(hipMemcpy(&b[0], lv.bnd_ptr + a, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    PR_HIP_CHECK(hipMemcpy(&b[1], lv.bnd_ptr + z, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    I.v_gang += z - a;
+    I.m_gang_internal += lv.h_int_ptr[z] - lv.h_int_ptr[a];
     I.m_gang_between += b[1] - b[0];
   }
   I.n_phases = (int64_t)phases.size();
