@@ -518,12 +518,14 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
     if (pstart) st_pb(pid, i);
     if (i == 0) st_pb(npath, nvi);
   }
-  double acc = 0.0;
-  if (nr > 0) acc = wave_tile_gather<64, double, true, WT>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile, p.bnd_w);
-  if (act) {
-    acc += p.W[p.perm[v]];
-    p.wprime[v] = acc;
-  }
+  // Everything that does not need other items' x is loaded before the
+  // boundary gather waits for them: W, the CAC row and its source ids.
+  // After the wait only the sums remain (one round trip for the x of
+  // earlier items), so an item on the chain of dependencies starts its walk
+  // soon after its last source is published.
+  const int orig = act ? p.perm[v] : 0;
+  const double wv = act ? p.W[orig] : 0.0;
+  const double cinv = act ? p.c * p.inv64[v] : 0.0;
   const uint32_t lo = act ? p.int_ptr[v] : 0u;
   const uint32_t hi = act ? p.int_ptr[v + 1] : 0u;
   const bool lng = (hi - lo) > kLongLane;
@@ -567,6 +569,15 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
         }
       }
     }
+  }
+  // the rank from higher levels: W' = W + the boundary gather (eq. PR:levels)
+  double acc = 0.0;
+  if (nr > 0) acc = wave_tile_gather<64, double, true, WT>(p, p.bnd_ptr, p.bnd_src, p.x, ra, nr, tile, p.bnd_w);
+  if (act) {
+    acc += wv;
+    p.wprime[v] = acc;
+  }
+  if (act && !lng) {
     if (ns <= 4u) {
       // sources of earlier items that are already published are added now
       // and dropped from the list.  The walk adds a vertex's sources of
@@ -646,7 +657,6 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
     part = wave_sum(part);
     if (lane == b) acc += part;
   }
-  const int orig = act ? p.perm[v] : 0;
   if (act) {
     // hop kind: 0 no CAC source, 1 the path predecessor is the only one, 2 up
     // to four listed sources, 3 many (the walk reads the row)
@@ -655,7 +665,7 @@ __device__ __attribute__((always_inline)) void run_verts(const SolveParams& p, i
         (lng || ns > 4u) ? 3u : ns == 0u ? 0u : (ns == 1u && !(s0 & kExt) && !(qw & 0x10000)) ? 1u : 2u;
     const int q = qw & 0xffff;
     sA[q] = acc;
-    sC[q] = p.c * p.inv64[v];
+    sC[q] = cinv;
     sS[q] = make_uint4(s0, s1, s2, s3);
     if constexpr (WT) {
       sWt[4 * q] = g0;
